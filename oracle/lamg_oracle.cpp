@@ -1,0 +1,1140 @@
+// LAMG CPU oracle -- TEST INFRASTRUCTURE ONLY.
+//
+// A plain, serial, slow implementation of what the Lean Algebraic Multigrid
+// solve path computes (Livne & Brandt, "Lean Algebraic Multigrid (LAMG): Fast
+// Graph Laplacian Linear Solver").  Only the test-suite, the smoke check and
+// the benchmark's CPU-baseline leg may load this library.  It shares no code,
+// header or table with the HIP library; the only things both sides agree on
+// are written down twice, each from its definition:
+//   * the splitmix64 finaliser (Steele, Lea & Flood 2014) used as a
+//     counter-based hash for colouring priorities and test-vector draws;
+//   * the fixed row-reduction order used for every row sum (sequential in
+//     column order for rows of at most 64 terms; otherwise 64 strided partial
+//     sums folded by an xor butterfly with offsets 32..1);
+//   * the level node order (colour-major, then previous id).
+// Build: g++ -O2 -ffp-contract=off -fno-fast-math -shared -fPIC.
+// Parity status of every function is stated beside it (pinned / unpinned).
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <functional>
+#include <numeric>
+#include <vector>
+
+using std::vector;
+typedef int64_t i64;
+typedef int32_t i32;
+
+namespace {
+
+// ---------------------------------------------------------------- hashing
+// splitmix64 finaliser applied to x + golden gamma (Steele, Lea, Flood 2014).
+inline uint64_t sm64(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+// Chained counter hash h(seed, stream, a, b, c).
+inline uint64_t hash5(uint64_t seed, uint64_t stream, uint64_t a, uint64_t b, uint64_t c) {
+  uint64_t h = sm64(seed);
+  h = sm64(h ^ stream);
+  h = sm64(h ^ a);
+  h = sm64(h ^ b);
+  h = sm64(h ^ c);
+  return h;
+}
+const uint64_t STREAM_COLOUR = 7, STREAM_TV = 3;
+// U[-1,1): top 53 bits scaled by 2^-52, minus 1 (exact in binary64).
+inline double unit_pm1(uint64_t h) { return (double)(h >> 11) * (1.0 / 4503599627370496.0) - 1.0; }
+
+// ------------------------------------------------- fixed row-reduction order
+template <class T, class F>
+T row_reduce(i64 len, F term) {
+  if (len <= 64) {
+    T s = 0;
+    for (i64 t = 0; t < len; ++t) s += term(t);
+    return s;
+  }
+  T p[64];
+  for (int j = 0; j < 64; ++j) {
+    T s = 0;
+    for (i64 t = j; t < len; t += 64) s += term(t);
+    p[j] = s;
+  }
+  for (int off = 32; off >= 1; off >>= 1) {
+    T q[64];
+    for (int j = 0; j < 64; ++j) q[j] = p[j] + p[j ^ off];
+    std::memcpy(p, q, sizeof(p));
+  }
+  return p[0];
+}
+
+// ------------------------------------------------------------- structures
+// Graph Laplacian (Section 1, eq. lap): off-diagonal weights w_uv > 0 stored
+// as positive values (a_uv = -w_uv), diagonal a_uu = sum_v w_uv.
+struct Csr {
+  i64 n = 0;
+  vector<i64> ptr;
+  vector<i32> col;
+  vector<double> val, diag;
+  i64 nnz() const { return (i64)col.size(); }
+  i64 deg(i64 u) const { return ptr[u + 1] - ptr[u]; }
+};
+
+enum { L_FINEST = 0, L_ELIM = 1, L_AGG = 2 };
+enum { ST_UNDECIDED = 0, ST_SEED = 1, ST_ASSOC = 2, ST_DUMMY = 3 };
+
+struct Opts {  // mirrors the library options, defaults from Section 4
+  double gamma = 1.5;
+  int nu_pre = 1, nu_post = 2;
+  int tv_k_min = 4, tv_k_max = 10, tv_sweeps = 3;
+  double q_max = 2.5, mu = 4.0 / 3.0, hub_factor = 8.0;
+  int elim_max_degree = 4, coarsest_max_n = 150;
+  double weak_edge_ratio = 1e-3, elim_stop_frac = 0.05;
+  int ec = 0;  // 0 = iterate recombination, 1 = flat mu
+  double tol = 1e-8;
+  int max_cycles = 100;
+  uint64_t seed = 0;
+  int max_levels = 60;
+  double stage1_quantile = 1.0;  // stage-1 affinity threshold: this quantile of best candidate affinities
+};
+
+struct AggDiag {  // aggregation-level setup quantities, kept for parity tests
+  int K = 0;
+  vector<double> tv;        // n x K, after relaxation
+  vector<double> aff;       // per directed edge c_us
+  vector<uint8_t> ok;       // per directed edge: admissible (energy test)
+  vector<uint8_t> weak;     // per directed edge
+  vector<uint8_t> hub;      // per node
+  vector<i32> state;        // final per-node state before numbering
+  double delta1 = 1, alpha1 = 0, alpha2 = -1;
+  int stage = 1;
+};
+
+struct Level {
+  Csr A;
+  vector<float> val32, diag32;
+  int ncol = 1;
+  vector<i64> cptr;   // colour class boundaries in this level's node order
+  vector<i32> perm;   // node order: perm[new] = natural id
+  int type = L_FINEST;
+  // transfer from the previous (finer) level to this one
+  vector<i32> agg;    // AGG: fine node -> coarse node
+  vector<i32> cidx;   // ELIM: fine node -> coarse node, -1 for F nodes
+  double gamma_next = 1.0;  // cycle index for visits from this level to the next
+  AggDiag diag;
+  i64 nF = 0;
+};
+
+struct Hier {
+  Opts o;
+  vector<Level> lv;
+  vector<i32> perm1;        // level-1 order: perm1[new] = input id
+  vector<double> chol;      // dense Cholesky factor of the coarsest system (row-major lower)
+  i64 nL = 0;
+  double removed_mean = 0;
+};
+
+// ---------------------------------------------------------------- Laplacian
+// COO -> Laplacian (Section 1, eq. lap; Section 5.1 preprocessing: duplicate
+// entries of an undirected pair are summed in input order).
+int build_laplacian(i64 n, i64 m, const i32* eu, const i32* ev, const double* w, Csr& A) {
+  if (n < 1 || m < 0) return 1;
+  for (i64 e = 0; e < m; ++e) {
+    if (eu[e] < 0 || eu[e] >= n || ev[e] < 0 || ev[e] >= n || eu[e] == ev[e]) return 1;
+    if (!std::isfinite(w[e]) || !(w[e] > 0)) return 2;
+  }
+  vector<i64> idx(m);
+  std::iota(idx.begin(), idx.end(), 0);
+  auto key = [&](i64 e) {
+    i64 a = std::min(eu[e], ev[e]), b = std::max(eu[e], ev[e]);
+    return a * n + b;
+  };
+  std::stable_sort(idx.begin(), idx.end(), [&](i64 x, i64 y) { return key(x) < key(y); });
+  vector<i64> ua, ub;
+  vector<double> uw;
+  for (i64 i = 0; i < m;) {
+    i64 k = key(idx[i]);
+    double s = w[idx[i]];
+    i64 j = i + 1;
+    for (; j < m && key(idx[j]) == k; ++j) s += w[idx[j]];
+    ua.push_back(k / n);
+    ub.push_back(k % n);
+    uw.push_back(s);
+    i = j;
+  }
+  A.n = n;
+  A.ptr.assign(n + 1, 0);
+  for (size_t e = 0; e < ua.size(); ++e) { A.ptr[ua[e] + 1]++; A.ptr[ub[e] + 1]++; }
+  for (i64 u = 0; u < n; ++u) A.ptr[u + 1] += A.ptr[u];
+  A.col.assign(A.ptr[n], 0);
+  A.val.assign(A.ptr[n], 0);
+  vector<i64> fill(A.ptr.begin(), A.ptr.end() - 1);
+  // unique keys in ascending (a,b) order: row a receives b ascending; row b
+  // receives a ascending because keys are sorted by a first.
+  for (size_t e = 0; e < ua.size(); ++e) {
+    A.col[fill[ua[e]]] = (i32)ub[e]; A.val[fill[ua[e]]++] = uw[e];
+  }
+  for (size_t e = 0; e < ua.size(); ++e) {
+    A.col[fill[ub[e]]] = (i32)ua[e]; A.val[fill[ub[e]]++] = uw[e];
+  }
+  for (i64 u = 0; u < n; ++u) {  // sort each row by column (entries unique)
+    vector<std::pair<i32, double>> row;
+    for (i64 t = A.ptr[u]; t < A.ptr[u + 1]; ++t) row.push_back({A.col[t], A.val[t]});
+    std::sort(row.begin(), row.end());
+    for (size_t t = 0; t < row.size(); ++t) { A.col[A.ptr[u] + t] = row[t].first; A.val[A.ptr[u] + t] = row[t].second; }
+  }
+  A.diag.assign(n, 0);
+  for (i64 u = 0; u < n; ++u)
+    A.diag[u] = row_reduce<double>(A.deg(u), [&](i64 t) { return A.val[A.ptr[u] + t]; });
+  return 0;
+}
+
+bool connected(const Csr& A) {
+  vector<uint8_t> seen(A.n, 0);
+  vector<i64> stack{0};
+  seen[0] = 1;
+  i64 cnt = 1;
+  while (!stack.empty()) {
+    i64 u = stack.back(); stack.pop_back();
+    for (i64 t = A.ptr[u]; t < A.ptr[u + 1]; ++t)
+      if (!seen[A.col[t]]) { seen[A.col[t]] = 1; ++cnt; stack.push_back(A.col[t]); }
+  }
+  return cnt == A.n;
+}
+
+// ---------------------------------------------------------------- colouring
+// Greedy first-fit colouring in priority order (degree descending, hash
+// ascending, id ascending).  Each node takes the smallest colour not used by
+// an already coloured (higher-priority) neighbour.
+bool higher(const Csr& A, const vector<uint64_t>& h, i64 a, i64 b) {
+  if (A.deg(a) != A.deg(b)) return A.deg(a) > A.deg(b);
+  if (h[a] != h[b]) return h[a] < h[b];
+  return a < b;
+}
+vector<i32> colour_greedy(const Csr& A, uint64_t seed, int level) {
+  vector<uint64_t> h(A.n);
+  for (i64 u = 0; u < A.n; ++u) h[u] = hash5(seed, STREAM_COLOUR, (uint64_t)level, 0, (uint64_t)u);
+  vector<i64> order(A.n);
+  std::iota(order.begin(), order.end(), 0);
+  std::sort(order.begin(), order.end(), [&](i64 a, i64 b) { return higher(A, h, a, b); });
+  vector<i32> col(A.n, -1);
+  vector<i64> mark;
+  for (i64 u : order) {
+    mark.assign(A.deg(u) + 2, 0);
+    for (i64 t = A.ptr[u]; t < A.ptr[u + 1]; ++t) {
+      i32 c = col[A.col[t]];
+      if (c >= 0 && c < (i32)mark.size()) mark[c] = 1;
+    }
+    i32 c = 0;
+    while (mark[c]) ++c;
+    col[u] = c;
+  }
+  return col;
+}
+// Jones-Plassmann rounds with the same priority: a node is coloured in the
+// first round in which all its higher-priority neighbours are coloured.
+// Used only to pin that the round-based form equals the sequential one.
+vector<i32> colour_jp(const Csr& A, uint64_t seed, int level, int* rounds) {
+  vector<uint64_t> h(A.n);
+  for (i64 u = 0; u < A.n; ++u) h[u] = hash5(seed, STREAM_COLOUR, (uint64_t)level, 0, (uint64_t)u);
+  vector<i32> col(A.n, -1);
+  i64 left = A.n;
+  int r = 0;
+  while (left > 0) {
+    vector<i32> next = col;
+    for (i64 u = 0; u < A.n; ++u) {
+      if (col[u] >= 0) continue;
+      bool ready = true;
+      for (i64 t = A.ptr[u]; t < A.ptr[u + 1] && ready; ++t)
+        if (higher(A, h, A.col[t], u) && col[A.col[t]] < 0) ready = false;
+      if (!ready) continue;
+      vector<uint8_t> mark(A.deg(u) + 2, 0);
+      for (i64 t = A.ptr[u]; t < A.ptr[u + 1]; ++t) {
+        i32 c = col[A.col[t]];
+        if (c >= 0 && c < (i32)mark.size()) mark[c] = 1;
+      }
+      i32 c = 0;
+      while (mark[c]) ++c;
+      next[u] = c;
+      --left;
+    }
+    col.swap(next);
+    ++r;
+  }
+  if (rounds) *rounds = r;
+  return col;
+}
+
+// Renumber a level into colour-major order (colour, then previous id).
+// perm[new] = old.  Values and the diagonal are carried over unchanged;
+// every row is re-sorted by its new column ids.
+Csr permute(const Csr& A, const vector<i32>& perm) {
+  vector<i32> inv(A.n);
+  for (i64 i = 0; i < A.n; ++i) inv[perm[i]] = (i32)i;
+  Csr B;
+  B.n = A.n;
+  B.ptr.assign(A.n + 1, 0);
+  for (i64 i = 0; i < A.n; ++i) B.ptr[i + 1] = B.ptr[i] + A.deg(perm[i]);
+  B.col.resize(A.nnz());
+  B.val.resize(A.nnz());
+  B.diag.resize(A.n);
+  for (i64 i = 0; i < A.n; ++i) {
+    i64 o = perm[i];
+    vector<std::pair<i32, double>> row;
+    for (i64 t = A.ptr[o]; t < A.ptr[o + 1]; ++t) row.push_back({inv[A.col[t]], A.val[t]});
+    std::sort(row.begin(), row.end());
+    for (size_t t = 0; t < row.size(); ++t) { B.col[B.ptr[i] + t] = row[t].first; B.val[B.ptr[i] + t] = row[t].second; }
+    B.diag[i] = A.diag[o];
+  }
+  return B;
+}
+
+void colour_and_order(Level& L, uint64_t seed, int level) {
+  vector<i32> c = colour_greedy(L.A, seed, level);
+  i32 nc = 0;
+  for (i32 x : c) nc = std::max(nc, x + 1);
+  vector<i32> perm(L.A.n);
+  std::iota(perm.begin(), perm.end(), 0);
+  std::stable_sort(perm.begin(), perm.end(), [&](i32 a, i32 b) { return c[a] < c[b]; });
+  L.ncol = nc;
+  L.cptr.assign(nc + 1, 0);
+  for (i32 x : c) L.cptr[x + 1]++;
+  for (int k = 0; k < nc; ++k) L.cptr[k + 1] += L.cptr[k];
+  L.A = permute(L.A, perm);
+  L.perm = perm;
+}
+
+// ------------------------------------------------------------- Gauss-Seidel
+// One lexicographic sweep (Section 3.1.1, eq. gs): u = 0..n-1,
+// x_u <- (b_u + sum_v w_uv x_v) / a_uu.  On a colour-ordered level this is the
+// multicolour sweep.  k vectors stored n x k row-major are relaxed together.
+template <class T>
+void gs_sweep(const Csr& A, const T* val, const T* diag, const T* b, T* x, int k) {
+  for (i64 u = 0; u < A.n; ++u) {
+    i64 p0 = A.ptr[u];
+    for (int j = 0; j < k; ++j) {
+      T s = row_reduce<T>(A.deg(u), [&](i64 t) { return val[p0 + t] * x[(i64)A.col[p0 + t] * k + j]; });
+      T bu = b ? b[u * k + j] : (T)0;
+      x[u * k + j] = (bu + s) / diag[u];
+    }
+  }
+}
+// r = b - A x, evaluated as (b_u + sum_v w_uv x_v) - a_uu x_u.
+template <class T>
+void residual(const Csr& A, const T* val, const T* diag, const T* b, const T* x, T* r) {
+  for (i64 u = 0; u < A.n; ++u) {
+    i64 p0 = A.ptr[u];
+    T s = row_reduce<T>(A.deg(u), [&](i64 t) { return val[p0 + t] * x[A.col[p0 + t]]; });
+    r[u] = (b[u] + s) - diag[u] * x[u];
+  }
+}
+
+// ------------------------------------------------------ low-degree elimination
+// Section 3.2: sweep nodes in order; an eligible node of degree <= 4 joins F
+// and its neighbours become ineligible.
+vector<uint8_t> elim_select(const Csr& A, int maxdeg) {
+  vector<uint8_t> inF(A.n, 0);
+  for (i64 u = 0; u < A.n; ++u) {
+    if (A.deg(u) > maxdeg) continue;
+    bool ok = true;
+    for (i64 t = A.ptr[u]; t < A.ptr[u + 1]; ++t) if (inF[A.col[t]]) { ok = false; break; }
+    if (ok) inF[u] = 1;
+  }
+  return inF;
+}
+
+// Merge (row, col, value) triples: stable sort by (row, col), sum each run in
+// list order, build CSR with the diagonal as the row sum.
+Csr merge_triples(i64 nc, const vector<i64>& ti, const vector<i64>& tj, const vector<double>& tv) {
+  vector<i64> idx(ti.size());
+  std::iota(idx.begin(), idx.end(), 0);
+  std::stable_sort(idx.begin(), idx.end(), [&](i64 a, i64 b) {
+    return ti[a] != ti[b] ? ti[a] < ti[b] : tj[a] < tj[b];
+  });
+  Csr C;
+  C.n = nc;
+  C.ptr.assign(nc + 1, 0);
+  for (size_t i = 0; i < idx.size();) {
+    i64 r = ti[idx[i]], c = tj[idx[i]];
+    double s = tv[idx[i]];
+    size_t j = i + 1;
+    for (; j < idx.size() && ti[idx[j]] == r && tj[idx[j]] == c; ++j) s += tv[idx[j]];
+    C.col.push_back((i32)c);
+    C.val.push_back(s);
+    C.ptr[r + 1]++;
+    i = j;
+  }
+  for (i64 u = 0; u < nc; ++u) C.ptr[u + 1] += C.ptr[u];
+  C.diag.assign(nc, 0);
+  for (i64 u = 0; u < nc; ++u)
+    C.diag[u] = row_reduce<double>(C.deg(u), [&](i64 t) { return C.val[C.ptr[u] + t]; });
+  return C;
+}
+
+// Schur complement onto C = N \ F (Section 3.2, eq. elim):
+// w^c_ij = w_ij + sum_{f in F adjacent to i and j} w_fi w_fj / a_ff.
+// Triples are listed C-C edges first (rows in id order, CSR order), then the
+// fill of each F node in id order over ordered neighbour pairs (CSR order).
+Csr schur(const Csr& A, const vector<uint8_t>& inF, vector<i32>& crank) {
+  crank.assign(A.n, -1);
+  i64 nc = 0;
+  for (i64 u = 0; u < A.n; ++u) if (!inF[u]) crank[u] = (i32)nc++;
+  vector<i64> ti, tj;
+  vector<double> tv;
+  for (i64 u = 0; u < A.n; ++u) {
+    if (inF[u]) continue;
+    for (i64 t = A.ptr[u]; t < A.ptr[u + 1]; ++t)
+      if (!inF[A.col[t]]) { ti.push_back(crank[u]); tj.push_back(crank[A.col[t]]); tv.push_back(A.val[t]); }
+  }
+  for (i64 f = 0; f < A.n; ++f) {
+    if (!inF[f]) continue;
+    for (i64 a = A.ptr[f]; a < A.ptr[f + 1]; ++a)
+      for (i64 b = A.ptr[f]; b < A.ptr[f + 1]; ++b) {
+        if (a == b) continue;
+        ti.push_back(crank[A.col[a]]);
+        tj.push_back(crank[A.col[b]]);
+        tv.push_back((A.val[a] * A.val[b]) / A.diag[f]);
+      }
+  }
+  return merge_triples(nc, ti, tj, tv);
+}
+
+// ------------------------------------------------------------ aggregation
+// Section 3.3-3.4: test vectors, affinity (eq. cuv), energy-ratio test
+// (eq. qut, read with the ratio inverted so that it is >= 1), hubs (Section
+// 3.4.1 footnote), weak edges, staged aggregation (Section 3.4.2).
+struct AggResult { vector<i32> agg; i64 nc; };
+
+AggResult aggregate(const Level& L, const Opts& o, int agg_index, int level, AggDiag& D) {
+  const Csr& A = L.A;
+  const i64 n = A.n;
+  const int K = std::min(o.tv_k_max, o.tv_k_min + 2 * agg_index);
+  D.K = K;
+  // test vectors: U[-1,1) draws, then nu sweeps of GS on A x = 0
+  vector<double> X((size_t)n * K);
+  for (i64 u = 0; u < n; ++u)
+    for (int k = 0; k < K; ++k)
+      X[u * K + k] = unit_pm1(hash5(o.seed, STREAM_TV, (uint64_t)level, (uint64_t)k, (uint64_t)u));
+  for (int s = 0; s < o.tv_sweeps; ++s) gs_sweep<double>(A, A.val.data(), A.diag.data(), nullptr, X.data(), K);
+  D.tv = X;
+  // node quantities
+  vector<double> nrm(n), ystar((size_t)n * K), emin((size_t)n * K), sw(n), swd(n), maxw(n, 0.0);
+  for (i64 u = 0; u < n; ++u) {
+    double s = 0;
+    for (int k = 0; k < K; ++k) s += X[u * K + k] * X[u * K + k];
+    nrm[u] = s;
+    i64 p0 = A.ptr[u];
+    for (int k = 0; k < K; ++k) {
+      double B = row_reduce<double>(A.deg(u), [&](i64 t) { return A.val[p0 + t] * X[(i64)A.col[p0 + t] * K + k]; });
+      double y = B / A.diag[u];
+      double S2 = row_reduce<double>(A.deg(u), [&](i64 t) {
+        double d = X[(i64)A.col[p0 + t] * K + k] - y;
+        return A.val[p0 + t] * (d * d);
+      });
+      ystar[u * K + k] = y;
+      emin[u * K + k] = 0.5 * S2;  // min_y E_u(x; y)
+    }
+    sw[u] = row_reduce<double>(A.deg(u), [&](i64 t) { return A.val[p0 + t]; });
+    swd[u] = row_reduce<double>(A.deg(u), [&](i64 t) { return A.val[p0 + t] * (double)A.deg(A.col[p0 + t]); });
+    for (i64 t = p0; t < A.ptr[u + 1]; ++t) maxw[u] = std::max(maxw[u], A.val[t]);
+  }
+  // per directed edge: affinity, admissibility, weak flag
+  const i64 E2 = A.nnz();
+  D.aff.assign(E2, 1.0);
+  D.ok.assign(E2, 0);
+  D.weak.assign(E2, 0);
+  const double qfac = 2.0 * (o.q_max - 1.0);
+  for (i64 u = 0; u < n; ++u) {
+    for (i64 t = A.ptr[u]; t < A.ptr[u + 1]; ++t) {
+      i64 s = A.col[t];
+      double p = 0;
+      for (int k = 0; k < K; ++k) p += X[u * K + k] * X[s * K + k];
+      double c = 1.0;
+      if (nrm[u] > 0 && nrm[s] > 0) {
+        c = 1.0 - (p * p) / (nrm[u] * nrm[s]);
+        if (c < 0) c = 0;
+      }
+      D.aff[t] = c;
+      bool ok = true;
+      for (int k = 0; k < K && ok; ++k) {
+        double d = X[s * K + k] - ystar[u * K + k];
+        ok = (A.diag[u] * (d * d)) <= (qfac * emin[u * K + k]);
+      }
+      D.ok[t] = ok;
+      D.weak[t] = A.val[t] < o.weak_edge_ratio * std::max(maxw[u], maxw[s]);
+    }
+  }
+  // initial states: hubs are seeds; nodes with only weak edges go to the dummy aggregate
+  vector<i32> st(n, ST_UNDECIDED), seedof(n, -1);
+  D.hub.assign(n, 0);
+  for (i64 u = 0; u < n; ++u) {
+    if ((double)A.deg(u) * sw[u] >= o.hub_factor * swd[u]) { D.hub[u] = 1; st[u] = ST_SEED; continue; }
+    bool allweak = A.deg(u) > 0;
+    for (i64 t = A.ptr[u]; t < A.ptr[u + 1]; ++t) if (!D.weak[t]) { allweak = false; break; }
+    if (allweak) st[u] = ST_DUMMY;
+  }
+  auto candidate = [&](i64 t, double delta) {
+    i32 s = A.col[t];
+    return (st[s] == ST_SEED || st[s] == ST_UNDECIDED) && !D.weak[t] && D.ok[t] && D.aff[t] <= delta;
+  };
+  // stage-1 threshold: a quantile (1.0 = the largest) over undecided nodes of
+  // their best candidate affinity; stage 2 admits every candidate.
+  vector<double> best;
+  for (i64 u = 0; u < n; ++u) {
+    if (st[u] != ST_UNDECIDED) continue;
+    double b = 2.0;
+    for (i64 t = A.ptr[u]; t < A.ptr[u + 1]; ++t) if (candidate(t, 1.0)) b = std::min(b, D.aff[t]);
+    if (b <= 1.0) best.push_back(b);
+  }
+  std::sort(best.begin(), best.end());
+  D.delta1 = best.empty() ? 1.0 : best[(size_t)((double)(best.size() - 1) * o.stage1_quantile)];
+  const double amax = 0.7 / o.gamma;
+  auto run_stage = [&](double delta) {
+    for (int c = 0; c < L.ncol; ++c)
+      for (i64 u = L.cptr[c]; u < L.cptr[c + 1]; ++u) {
+        if (st[u] != ST_UNDECIDED) continue;
+        i64 bt = -1;
+        for (i64 t = A.ptr[u]; t < A.ptr[u + 1]; ++t)
+          if (candidate(t, delta) && (bt < 0 || D.aff[t] < D.aff[bt])) bt = t;
+        if (bt >= 0) { st[u] = ST_ASSOC; seedof[u] = A.col[bt]; st[A.col[bt]] = ST_SEED; }
+      }
+    i64 cnt = 0, ndum = 0;
+    for (i64 u = 0; u < n; ++u) { cnt += (st[u] == ST_SEED || st[u] == ST_UNDECIDED); ndum += st[u] == ST_DUMMY; }
+    return (double)(cnt + (ndum > 0 ? 1 : 0)) / (double)n;
+  };
+  D.alpha1 = run_stage(D.delta1);
+  D.stage = 1;
+  D.alpha2 = -1;
+  if (D.alpha1 > amax) {
+    vector<i32> st1 = st, so1 = seedof;
+    D.alpha2 = run_stage(1.0);
+    if (std::fabs(D.alpha1 - amax) <= std::fabs(D.alpha2 - amax)) { st = st1; seedof = so1; D.stage = 1; }
+    else D.stage = 2;
+  }
+  for (i64 u = 0; u < n; ++u) if (st[u] == ST_UNDECIDED) st[u] = ST_SEED;
+  D.state = st;
+  // numbering: representatives (seeds and the smallest dummy member) in id order
+  i64 dmin = -1;
+  for (i64 u = 0; u < n; ++u) if (st[u] == ST_DUMMY) { dmin = u; break; }
+  vector<i32> id(n, -1);
+  i64 nc = 0;
+  for (i64 u = 0; u < n; ++u) if (st[u] == ST_SEED || u == dmin) id[u] = (i32)nc++;
+  AggResult R;
+  R.nc = nc;
+  R.agg.assign(n, -1);
+  for (i64 u = 0; u < n; ++u) {
+    if (st[u] == ST_SEED) R.agg[u] = id[u];
+    else if (st[u] == ST_ASSOC) R.agg[u] = id[seedof[u]];
+    else R.agg[u] = id[dmin];
+  }
+  return R;
+}
+
+// Galerkin operator P^T A P for a 0/1 aggregation P (Section 2, eq. galerkin):
+// coarse off-diagonal weight = sum of fine weights between the two aggregates.
+Csr galerkin(const Csr& A, const vector<i32>& agg, i64 nc) {
+  vector<i64> ti, tj;
+  vector<double> tv;
+  for (i64 u = 0; u < A.n; ++u)
+    for (i64 t = A.ptr[u]; t < A.ptr[u + 1]; ++t)
+      if (agg[u] != agg[A.col[t]]) { ti.push_back(agg[u]); tj.push_back(agg[A.col[t]]); tv.push_back(A.val[t]); }
+  return merge_triples(nc, ti, tj, tv);
+}
+
+// ------------------------------------------------------------- dense coarsest
+// Coarsest level: Cholesky of A_L + (mean diag / n_L) 1 1^T, which is SPD for a
+// connected Laplacian and returns the zero-mean solution for a zero-sum rhs.
+void coarsest_factor(Hier& H) {
+  const Csr& A = H.lv.back().A;
+  i64 n = A.n;
+  H.nL = n;
+  double dbar = 0;
+  for (i64 u = 0; u < n; ++u) dbar += A.diag[u];
+  dbar /= (double)n;
+  if (!(dbar > 0)) dbar = 1.0;
+  double c = dbar / (double)n;
+  vector<double> M((size_t)n * n, c);
+  for (i64 u = 0; u < n; ++u) {
+    M[u * n + u] += A.diag[u];
+    for (i64 t = A.ptr[u]; t < A.ptr[u + 1]; ++t) M[u * n + A.col[t]] -= A.val[t];
+  }
+  for (i64 j = 0; j < n; ++j) {
+    double s = M[j * n + j];
+    for (i64 k = 0; k < j; ++k) s -= M[j * n + k] * M[j * n + k];
+    M[j * n + j] = std::sqrt(s);
+    for (i64 i = j + 1; i < n; ++i) {
+      double t = M[i * n + j];
+      for (i64 k = 0; k < j; ++k) t -= M[i * n + k] * M[j * n + k];
+      M[i * n + j] = t / M[j * n + j];
+    }
+  }
+  for (i64 i = 0; i < n; ++i) for (i64 j = i + 1; j < n; ++j) M[i * n + j] = 0;
+  H.chol = M;
+}
+void coarsest_solve(const Hier& H, const double* b, double* x) {
+  i64 n = H.nL;
+  const vector<double>& M = H.chol;
+  vector<double> y(n);
+  for (i64 i = 0; i < n; ++i) {
+    double s = b[i];
+    for (i64 k = 0; k < i; ++k) s -= M[i * n + k] * y[k];
+    y[i] = s / M[i * n + i];
+  }
+  for (i64 i = n - 1; i >= 0; --i) {
+    double s = y[i];
+    for (i64 k = i + 1; k < n; ++k) s -= M[k * n + i] * x[k];
+    x[i] = s / M[i * n + i];
+  }
+}
+
+// ------------------------------------------------------------------- setup
+// Section 4.1: coarsen by low-degree elimination or caliber-1 aggregation
+// until fewer than coarsest_max_n nodes remain.
+int setup(Hier& H, i64 n, i64 m, const i32* eu, const i32* ev, const double* w) {
+  Level L1;
+  int rc = build_laplacian(n, m, eu, ev, w, L1.A);
+  if (rc) return rc;
+  if (!connected(L1.A)) return 3;
+  L1.type = L_FINEST;
+  colour_and_order(L1, H.o.seed, 0);
+  H.perm1 = L1.perm;
+  H.lv.push_back(std::move(L1));
+  int nagg = 0;
+  while (H.lv.back().A.n >= H.o.coarsest_max_n && (int)H.lv.size() < H.o.max_levels) {
+    int l = (int)H.lv.size() - 1;
+    Level& F = H.lv[l];
+    // elimination round
+    vector<uint8_t> inF = elim_select(F.A, H.o.elim_max_degree);
+    i64 nF = 0;
+    for (auto v : inF) nF += v;
+    if (nF > 0 && (double)nF >= H.o.elim_stop_frac * (double)F.A.n) {
+      Level C;
+      vector<i32> crank;
+      C.A = schur(F.A, inF, crank);
+      C.type = L_ELIM;
+      C.nF = nF;
+      colour_and_order(C, H.o.seed, l + 1);
+      vector<i32> inv(C.A.n);
+      for (i64 i = 0; i < C.A.n; ++i) inv[C.perm[i]] = (i32)i;
+      C.cidx.assign(F.A.n, -1);
+      for (i64 u = 0; u < F.A.n; ++u) if (crank[u] >= 0) C.cidx[u] = inv[crank[u]];
+      H.lv.push_back(std::move(C));
+      continue;
+    }
+    AggDiag D;
+    AggResult R = aggregate(F, H.o, nagg, l, D);
+    F.diag = D;
+    if (R.nc >= F.A.n) break;  // no coarsening possible: this level is the coarsest
+    Level C;
+    C.A = galerkin(F.A, R.agg, R.nc);
+    C.type = L_AGG;
+    colour_and_order(C, H.o.seed, l + 1);
+    vector<i32> inv(C.A.n);
+    for (i64 i = 0; i < C.A.n; ++i) inv[C.perm[i]] = (i32)i;
+    C.agg.resize(F.A.n);
+    for (i64 u = 0; u < F.A.n; ++u) C.agg[u] = inv[R.agg[u]];
+    H.lv.push_back(std::move(C));
+    ++nagg;
+  }
+  // cycle indices (Section 4.2, eq. cycle_index, read so that gamma^l >= 1)
+  double E1 = (double)H.lv[0].A.nnz();
+  for (size_t l = 0; l + 1 < H.lv.size(); ++l) {
+    Level& F = H.lv[l];
+    const Level& C = H.lv[l + 1];
+    if (C.type == L_ELIM) { F.gamma_next = 1.0; continue; }
+    double El = (double)F.A.nnz(), Ec = (double)C.A.nnz();
+    if (El > 0.1 * E1) F.gamma_next = H.o.gamma;
+    else if (Ec <= 0) F.gamma_next = 1.0;
+    else F.gamma_next = std::max(1.0, std::min(2.0, 0.7 * El / Ec));
+  }
+  for (auto& L : H.lv) {
+    L.val32.assign(L.A.val.begin(), L.A.val.end());
+    L.diag32.assign(L.A.diag.begin(), L.A.diag.end());
+  }
+  coarsest_factor(H);
+  return 0;
+}
+
+// ------------------------------------------------------------------- cycle
+// Section 4.2 cycle with pre/post relaxation (1,2), flat energy correction
+// (eq. galerkin2) or iterate recombination (eq. recomb), fractional cycle
+// index by per-level visit counters, dense coarsest solve, mean removal.
+template <class T>
+struct Work {
+  vector<vector<T>> x, b, r;
+  vector<vector<vector<T>>> X, R;  // saved iterates / residuals per sub-cycle
+  vector<i64> count;
+};
+
+template <class T> const T* VAL(const Level& L);
+template <> const double* VAL<double>(const Level& L) { return L.A.val.data(); }
+template <> const float* VAL<float>(const Level& L) { return L.val32.data(); }
+template <class T> const T* DIAG(const Level& L);
+template <> const double* DIAG<double>(const Level& L) { return L.A.diag.data(); }
+template <> const float* DIAG<float>(const Level& L) { return L.diag32.data(); }
+
+template <class T>
+double dot(const vector<T>& a, const vector<T>& b) {
+  double s = 0;
+  for (size_t i = 0; i < a.size(); ++i) s += (double)a[i] * (double)b[i];
+  return s;
+}
+
+// Residual-minimising combination y = x + sum_i alpha_i (x_i - x) (eq. recomb).
+template <class T>
+void recombine(const Hier& H, Work<T>& W, int l, int th) {
+  const Level& L = H.lv[l];
+  i64 n = L.A.n;
+  vector<T>& x = W.x[l];
+  vector<T>& r = W.r[l];
+  residual<T>(L.A, VAL<T>(L), DIAG<T>(L), W.b[l].data(), x.data(), r.data());
+  vector<vector<T>> d(th, vector<T>(n));
+  for (int i = 0; i < th; ++i) for (i64 u = 0; u < n; ++u) d[i][u] = W.R[l][i][u] - r[u];
+  double G[2][2] = {{0, 0}, {0, 0}}, g[2] = {0, 0}, rr = dot(r, r);
+  for (int i = 0; i < th; ++i) {
+    g[i] = dot(d[i], r);
+    for (int j = 0; j < th; ++j) G[i][j] = dot(d[i], d[j]);
+  }
+  double alpha[2] = {0, 0};
+  const double tiny = 1e-28 * rr;
+  if (th == 1) {
+    if (G[0][0] > tiny) alpha[0] = -g[0] / G[0][0];
+  } else {
+    double det = G[0][0] * G[1][1] - G[0][1] * G[1][0];
+    if (G[0][0] > tiny && G[1][1] > tiny && det > 1e-12 * G[0][0] * G[1][1]) {
+      alpha[0] = (-g[0] * G[1][1] + g[1] * G[0][1]) / det;
+      alpha[1] = (-g[1] * G[0][0] + g[0] * G[1][0]) / det;
+    } else {
+      int i = G[0][0] >= G[1][1] ? 0 : 1;
+      if (G[i][i] > tiny) alpha[i] = -g[i] / G[i][i];
+    }
+  }
+  for (i64 u = 0; u < n; ++u) {
+    double y = (double)x[u];
+    for (int i = 0; i < th; ++i) y += alpha[i] * ((double)W.X[l][i][u] - (double)x[u]);
+    x[u] = (T)y;
+  }
+}
+
+template <class T>
+void visit(const Hier& H, Work<T>& W, int l, int th);
+
+template <class T>
+void body(const Hier& H, Work<T>& W, int l, int sub) {
+  const int Lc = (int)H.lv.size() - 1;
+  const Level& L = H.lv[l];
+  vector<T>& x = W.x[l];
+  vector<T>& b = W.b[l];
+  vector<T>& r = W.r[l];
+  i64 n = L.A.n;
+  if (l == Lc) {
+    vector<double> bd(b.begin(), b.end()), xd(n);
+    coarsest_solve(H, bd.data(), xd.data());
+    for (i64 u = 0; u < n; ++u) x[u] = (T)xd[u];
+    return;
+  }
+  const Level& C = H.lv[l + 1];
+  vector<T>& xc = W.x[l + 1];
+  vector<T>& bc = W.b[l + 1];
+  if (C.type == L_ELIM) {
+    residual<T>(L.A, VAL<T>(L), DIAG<T>(L), b.data(), x.data(), r.data());
+    // restriction P^T r: r_c + sum over F neighbours (w_cf / a_ff) r_f
+    for (i64 u = 0; u < n; ++u) {
+      if (C.cidx[u] < 0) continue;
+      T s = r[u];
+      for (i64 t = L.A.ptr[u]; t < L.A.ptr[u + 1]; ++t) {
+        i32 f = L.A.col[t];
+        if (C.cidx[f] < 0) s += (VAL<T>(L)[t] / DIAG<T>(L)[f]) * r[f];
+      }
+      bc[C.cidx[u]] = s;
+    }
+    std::fill(xc.begin(), xc.end(), (T)0);
+    visit<T>(H, W, l + 1, 1);
+    // exact correction: e_C = e^c, e_F = (r_F + W_FC e^c) / a_FF
+    for (i64 u = 0; u < n; ++u) {
+      if (C.cidx[u] >= 0) continue;
+      T s = r[u];
+      for (i64 t = L.A.ptr[u]; t < L.A.ptr[u + 1]; ++t) s += VAL<T>(L)[t] * xc[C.cidx[L.A.col[t]]];
+      x[u] += s / DIAG<T>(L)[u];
+    }
+    for (i64 u = 0; u < n; ++u) if (C.cidx[u] >= 0) x[u] += xc[C.cidx[u]];
+    return;
+  }
+  const bool rec = H.o.ec == 0;
+  for (int s = 0; s < H.o.nu_pre; ++s) gs_sweep<T>(L.A, VAL<T>(L), DIAG<T>(L), b.data(), x.data(), 1);
+  residual<T>(L.A, VAL<T>(L), DIAG<T>(L), b.data(), x.data(), r.data());
+  if (rec) { W.X[l][sub] = x; W.R[l][sub] = r; }
+  const T mu = rec ? (T)1 : (T)H.o.mu;
+  std::fill(bc.begin(), bc.end(), (T)0);
+  for (i64 u = 0; u < n; ++u) bc[C.agg[u]] += r[u];
+  for (auto& v : bc) v = mu * v;
+  std::fill(xc.begin(), xc.end(), (T)0);
+  i64 c = W.count[l]++;
+  double gl = L.gamma_next;
+  int th = (int)(std::ceil((double)(c + 1) * gl) - std::ceil((double)c * gl));
+  visit<T>(H, W, l + 1, th);
+  for (i64 u = 0; u < n; ++u) x[u] += xc[C.agg[u]];
+  for (int s = 0; s < H.o.nu_post; ++s) gs_sweep<T>(L.A, VAL<T>(L), DIAG<T>(L), b.data(), x.data(), 1);
+}
+
+template <class T>
+void visit(const Hier& H, Work<T>& W, int l, int th) {
+  const int Lc = (int)H.lv.size() - 1;
+  if (l == Lc) { body<T>(H, W, l, 0); return; }  // repeated exact solves are identical
+  for (int i = 0; i < th; ++i) body<T>(H, W, l, i);
+  if (H.o.ec == 0 && H.lv[l + 1].type == L_AGG) recombine<T>(H, W, l, th);
+}
+
+template <class T>
+void init_work(const Hier& H, Work<T>& W) {
+  size_t nl = H.lv.size();
+  W.x.resize(nl); W.b.resize(nl); W.r.resize(nl); W.X.resize(nl); W.R.resize(nl);
+  W.count.assign(nl, 0);
+  for (size_t l = 0; l < nl; ++l) {
+    i64 n = H.lv[l].A.n;
+    W.x[l].assign(n, 0); W.b[l].assign(n, 0); W.r[l].assign(n, 0);
+    W.X[l].assign(2, vector<T>(n, 0)); W.R[l].assign(2, vector<T>(n, 0));
+  }
+}
+
+template <class T>
+void cycle(const Hier& H, Work<T>& W) {
+  std::fill(W.count.begin(), W.count.end(), 0);
+  visit<T>(H, W, 0, 1);
+  vector<T>& x = W.x[0];
+  double mean = 0;
+  for (T v : x) mean += (double)v;
+  mean /= (double)x.size();
+  for (auto& v : x) v = (T)((double)v - mean);
+}
+
+double norm_res(const Level& L, const vector<double>& b, const vector<double>& x, vector<double>& r) {
+  residual<double>(L.A, L.A.val.data(), L.A.diag.data(), b.data(), x.data(), r.data());
+  return std::sqrt(dot(r, r));
+}
+
+struct SolveInfo { i64 cycles = 0; double rel = 0, acf = 0, removed_mean = 0; };
+
+// FP64 solve from x0 = 0 (or warm start) until ||b - Ax|| <= tol ||b||.
+int solve64(const Hier& H, const double* bin, double* xout, int warm, SolveInfo& I, double* hist) {
+  const Level& L = H.lv[0];
+  i64 n = L.A.n;
+  Work<double> W;
+  init_work(H, W);
+  double mb = 0;
+  for (i64 i = 0; i < n; ++i) mb += bin[i];
+  mb /= (double)n;
+  I.removed_mean = mb;
+  for (i64 i = 0; i < n; ++i) W.b[0][i] = bin[H.perm1[i]] - mb;
+  for (i64 i = 0; i < n; ++i) W.x[0][i] = warm ? xout[H.perm1[i]] : 0.0;
+  vector<double> r(n);
+  double nb = std::sqrt(dot(W.b[0], W.b[0]));
+  double r0 = norm_res(L, W.b[0], W.x[0], r), rk = r0;
+  if (hist) hist[0] = r0;
+  i64 it = 0;
+  if (nb == 0) { for (i64 i = 0; i < n; ++i) xout[H.perm1[i]] = 0; I.cycles = 0; I.rel = 0; return 0; }
+  while (rk > H.o.tol * nb && it < H.o.max_cycles) {
+    cycle<double>(H, W);
+    rk = norm_res(L, W.b[0], W.x[0], r);
+    ++it;
+    if (hist) hist[it] = rk;
+    if (!std::isfinite(rk)) break;
+  }
+  for (i64 i = 0; i < n; ++i) xout[H.perm1[i]] = W.x[0][i];
+  I.cycles = it;
+  I.rel = rk / nb;
+  I.acf = it > 0 ? std::pow(rk / r0, 1.0 / (double)it) : 0.0;
+  if (!std::isfinite(rk)) return 5;
+  return rk <= H.o.tol * nb ? 0 : 4;
+}
+
+// FP32 cycles with FP64 iterative refinement: the outer residual, the
+// zero-mean projection, recombination coefficients and the coarsest solve
+// stay FP64; relaxation, transfers and level matrices are FP32.
+int solve32(const Hier& H, const double* bin, double* xout, int warm, SolveInfo& I, double* hist) {
+  const Level& L = H.lv[0];
+  i64 n = L.A.n;
+  Work<float> W;
+  init_work(H, W);
+  double mb = 0;
+  for (i64 i = 0; i < n; ++i) mb += bin[i];
+  mb /= (double)n;
+  I.removed_mean = mb;
+  vector<double> b(n), x(n), r(n);
+  for (i64 i = 0; i < n; ++i) b[i] = bin[H.perm1[i]] - mb;
+  for (i64 i = 0; i < n; ++i) x[i] = warm ? xout[H.perm1[i]] : 0.0;
+  double nb = std::sqrt(dot(b, b));
+  if (nb == 0) { for (i64 i = 0; i < n; ++i) xout[H.perm1[i]] = 0; I.cycles = 0; I.rel = 0; return 0; }
+  double r0 = norm_res(L, b, x, r), rk = r0;
+  if (hist) hist[0] = r0;
+  i64 it = 0;
+  while (rk > H.o.tol * nb && it < H.o.max_cycles) {
+    double mr = 0;
+    for (double v : r) mr += v;
+    mr /= (double)n;
+    for (i64 i = 0; i < n; ++i) W.b[0][i] = (float)(r[i] - mr);
+    std::fill(W.x[0].begin(), W.x[0].end(), 0.0f);
+    cycle<float>(H, W);
+    for (i64 i = 0; i < n; ++i) x[i] += (double)W.x[0][i];
+    double mx = 0;
+    for (double v : x) mx += v;
+    mx /= (double)n;
+    for (auto& v : x) v -= mx;
+    rk = norm_res(L, b, x, r);
+    ++it;
+    if (hist) hist[it] = rk;
+    if (!std::isfinite(rk)) break;
+  }
+  for (i64 i = 0; i < n; ++i) xout[H.perm1[i]] = x[i];
+  I.cycles = it;
+  I.rel = rk / nb;
+  I.acf = it > 0 ? std::pow(rk / r0, 1.0 / (double)it) : 0.0;
+  if (!std::isfinite(rk)) return 5;
+  return rk <= H.o.tol * nb ? 0 : 4;
+}
+
+}  // namespace
+
+// ======================================================================= C ABI
+extern "C" {
+
+typedef struct ora_opts {
+  double gamma; int nu_pre, nu_post;
+  int tv_k_min, tv_k_max, tv_sweeps;
+  double q_max, mu, hub_factor;
+  int elim_max_degree, coarsest_max_n;
+  double weak_edge_ratio, elim_stop_frac;
+  int ec; double tol; int max_cycles; uint64_t seed;
+  double stage1_quantile;
+} ora_opts;
+
+void ora_opts_default(ora_opts* o) {
+  Opts d;
+  o->gamma = d.gamma; o->nu_pre = d.nu_pre; o->nu_post = d.nu_post;
+  o->tv_k_min = d.tv_k_min; o->tv_k_max = d.tv_k_max; o->tv_sweeps = d.tv_sweeps;
+  o->q_max = d.q_max; o->mu = d.mu; o->hub_factor = d.hub_factor;
+  o->elim_max_degree = d.elim_max_degree; o->coarsest_max_n = d.coarsest_max_n;
+  o->weak_edge_ratio = d.weak_edge_ratio; o->elim_stop_frac = d.elim_stop_frac;
+  o->ec = d.ec; o->tol = d.tol; o->max_cycles = d.max_cycles; o->seed = d.seed;
+  o->stage1_quantile = d.stage1_quantile;
+}
+
+static Opts to_opts(const ora_opts* o) {
+  Opts d;
+  if (!o) return d;
+  d.gamma = o->gamma; d.nu_pre = o->nu_pre; d.nu_post = o->nu_post;
+  d.tv_k_min = o->tv_k_min; d.tv_k_max = o->tv_k_max; d.tv_sweeps = o->tv_sweeps;
+  d.q_max = o->q_max; d.mu = o->mu; d.hub_factor = o->hub_factor;
+  d.elim_max_degree = o->elim_max_degree; d.coarsest_max_n = o->coarsest_max_n;
+  d.weak_edge_ratio = o->weak_edge_ratio; d.elim_stop_frac = o->elim_stop_frac;
+  d.ec = o->ec; d.tol = o->tol; d.max_cycles = o->max_cycles; d.seed = o->seed;
+  d.stage1_quantile = o->stage1_quantile;
+  return d;
+}
+
+// --- Laplacian of a COO edge list (host arrays).  Returns status; fills nnz.
+void* ora_laplacian(i64 n, i64 m, const i32* eu, const i32* ev, const double* w, int* status) {
+  Csr* A = new Csr;
+  int rc = build_laplacian(n, m, eu, ev, w, *A);
+  if (status) *status = rc;
+  if (rc) { delete A; return nullptr; }
+  return A;
+}
+i64 ora_csr_nnz(void* a) { return ((Csr*)a)->nnz(); }
+void ora_csr_export(void* a, i64* ptr, i32* col, double* val, double* diag) {
+  Csr* A = (Csr*)a;
+  std::copy(A->ptr.begin(), A->ptr.end(), ptr);
+  std::copy(A->col.begin(), A->col.end(), col);
+  std::copy(A->val.begin(), A->val.end(), val);
+  std::copy(A->diag.begin(), A->diag.end(), diag);
+}
+void ora_csr_free(void* a) { delete (Csr*)a; }
+int ora_connected(i64 n, const i64* ptr, const i32* col) {
+  Csr A; A.n = n; A.ptr.assign(ptr, ptr + n + 1); A.col.assign(col, col + ptr[n]);
+  return connected(A) ? 1 : 0;
+}
+
+static Csr wrap(i64 n, const i64* ptr, const i32* col, const double* val, const double* diag) {
+  Csr A; A.n = n; A.ptr.assign(ptr, ptr + n + 1);
+  A.col.assign(col, col + ptr[n]);
+  if (val) A.val.assign(val, val + ptr[n]);
+  if (diag) A.diag.assign(diag, diag + n);
+  return A;
+}
+
+// --- greedy colouring (sequential and Jones-Plassmann rounds)
+void ora_colour(i64 n, const i64* ptr, const i32* col, uint64_t seed, int level, i32* out) {
+  Csr A = wrap(n, ptr, col, nullptr, nullptr);
+  vector<i32> c = colour_greedy(A, seed, level);
+  std::copy(c.begin(), c.end(), out);
+}
+int ora_colour_jp(i64 n, const i64* ptr, const i32* col, uint64_t seed, int level, i32* out) {
+  Csr A = wrap(n, ptr, col, nullptr, nullptr);
+  int r = 0;
+  vector<i32> c = colour_jp(A, seed, level, &r);
+  std::copy(c.begin(), c.end(), out);
+  return r;
+}
+uint64_t ora_hash5(uint64_t seed, uint64_t stream, uint64_t a, uint64_t b, uint64_t c) { return hash5(seed, stream, a, b, c); }
+double ora_unit_pm1(uint64_t h) { return unit_pm1(h); }
+double ora_row_reduce(i64 len, const double* terms) { return row_reduce<double>(len, [&](i64 t) { return terms[t]; }); }
+
+// --- Gauss-Seidel sweeps and residual on a raw CSR (k vectors row-major)
+void ora_gs(i64 n, const i64* ptr, const i32* col, const double* val, const double* diag,
+            const double* b, double* x, int k, int sweeps) {
+  Csr A = wrap(n, ptr, col, val, diag);
+  for (int s = 0; s < sweeps; ++s) gs_sweep<double>(A, A.val.data(), A.diag.data(), b, x, k);
+}
+void ora_gs32(i64 n, const i64* ptr, const i32* col, const float* val, const float* diag,
+              const float* b, float* x, int k, int sweeps) {
+  Csr A = wrap(n, ptr, col, nullptr, nullptr);
+  for (int s = 0; s < sweeps; ++s) gs_sweep<float>(A, val, diag, b, x, k);
+}
+void ora_residual(i64 n, const i64* ptr, const i32* col, const double* val, const double* diag,
+                  const double* b, const double* x, double* r) {
+  Csr A = wrap(n, ptr, col, val, diag);
+  residual<double>(A, A.val.data(), A.diag.data(), b, x, r);
+}
+// Multicolour GS on an unpermuted system: colours in order, ids ascending inside.
+void ora_gs_multicolour(i64 n, const i64* ptr, const i32* col, const double* val, const double* diag,
+                        const i32* colour, const double* b, double* x) {
+  i32 nc = 0;
+  for (i64 u = 0; u < n; ++u) nc = std::max(nc, colour[u] + 1);
+  for (i32 c = 0; c < nc; ++c)
+    for (i64 u = 0; u < n; ++u) {
+      if (colour[u] != c) continue;
+      i64 p0 = ptr[u];
+      double s = row_reduce<double>(ptr[u + 1] - p0, [&](i64 t) { return val[p0 + t] * x[col[p0 + t]]; });
+      x[u] = (b[u] + s) / diag[u];
+    }
+}
+
+// --- elimination and Galerkin building blocks
+void ora_elim_select(i64 n, const i64* ptr, const i32* col, int maxdeg, uint8_t* inF) {
+  Csr A = wrap(n, ptr, col, nullptr, nullptr);
+  vector<uint8_t> f = elim_select(A, maxdeg);
+  std::copy(f.begin(), f.end(), inF);
+}
+void* ora_schur(i64 n, const i64* ptr, const i32* col, const double* val, const double* diag,
+                const uint8_t* inF, i32* crank) {
+  Csr A = wrap(n, ptr, col, val, diag);
+  vector<uint8_t> f(inF, inF + n);
+  vector<i32> cr;
+  Csr* C = new Csr(schur(A, f, cr));
+  std::copy(cr.begin(), cr.end(), crank);
+  return C;
+}
+i64 ora_csr_n(void* a) { return ((Csr*)a)->n; }
+void* ora_galerkin(i64 n, const i64* ptr, const i32* col, const double* val, const double* diag,
+                   const i32* agg, i64 nc) {
+  Csr A = wrap(n, ptr, col, val, diag);
+  vector<i32> g(agg, agg + n);
+  return new Csr(galerkin(A, g, nc));
+}
+
+// --- hierarchy
+void* ora_setup(i64 n, i64 m, const i32* eu, const i32* ev, const double* w, const ora_opts* o, int* status) {
+  Hier* H = new Hier;
+  H->o = to_opts(o);
+  int rc = setup(*H, n, m, eu, ev, w);
+  if (status) *status = rc;
+  if (rc) { delete H; return nullptr; }
+  return H;
+}
+void ora_free(void* h) { delete (Hier*)h; }
+int ora_num_levels(void* h) { return (int)((Hier*)h)->lv.size(); }
+// dims: n, nnz, type, ncol, nF, K, stage, (reserved)
+void ora_level_dims(void* h, int l, i64* d) {
+  const Level& L = ((Hier*)h)->lv[l];
+  d[0] = L.A.n; d[1] = L.A.nnz(); d[2] = L.type; d[3] = L.ncol; d[4] = L.nF;
+  d[5] = L.diag.K; d[6] = L.diag.stage; d[7] = 0;
+}
+double ora_level_gamma(void* h, int l) { return ((Hier*)h)->lv[l].gamma_next; }
+void ora_level_export(void* h, int l, i64* ptr, i32* col, double* val, double* diag, i64* cptr, i32* perm) {
+  const Level& L = ((Hier*)h)->lv[l];
+  if (ptr) std::copy(L.A.ptr.begin(), L.A.ptr.end(), ptr);
+  if (col) std::copy(L.A.col.begin(), L.A.col.end(), col);
+  if (val) std::copy(L.A.val.begin(), L.A.val.end(), val);
+  if (diag) std::copy(L.A.diag.begin(), L.A.diag.end(), diag);
+  if (cptr) std::copy(L.cptr.begin(), L.cptr.end(), cptr);
+  if (perm) std::copy(L.perm.begin(), L.perm.end(), perm);
+}
+// transfer into level l (l >= 1): agg (AGG) or cidx (ELIM), length n_{l-1}
+void ora_transfer_export(void* h, int l, i32* out) {
+  const Level& L = ((Hier*)h)->lv[l];
+  const vector<i32>& v = L.type == L_AGG ? L.agg : L.cidx;
+  std::copy(v.begin(), v.end(), out);
+}
+// aggregation diagnostics of level l (the fine side of an aggregation step)
+void ora_agg_export(void* h, int l, double* tv, double* aff, uint8_t* ok, uint8_t* weak, uint8_t* hub,
+                    i32* state, double* scal) {
+  const AggDiag& D = ((Hier*)h)->lv[l].diag;
+  if (tv) std::copy(D.tv.begin(), D.tv.end(), tv);
+  if (aff) std::copy(D.aff.begin(), D.aff.end(), aff);
+  if (ok) std::copy(D.ok.begin(), D.ok.end(), ok);
+  if (weak) std::copy(D.weak.begin(), D.weak.end(), weak);
+  if (hub) std::copy(D.hub.begin(), D.hub.end(), hub);
+  if (state) std::copy(D.state.begin(), D.state.end(), state);
+  if (scal) { scal[0] = D.delta1; scal[1] = D.alpha1; scal[2] = D.alpha2; scal[3] = D.stage; }
+}
+void ora_perm1(void* h, i32* out) { const Hier* H = (Hier*)h; std::copy(H->perm1.begin(), H->perm1.end(), out); }
+i64 ora_coarsest_n(void* h) { return ((Hier*)h)->nL; }
+void ora_coarsest_solve(void* h, const double* b, double* x) { coarsest_solve(*(Hier*)h, b, x); }
+
+// info: cycles, rel_residual, acf, removed_mean
+int ora_solve(void* h, const double* b, double* x, int precision, int warm, double* info, double* hist) {
+  SolveInfo I;
+  int rc = precision == 0 ? solve64(*(Hier*)h, b, x, warm, I, hist) : solve32(*(Hier*)h, b, x, warm, I, hist);
+  if (info) { info[0] = (double)I.cycles; info[1] = I.rel; info[2] = I.acf; info[3] = I.removed_mean; }
+  return rc;
+}
+// One FP64 cycle on the level-1 (colour-ordered) system: x updated in place.
+void ora_cycle(void* h, const double* b_perm, double* x_perm) {
+  const Hier& H = *(Hier*)h;
+  Work<double> W;
+  init_work(H, W);
+  i64 n = H.lv[0].A.n;
+  std::copy(b_perm, b_perm + n, W.b[0].begin());
+  std::copy(x_perm, x_perm + n, W.x[0].begin());
+  cycle<double>(H, W);
+  std::copy(W.x[0].begin(), W.x[0].end(), x_perm);
+}
+// Solve-phase visit counts per level for one finest cycle.
+void ora_visit_counts(void* h, i64* counts) {
+  const Hier& H = *(Hier*)h;
+  size_t nl = H.lv.size();
+  vector<i64> cnt(nl, 0), bodies(nl, 0);
+  // replay the schedule without arithmetic
+  std::function<void(int, int)> vis;
+  vector<i64> ctr(nl, 0);
+  vis = [&](int l, int th) {
+    if (l == (int)nl - 1) { bodies[l] += 1; return; }
+    for (int i = 0; i < th; ++i) {
+      bodies[l] += 1;
+      if (H.lv[l + 1].type == L_ELIM) { vis(l + 1, 1); continue; }
+      i64 c = ctr[l]++;
+      double gl = H.lv[l].gamma_next;
+      vis(l + 1, (int)(std::ceil((double)(c + 1) * gl) - std::ceil((double)c * gl)));
+    }
+  };
+  vis(0, 1);
+  std::copy(bodies.begin(), bodies.end(), counts);
+}
+
+// Adjoint of the solve (x = A^+ b): lam = A^+ (g - mean g); grad_b = lam;
+// grad_w[e] = -(lam_u - lam_v)(x_u - x_v) for every input edge.
+int ora_adjoint(void* h, i64 m, const i32* eu, const i32* ev, const double* x, const double* g,
+                double* grad_b, double* grad_w, double* info) {
+  SolveInfo I;
+  int rc = solve64(*(Hier*)h, g, grad_b, 0, I, nullptr);
+  for (i64 e = 0; e < m; ++e)
+    grad_w[e] = -(grad_b[eu[e]] - grad_b[ev[e]]) * (x[eu[e]] - x[ev[e]]);
+  if (info) { info[0] = (double)I.cycles; info[1] = I.rel; info[2] = I.acf; info[3] = I.removed_mean; }
+  return rc;
+}
+
+}  // extern "C"
