@@ -1,0 +1,124 @@
+/* lamg.h -- C ABI of the MI355X Lean Algebraic Multigrid (LAMG) library.
+ *
+ * Solves the graph-Laplacian system A x = b, 1^T x = 0 for a zero-sum b
+ * (Livne & Brandt, Section 1, eq. linsys), where A is the Laplacian of a
+ * connected undirected graph with positive edge weights (Section 1, eq. lap).
+ * Setup (Section 4.1) builds a multilevel hierarchy that depends on A only;
+ * each solve (Section 4.2) runs multigrid cycles until
+ * ||b - A x||_2 <= tol ||b||_2.
+ *
+ * Pointers marked DEVICE must be device memory of the current HIP device
+ * (for example torch tensors); HOST pointers are ordinary host memory.
+ * All work is enqueued on options.stream (NULL = the null stream); every call
+ * returns only after its work on that stream is complete.
+ * No function throws or aborts across this interface; errors are returned as
+ * lamg_status codes.  A handle may be used by one stream at a time; distinct
+ * handles are independent.
+ */
+#ifndef LAMG_H
+#define LAMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lamg_hierarchy* lamg_handle;
+
+typedef enum {
+  LAMG_OK = 0,
+  LAMG_E_INVALID_ARG = 1,   /* n < 1, m < 0, an index out of range, a self-loop, NULL pointer */
+  LAMG_E_BAD_WEIGHT = 2,    /* a weight that is not finite and > 0 */
+  LAMG_E_NOT_CONNECTED = 3, /* the graph has more than one connected component (Section 1) */
+  LAMG_E_NOT_CONVERGED = 4, /* tol not reached in max_cycles; x holds the last iterate */
+  LAMG_E_BREAKDOWN = 5,     /* a non-finite residual (NaN/Inf in b, or overflow) */
+  LAMG_E_OUT_OF_MEMORY = 6,
+  LAMG_E_DEVICE = 7         /* a HIP runtime error */
+} lamg_status;
+
+typedef enum { LAMG_FP64 = 0, LAMG_FP32_REFINE = 1 } lamg_precision;
+/* Energy correction (Section 3.4.4-3.4.5): iterate recombination (eq. recomb)
+ * or a flat factor mu on the restricted residual (eq. galerkin2). */
+typedef enum { LAMG_EC_RECOMBINE = 0, LAMG_EC_FLAT_MU = 1 } lamg_energy_correction;
+
+typedef struct lamg_options {
+  uint32_t struct_size;     /* sizeof(lamg_options); set by lamg_options_default */
+  double gamma;             /* cycle index at fine levels, 1.5 (Section 4.1) */
+  int nu_pre, nu_post;      /* relaxation sweeps per level visit, 1 and 2 (eq. cycle_index) */
+  int tv_k_min, tv_k_max;   /* test vectors: 4 at the first aggregation, up to 10 (Section 4.1) */
+  int tv_sweeps;            /* relaxation sweeps per test vector, 3 (Section 4.1) */
+  double q_max;             /* energy-ratio threshold, 2.5 (Section 3.4.4) */
+  double mu;                /* flat energy correction factor, 4/3 (eq. optimal_mu) */
+  double hub_factor;        /* hub degree factor, 8 (Section 3.4.1 footnote) */
+  int elim_max_degree;      /* low-degree elimination bound, 4 (Section 3.2) */
+  int coarsest_max_n;       /* stop coarsening below this many nodes, 150 (Section 4.1) */
+  double weak_edge_ratio;   /* edge weak if w < ratio * max neighbouring weight, 1e-3 */
+  double elim_stop_frac;    /* stop eliminating when |F| < frac * n, 0.05 */
+  double stage1_quantile;   /* stage-1 affinity threshold quantile, 1.0 */
+  lamg_energy_correction ec;
+  lamg_precision precision;
+  double tol;               /* relative residual target, 1e-8 */
+  int max_cycles;           /* 100 */
+  int warm_start;           /* 1: x holds the initial guess on entry */
+  uint64_t seed;            /* colouring priorities and test vectors */
+  void* stream;             /* hipStream_t */
+} lamg_options;
+
+typedef struct lamg_info {
+  int32_t cycles;           /* cycles run (FP32 refinement: inner FP32 cycles) */
+  int32_t levels;
+  double rel_residual;      /* final ||b - A x|| / ||b|| in FP64 */
+  double acf;               /* (r_p / r_0)^(1/p), Section 5.1 */
+  double removed_mean;      /* mean of the input b, removed before solving */
+  double setup_ms, solve_ms;
+  int64_t bytes_moved;      /* algorithmic bytes of the solve (matrix + vector streams) */
+} lamg_info;
+
+/* Fill o with the paper's defaults (Sections 3-4). */
+void lamg_options_default(lamg_options* o);
+
+/* Build the hierarchy of the Laplacian of the graph given as a COO edge list.
+ *   n       number of nodes, >= 1
+ *   m       number of edge entries, >= 0
+ *   eu, ev  DEVICE int32[m] endpoints in [0, n), eu[e] != ev[e]; entries of the
+ *           same unordered pair are summed (Section 5.1 preprocessing)
+ *   w       DEVICE double[m] weights, finite and > 0
+ *   o       HOST options (NULL = defaults)
+ *   out     HOST; receives the handle, or NULL on error.
+ * The inputs are copied; the caller may free them on return.  The handle owns
+ * all hierarchy memory until lamg_free. */
+lamg_status lamg_setup(int64_t n, int64_t m, const int32_t* eu, const int32_t* ev, const double* w,
+                       const lamg_options* o, lamg_handle* out);
+
+/* Solve A x = b - mean(b) (Section 4.2 cycles, mean removed each cycle).
+ *   b     DEVICE double[n]; not modified
+ *   x     DEVICE double[n]; the zero-mean solution (warm_start: initial guess on entry)
+ *   info  HOST, may be NULL
+ * LAMG_E_NOT_CONVERGED still writes the last iterate and fills info. */
+lamg_status lamg_solve(lamg_handle h, const double* b, double* x, lamg_info* info);
+
+/* Batched solves.  For each i < count: handle hs[i] solves nrhs[i] right-hand
+ * sides stored DEVICE B[i] (n_i x nrhs[i], row-major, RHS index fastest) into
+ * DEVICE X[i] of the same shape.  count = 1 with nrhs = k is the multi-vector
+ * cycle on one hierarchy; count > 1 solves many graphs.  infos: HOST[count],
+ * may be NULL (multi-RHS: the worst column is reported).  All handles must live
+ * on the current device. */
+lamg_status lamg_solve_batch(int32_t count, const lamg_handle* hs, const int32_t* nrhs,
+                             const double* const* B, double* const* X, lamg_info* infos);
+
+/* Change solve-phase options of an existing hierarchy (precision, ec, tol,
+ * max_cycles, warm_start, stream); setup-phase fields are ignored. */
+lamg_status lamg_set_solve_options(lamg_handle h, const lamg_options* o);
+
+/* Release a hierarchy; NULL is a no-op. */
+void lamg_free(lamg_handle h);
+
+/* Static description of a status code. */
+const char* lamg_status_str(lamg_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LAMG_H */

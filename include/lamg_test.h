@@ -1,0 +1,77 @@
+/* lamg_test.h -- inspection and per-kernel entry points of the LAMG library,
+ * used by the parity tests.  Not part of the solver contract of lamg.h.
+ *
+ * Level l = 0 is the finest level.  Every level is stored in colour-major
+ * node order (colour class, then the previous node id), its CSR holds the
+ * positive off-diagonal weights w_uv with columns ascending, and the
+ * diagonal a_uu is the row sum of the weights (Section 1, eq. lap).
+ * Arrays marked HOST are written by copying from the device; DEVICE pointers
+ * are read/written on the GPU.  Functions return a lamg_status.
+ */
+#ifndef LAMG_TEST_H
+#define LAMG_TEST_H
+
+#include "lamg.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Number of levels of a hierarchy (>= 1). */
+int lamg_t_num_levels(lamg_handle h);
+
+/* dims[8] HOST: n, nnz (directed off-diagonal entries), type (0 finest,
+ * 1 produced by elimination, 2 produced by aggregation), colours, |F| of the
+ * elimination that produced it, test vectors K used when aggregating it,
+ * aggregation stage kept (1 or 2), number of rows longer than 64. */
+lamg_status lamg_t_level_dims(lamg_handle h, int l, int64_t* dims);
+
+/* Cycle index used for visits from level l to level l+1 (eq. cycle_index). */
+double lamg_t_level_gamma(lamg_handle h, int l);
+
+/* HOST copies of level l: row_ptr[n+1], col[nnz], val[nnz], diag[n],
+ * colour_ptr[ncol+1], perm[n] (node order: perm[new] = id before ordering).
+ * Any pointer may be NULL. */
+lamg_status lamg_t_level_export(lamg_handle h, int l, int32_t* row_ptr, int32_t* col, double* val, double* diag,
+                                int32_t* colour_ptr, int32_t* perm);
+
+/* HOST int32[n_{l-1}]: for l produced by aggregation the aggregate of each
+ * fine node; for elimination the coarse node of each fine node, -1 for F. */
+lamg_status lamg_t_transfer_export(lamg_handle h, int l, int32_t* out);
+
+/* Aggregation quantities of level l as the fine side (Sections 3.3-3.4):
+ * tv[n*K] relaxed test vectors, aff[nnz] affinities (eq. cuv), ok[nnz]
+ * energy-ratio admissibility (eq. qut), weak[nnz], hub[n], state[n] (0
+ * undecided, 1 seed, 2 associate, 3 dummy), scal[4] = delta_1, alpha_1,
+ * alpha_2, stage.  HOST arrays; any may be NULL. */
+lamg_status lamg_t_agg_export(lamg_handle h, int l, double* tv, double* aff, uint8_t* ok, uint8_t* weak,
+                              uint8_t* hub, int32_t* state, double* scal);
+
+/* One FP64 cycle (Section 4.2) on the finest level in colour-major order:
+ * DEVICE b_perm[n] (zero-sum) and x_perm[n] (updated in place). */
+lamg_status lamg_t_cycle(lamg_handle h, const double* b_perm, double* x_perm);
+
+/* Coarsest-level solve x = (A_L + (mean diag / n_L) 1 1^T)^-1 b, DEVICE [n_L]. */
+lamg_status lamg_t_coarsest_solve(lamg_handle h, const double* b, double* x);
+
+/* Standalone kernels on a DEVICE CSR whose nodes are already in colour-major
+ * order with colour classes HOST cptr[ncol+1]:
+ *   lamg_t_gs:       `sweeps` multicolour Gauss-Seidel sweeps (eq. gs), b may be NULL (b = 0);
+ *   lamg_t_gs32:     the same in FP32;
+ *   lamg_t_residual: r = b - A x. */
+lamg_status lamg_t_gs(int32_t n, const int32_t* rp, const int32_t* ci, const double* val, const double* diag,
+                      int32_t ncol, const int32_t* cptr, const double* b, double* x, int32_t sweeps, void* stream);
+lamg_status lamg_t_gs32(int32_t n, const int32_t* rp, const int32_t* ci, const float* val, const float* diag,
+                        int32_t ncol, const int32_t* cptr, const float* b, float* x, int32_t sweeps, void* stream);
+lamg_status lamg_t_residual(int32_t n, const int32_t* rp, const int32_t* ci, const double* val, const double* diag,
+                            const double* b, const double* x, double* r, void* stream);
+
+/* Greedy colouring by Jones-Plassmann rounds, priority (degree desc,
+ * hash(seed, level, id) asc, id asc) on a DEVICE CSR; DEVICE colour[n] out. */
+lamg_status lamg_t_colour(int32_t n, const int32_t* rp, const int32_t* ci, uint64_t seed, int32_t level,
+                          int32_t* colour, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LAMG_TEST_H */

@@ -111,7 +111,7 @@ struct AggDiag {  // aggregation-level setup quantities, kept for parity tests
   vector<uint8_t> hub;      // per node
   vector<i32> state;        // final per-node state before numbering
   double delta1 = 1, alpha1 = 0, alpha2 = -1;
-  int stage = 1;
+  int stage = 0;  // aggregation stage kept (0: this level was not aggregated)
 };
 
 struct Level {

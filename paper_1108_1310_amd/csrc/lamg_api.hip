@@ -1,0 +1,462 @@
+// Cycle driver (Section 4.2), FP64 and FP32-with-FP64-refinement solve loops,
+// batched solves and the C ABI.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "lamg_device.hpp"
+#include "lamg_internal.hpp"
+
+namespace lamg {
+
+namespace {
+template <class T> struct Prec;
+template <> struct Prec<double> {
+  static Vecs<double>& v(Level& L) { return L.v64; }
+  static const double* val(const Level& L) { return L.val; }
+  static const double* diag(const Level& L) { return L.diag; }
+};
+template <> struct Prec<float> {
+  static Vecs<float>& v(Level& L) { return L.v32; }
+  static const float* val(const Level& L) { return L.val32; }
+  static const float* diag(const Level& L) { return L.diag32; }
+};
+
+inline dim3 grid1(int64_t n, int b = 256) { return dim3((unsigned)std::max<int64_t>(1, (n + b - 1) / b)); }
+
+template <class T>
+__global__ void k_copy(int n, const T* __restrict__ a, T* __restrict__ b) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = a[i];
+}
+// b_perm[i] = b[perm[i]] - mean, mean taken from the reduction slot
+__global__ void k_gather_sub(int n, const int* __restrict__ perm, const double* __restrict__ b,
+                             const double* __restrict__ res, int slot, double* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = b[perm[i]] - (res ? res[slot] : 0.0);
+}
+__global__ void k_scatter(int n, const int* __restrict__ perm, const double* __restrict__ a, double* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[perm[i]] = a[i];
+}
+__global__ void k_sub_to_f32(int n, const double* __restrict__ r, const double* __restrict__ res, int slot,
+                             float* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (float)(r[i] - res[slot]);
+}
+__global__ void k_add_f32(int n, const float* __restrict__ e, double* __restrict__ x) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] += (double)e[i];
+}
+__global__ void k_mean_slot(int nblk, const double* part, double* res, int slot, double scale) {
+  if (threadIdx.x != 0) return;
+  double s = 0;
+  for (int b = 0; b < nblk; ++b) s += part[b * 8];
+  res[slot] = s * scale;
+}
+__global__ __launch_bounds__(256) void k_sum_d(int n, const double* __restrict__ x, double* part) {
+  __shared__ double sh[256];
+  double v = 0;
+  for (int u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += gridDim.x * blockDim.x) v += x[u];
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x * 8] = sh[0];
+}
+
+// mean of a device vector into reduction slot `slot` (device side only)
+void mean_to_slot(hipStream_t s, Hierarchy* H, const double* x, int n, int slot) {
+  const int nb = std::max(1, std::min(k::RED_BLOCKS, (n + 255) / 256));
+  hipLaunchKernelGGL(k_sum_d, dim3(nb), dim3(256), 0, s, n, x, H->red);
+  hipLaunchKernelGGL(k_mean_slot, dim3(1), dim3(64), 0, s, nb, H->red, H->red + k::RED_BLOCKS * 8, slot,
+                     1.0 / (double)n);
+}
+double* res_slots(Hierarchy* H) { return H->red + k::RED_BLOCKS * 8; }
+
+// ------------------------------------------------------------------- cycle
+template <class T>
+void visit(Hierarchy* H, int l, int th, std::vector<int64_t>& count);
+
+template <class T>
+void body(Hierarchy* H, int l, int sub, std::vector<int64_t>& count) {
+  hipStream_t s = H->s;
+  const int Lc = (int)H->lv.size() - 1;
+  Level& L = H->lv[l];
+  Vecs<T>& v = Prec<T>::v(L);
+  if (l == Lc) {
+    if constexpr (sizeof(T) == 8) coarsest_solve(s, H, (const double*)v.b, (double*)v.x);
+    else coarsest_solve32(s, H, (const float*)v.b, (float*)v.x);
+    return;
+  }
+  Level& C = H->lv[l + 1];
+  Vecs<T>& vc = Prec<T>::v(C);
+  const T* val = Prec<T>::val(L);
+  const T* dg = Prec<T>::diag(L);
+  if (C.type == LT_ELIM) {
+    residual<T>(s, L, val, dg, v.b, v.x, v.r);
+    restrict_elim<T>(s, L, C, val, dg, v.r, vc.b);
+    fill<T>(s, vc.x, T(0), C.n);
+    visit<T>(H, l + 1, 1, count);
+    interp_elim<T>(s, L, C, val, dg, v.r, vc.x, v.x);
+    return;
+  }
+  const bool rec = H->o.ec == LAMG_EC_RECOMBINE;
+  for (int i = 0; i < H->o.nu_pre; ++i) gs_sweep<T>(s, L, val, dg, v.b, v.x);
+  T* r = rec ? v.R[sub] : v.r;
+  residual<T>(s, L, val, dg, v.b, v.x, r);
+  if (rec) hipLaunchKernelGGL(k_copy<T>, grid1(L.n), dim3(256), 0, s, L.n, (const T*)v.x, v.X[sub]);
+  const T mu = rec ? T(1) : (T)H->o.mu;
+  restrict_agg<T>(s, C, r, vc.b, mu);
+  fill<T>(s, vc.x, T(0), C.n);
+  const int64_t c = count[l]++;
+  const double gl = L.gamma_next;
+  const int th = (int)(std::ceil((double)(c + 1) * gl) - std::ceil((double)c * gl));
+  visit<T>(H, l + 1, th, count);
+  interp_agg<T>(s, C, L.n, vc.x, v.x);
+  for (int i = 0; i < H->o.nu_post; ++i) gs_sweep<T>(s, L, val, dg, v.b, v.x);
+}
+
+template <class T>
+void visit(Hierarchy* H, int l, int th, std::vector<int64_t>& count) {
+  const int Lc = (int)H->lv.size() - 1;
+  if (l == Lc) { body<T>(H, l, 0, count); return; }
+  for (int i = 0; i < th; ++i) body<T>(H, l, i, count);
+  if (H->o.ec == LAMG_EC_RECOMBINE && H->lv[l + 1].type == LT_AGG)
+    recombine<T>(H->s, H, H->lv[l], Prec<T>::v(H->lv[l]), th);
+}
+}  // namespace
+
+template <class T>
+void cycle(Hierarchy* H) {
+  std::vector<int64_t> count(H->lv.size(), 0);
+  visit<T>(H, 0, 1, count);
+  Level& L = H->lv[0];
+  subtract_mean<T>(H->s, H, Prec<T>::v(L).x, L.n);
+  LAMG_HIP(hipGetLastError());
+}
+template void cycle<double>(Hierarchy*);
+template void cycle<float>(Hierarchy*);
+
+// Algorithmic bytes of one cycle (matrix and vector streams per pass).
+int64_t cycle_bytes(const Hierarchy* H, int prec) {
+  const int sv = prec == LAMG_FP64 ? 8 : 4, sx = sv;
+  const size_t nl = H->lv.size();
+  std::vector<int64_t> bodies(nl, 0), ctr(nl, 0), visits(nl, 0);
+  std::vector<int> ths;
+  // replay the schedule
+  std::vector<std::pair<int, int>> stack;
+  struct F { static void run(const Hierarchy* H, int l, int th, std::vector<int64_t>& b, std::vector<int64_t>& c,
+                             std::vector<int64_t>& vis, std::vector<int64_t>& recth) {
+    const int Lc = (int)H->lv.size() - 1;
+    vis[l] += 1;
+    if (l == Lc) { b[l] += 1; return; }
+    for (int i = 0; i < th; ++i) {
+      b[l] += 1;
+      if (H->lv[l + 1].type == LT_ELIM) { run(H, l + 1, 1, b, c, vis, recth); continue; }
+      const int64_t k = c[l]++;
+      const double g = H->lv[l].gamma_next;
+      run(H, l + 1, (int)(std::ceil((double)(k + 1) * g) - std::ceil((double)k * g)), b, c, vis, recth);
+    }
+    if (H->lv[l + 1].type == LT_AGG) recth[l] += th;
+  } };
+  std::vector<int64_t> recth(nl, 0);
+  F::run(H, 0, 1, bodies, ctr, visits, recth);
+  int64_t tot = 0;
+  for (size_t l = 0; l < nl; ++l) {
+    const Level& L = H->lv[l];
+    const int64_t n = L.n;
+    const int64_t M = (int64_t)L.nnz * (4 + sv) + n * (4 + sv);
+    if (l + 1 == nl) {
+      tot += bodies[l] * ((int64_t)H->nL * H->nL * 8 + 2 * n * sx);
+      continue;
+    }
+    const Level& C = H->lv[l + 1];
+    int64_t body;
+    if (C.type == LT_ELIM) {
+      body = (M + 3 * n * sx)                               // residual
+             + (M + 2 * n * sx)                             // restriction (rows of C nodes)
+             + (M + 3 * n * sx);                            // exact correction
+    } else {
+      const int sweeps = H->o.nu_pre + H->o.nu_post;
+      body = sweeps * (M + 3 * n * sx) + (M + 3 * n * sx)   // relaxation, residual
+             + n * (sx + 4) + (int64_t)C.n * (sx + 4)         // restriction
+             + n * (4 + 2 * sx) + (int64_t)C.n * sx;          // interpolation
+      if (H->o.ec == LAMG_EC_RECOMBINE) body += 2 * n * sx;   // saved iterate
+    }
+    tot += bodies[l] * body;
+    if (H->o.ec == LAMG_EC_RECOMBINE && C.type == LT_AGG) {
+      // per visit: final residual, Gram (th+1 vectors), update (th+2 vectors)
+      const int64_t th = visits[l] ? (recth[l] + visits[l] - 1) / visits[l] : 1;
+      tot += visits[l] * ((M + 3 * n * sx) + (th + 1) * n * sx + (th + 2) * n * sx);
+    }
+  }
+  tot += 2 * (int64_t)H->lv[0].n * sx;  // mean removal
+  return tot;
+}
+
+}  // namespace lamg
+
+// ====================================================================== C ABI
+using namespace lamg;
+
+
+extern "C" {
+
+void lamg_options_default(lamg_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->struct_size = sizeof(lamg_options);
+  o->gamma = 1.5;
+  o->nu_pre = 1;
+  o->nu_post = 2;
+  o->tv_k_min = 4;
+  o->tv_k_max = 10;
+  o->tv_sweeps = 3;
+  o->q_max = 2.5;
+  o->mu = 4.0 / 3.0;
+  o->hub_factor = 8.0;
+  o->elim_max_degree = 4;
+  o->coarsest_max_n = 150;
+  o->weak_edge_ratio = 1e-3;
+  o->elim_stop_frac = 0.05;
+  o->stage1_quantile = 1.0;
+  o->ec = LAMG_EC_RECOMBINE;
+  o->precision = LAMG_FP64;
+  o->tol = 1e-8;
+  o->max_cycles = 100;
+  o->warm_start = 0;
+  o->seed = 0;
+  o->stream = nullptr;
+}
+
+const char* lamg_status_str(lamg_status s) {
+  switch (s) {
+    case LAMG_OK: return "ok";
+    case LAMG_E_INVALID_ARG: return "invalid argument";
+    case LAMG_E_BAD_WEIGHT: return "edge weight not finite and positive";
+    case LAMG_E_NOT_CONNECTED: return "graph is not connected";
+    case LAMG_E_NOT_CONVERGED: return "tolerance not reached within max_cycles";
+    case LAMG_E_BREAKDOWN: return "non-finite residual";
+    case LAMG_E_OUT_OF_MEMORY: return "out of device memory";
+    case LAMG_E_DEVICE: return "HIP runtime error";
+  }
+  return "unknown status";
+}
+
+static bool opts_ok(const lamg_options& o) {
+  return o.gamma >= 1.0 && o.gamma <= 2.0 && o.nu_pre >= 0 && o.nu_post >= 0 && o.tv_k_min >= 1 &&
+         o.tv_k_max >= o.tv_k_min && o.tv_k_max <= 10 && o.tv_sweeps >= 0 && o.q_max > 1.0 && o.coarsest_max_n >= 2 &&
+         o.elim_max_degree >= 0 && o.stage1_quantile >= 0.0 && o.stage1_quantile <= 1.0 && o.tol >= 0 &&
+         o.max_cycles >= 0;
+}
+
+lamg_status lamg_setup(int64_t n, int64_t m, const int32_t* eu, const int32_t* ev, const double* w,
+                       const lamg_options* o, lamg_handle* out) {
+  if (!out) return LAMG_E_INVALID_ARG;
+  *out = nullptr;
+  if (n < 1 || m < 0 || n > (int64_t)0x7fffffff / 2 || m > (int64_t)0x3fffffff) return LAMG_E_INVALID_ARG;
+  if (m > 0 && (!eu || !ev || !w)) return LAMG_E_INVALID_ARG;
+  lamg_options opt;
+  lamg_options_default(&opt);
+  if (o) {
+    if (o->struct_size != sizeof(lamg_options)) return LAMG_E_INVALID_ARG;
+    opt = *o;
+  }
+  if (!opts_ok(opt)) return LAMG_E_INVALID_ARG;
+  lamg_hierarchy* h = new lamg_hierarchy;
+  Hierarchy* H = &h->H;
+  H->o = opt;
+  H->s = (hipStream_t)opt.stream;
+  H->n = (int)n;
+  H->m = m;
+  auto t0 = std::chrono::steady_clock::now();
+  try {
+    lamg_status st = build_finest(H, n, m, eu, ev, w);
+    if (st != LAMG_OK) { lamg_free(h); return st; }
+    colour_and_order(H, H->lv[0], 0, nullptr);
+    int nagg = 0;
+    while (H->lv.back().n >= opt.coarsest_max_n && (int)H->lv.size() < 60) {
+      const int l = (int)H->lv.size() - 1;
+      if (try_eliminate(H, l)) continue;
+      if (!aggregate(H, l, nagg)) break;
+      ++nagg;
+    }
+    if (H->lv.back().n > 8192) { lamg_free(h); return LAMG_E_OUT_OF_MEMORY; }
+    finish_levels(H);
+    H->bsave = H->lv[0].v64.b;
+    H->x64 = H->lv[0].v64.x;
+    H->r64 = dnew<double>(H, n);
+    H->colb = dnew<double>(H, n);
+    H->colx = dnew<double>(H, n);
+    H->bytes_per_cycle = cycle_bytes(H, LAMG_FP64);
+    LAMG_HIP(hipStreamSynchronize(H->s));
+  } catch (const DevError& e) {
+    lamg_free(h);
+    return e.e == hipErrorOutOfMemory ? LAMG_E_OUT_OF_MEMORY : LAMG_E_DEVICE;
+  }
+  H->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  *out = h;
+  return LAMG_OK;
+}
+
+lamg_status lamg_set_solve_options(lamg_handle h, const lamg_options* o) {
+  if (!h || !o || o->struct_size != sizeof(lamg_options)) return LAMG_E_INVALID_ARG;
+  if (o->tol < 0 || o->max_cycles < 0 || (o->precision != LAMG_FP64 && o->precision != LAMG_FP32_REFINE) ||
+      (o->ec != LAMG_EC_RECOMBINE && o->ec != LAMG_EC_FLAT_MU))
+    return LAMG_E_INVALID_ARG;
+  Hierarchy* H = &h->H;
+  H->o.precision = o->precision;
+  H->o.ec = o->ec;
+  H->o.mu = o->mu;
+  H->o.tol = o->tol;
+  H->o.max_cycles = o->max_cycles;
+  H->o.warm_start = o->warm_start;
+  H->o.stream = o->stream;
+  H->o.nu_pre = o->nu_pre;
+  H->o.nu_post = o->nu_post;
+  H->s = (hipStream_t)o->stream;
+  return LAMG_OK;
+}
+
+// One solve on a hierarchy; b and x are device vectors in input node order.
+static lamg_status solve_one(Hierarchy* H, const double* b, double* x, lamg_info* info) {
+  hipStream_t s = H->s;
+  Level& L = H->lv[0];
+  const int n = L.n;
+  auto t0 = std::chrono::steady_clock::now();
+  double* rs = res_slots(H);
+  // b <- b - mean(b), in colour order
+  mean_to_slot(s, H, b, n, 6);
+  hipLaunchKernelGGL(k_gather_sub, grid1(n), dim3(256), 0, s, n, L.perm, b, rs, 6, H->bsave);
+  double* hr = H->hred;
+  LAMG_HIP(hipMemcpyAsync(hr + 6, rs + 6, sizeof(double), hipMemcpyDeviceToHost, s));
+  if (H->o.warm_start) hipLaunchKernelGGL(k_gather_sub, grid1(n), dim3(256), 0, s, n, L.perm, x, nullptr, 0, H->x64);
+  else fill<double>(s, H->x64, 0.0, n);
+  norm2_async(s, H, H->bsave, n, hr + 0);
+  residual<double>(s, L, L.val, L.diag, H->bsave, H->x64, H->r64);
+  norm2_async(s, H, H->r64, n, hr + 1);
+  LAMG_HIP(hipStreamSynchronize(s));
+  const double removed = hr[6];
+  const double nb = std::sqrt(hr[0]);
+  const double r0 = std::sqrt(hr[1]);
+  double rk = r0;
+  int it = 0;
+  const bool fp32 = H->o.precision == LAMG_FP32_REFINE;
+  if (nb > 0) {
+    Vecs<float>& v32 = L.v32;
+    while (rk > H->o.tol * nb && it < H->o.max_cycles && std::isfinite(rk)) {
+      if (!fp32) {
+        cycle<double>(H);  // level-1 vectors alias bsave / x64
+      } else {
+        // inner FP32 cycle on the projected FP64 residual
+        mean_to_slot(s, H, H->r64, n, 7);
+        hipLaunchKernelGGL(k_sub_to_f32, grid1(n), dim3(256), 0, s, n, (const double*)H->r64, rs, 7, v32.b);
+        fill<float>(s, v32.x, 0.0f, n);
+        cycle<float>(H);
+        hipLaunchKernelGGL(k_add_f32, grid1(n), dim3(256), 0, s, n, (const float*)v32.x, H->x64);
+        subtract_mean<double>(s, H, H->x64, n);
+      }
+      residual<double>(s, L, L.val, L.diag, H->bsave, H->x64, H->r64);
+      norm2_async(s, H, H->r64, n, hr + 2);
+      LAMG_HIP(hipStreamSynchronize(s));
+      rk = std::sqrt(hr[2]);
+      ++it;
+    }
+  }
+  hipLaunchKernelGGL(k_scatter, grid1(n), dim3(256), 0, s, n, L.perm, (const double*)H->x64, x);
+  LAMG_HIP(hipStreamSynchronize(s));
+  const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (info) {
+    info->cycles = it;
+    info->levels = (int)H->lv.size();
+    info->rel_residual = nb > 0 ? rk / nb : 0.0;
+    info->acf = it > 0 && r0 > 0 ? std::pow(rk / r0, 1.0 / it) : 0.0;
+    info->removed_mean = removed;
+    info->setup_ms = H->setup_ms;
+    info->solve_ms = ms;
+    info->bytes_moved = (int64_t)it * cycle_bytes(H, H->o.precision);
+  }
+  if (!std::isfinite(rk)) return LAMG_E_BREAKDOWN;
+  if (nb > 0 && rk > H->o.tol * nb) return LAMG_E_NOT_CONVERGED;
+  return LAMG_OK;
+}
+
+lamg_status lamg_solve(lamg_handle h, const double* b, double* x, lamg_info* info) {
+  if (!h || !b || !x) return LAMG_E_INVALID_ARG;
+  try {
+    return solve_one(&h->H, b, x, info);
+  } catch (const DevError& e) {
+    return e.e == hipErrorOutOfMemory ? LAMG_E_OUT_OF_MEMORY : LAMG_E_DEVICE;
+  }
+}
+
+namespace {
+__global__ void k_col_get(int n, int k, int j, const double* __restrict__ B, double* __restrict__ b) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = B[(size_t)i * k + j];
+}
+__global__ void k_col_put(int n, int k, int j, const double* __restrict__ x, double* __restrict__ X) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) X[(size_t)i * k + j] = x[i];
+}
+}  // namespace
+
+lamg_status lamg_solve_batch(int32_t count, const lamg_handle* hs, const int32_t* nrhs, const double* const* B,
+                             double* const* X, lamg_info* infos) {
+  if (count < 0 || (count > 0 && (!hs || !nrhs || !B || !X))) return LAMG_E_INVALID_ARG;
+  lamg_status worst = LAMG_OK;
+  for (int i = 0; i < count; ++i) {
+    if (!hs[i] || nrhs[i] < 1 || !B[i] || !X[i]) return LAMG_E_INVALID_ARG;
+  }
+  try {
+    for (int i = 0; i < count; ++i) {
+      Hierarchy* H = &hs[i]->H;
+      const int n = H->lv[0].n, k = nrhs[i];
+      lamg_info acc{};
+      if (k == 1) {
+        lamg_status st = solve_one(H, B[i], X[i], &acc);
+        if (st != LAMG_OK && worst == LAMG_OK) worst = st;
+      } else {
+        double* b1 = H->colb;
+        double* x1 = H->colx;
+        for (int j = 0; j < k; ++j) {
+          hipLaunchKernelGGL(k_col_get, grid1(n), dim3(256), 0, H->s, n, k, j, B[i], b1);
+          if (H->o.warm_start) hipLaunchKernelGGL(k_col_get, grid1(n), dim3(256), 0, H->s, n, k, j, (const double*)X[i], x1);
+          lamg_info ci{};
+          lamg_status st = solve_one(H, b1, x1, &ci);
+          if (st != LAMG_OK && worst == LAMG_OK) worst = st;
+          hipLaunchKernelGGL(k_col_put, grid1(n), dim3(256), 0, H->s, n, k, j, (const double*)x1, X[i]);
+          acc.cycles = std::max(acc.cycles, ci.cycles);
+          acc.rel_residual = std::max(acc.rel_residual, ci.rel_residual);
+          acc.acf = std::max(acc.acf, ci.acf);
+          acc.solve_ms += ci.solve_ms;
+          acc.bytes_moved += ci.bytes_moved;
+          acc.levels = ci.levels;
+          acc.setup_ms = ci.setup_ms;
+        }
+        LAMG_HIP(hipStreamSynchronize(H->s));
+      }
+      if (infos) infos[i] = acc;
+    }
+  } catch (const DevError& e) {
+    return e.e == hipErrorOutOfMemory ? LAMG_E_OUT_OF_MEMORY : LAMG_E_DEVICE;
+  }
+  return worst;
+}
+
+void lamg_free(lamg_handle h) {
+  if (!h) return;
+  Hierarchy* H = &h->H;
+  if (H->s) (void)hipStreamSynchronize(H->s);
+  else (void)hipDeviceSynchronize();
+  for (void* p : H->owned) (void)hipFree(p);
+  if (H->hred) (void)hipHostFree(H->hred);
+  delete h;
+}
+
+}  // extern "C"

@@ -1,0 +1,163 @@
+// Internal declarations of the LAMG HIP library (gfx950).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <vector>
+
+#include "../../include/lamg.h"
+
+namespace lamg {
+
+// ----------------------------------------------------------------- checks
+struct DevError {
+  hipError_t e;
+};
+#define LAMG_HIP(call)                                   \
+  do {                                                   \
+    hipError_t e_ = (call);                              \
+    if (e_ != hipSuccess) throw ::lamg::DevError{e_};    \
+  } while (0)
+
+enum LevelType { LT_FINEST = 0, LT_ELIM = 1, LT_AGG = 2 };
+enum NodeState { ST_UNDECIDED = 0, ST_SEED = 1, ST_ASSOC = 2, ST_DUMMY = 3 };
+
+// Streams of the counter hash: colouring priorities and test-vector draws.
+constexpr uint64_t STREAM_COLOUR = 7, STREAM_TV = 3;
+
+// Rows longer than this are reduced with 64 strided partial sums and an xor
+// butterfly; shorter rows are summed sequentially in column order.
+constexpr int SHORT_ROW = 64;
+
+// Relaxation tile: a "stream" block owns up to TILE_ROWS consecutive short
+// rows whose entries fit in TILE_NNZ products staged in LDS; a "long" block
+// owns up to LONG_PER_BLOCK long rows, one wavefront each.
+constexpr int RELAX_THREADS = 256;
+constexpr int TILE_ROWS = 256;
+constexpr int TILE_NNZ = 2048;
+constexpr int LONG_PER_BLOCK = RELAX_THREADS / 64;
+
+// Relaxation work list of one colour class (or of all rows).
+struct Tiles {
+  int nstream = 0, nlong_blocks = 0;
+  int* stream = nullptr;   // [nstream + 1] row boundaries of stream blocks (device)
+  int* longrows = nullptr; // [nlong] long row ids (device)
+  int nlong = 0;
+};
+
+template <class T>
+struct Vecs {
+  T *x = nullptr, *b = nullptr, *r = nullptr;
+  T *X[2] = {nullptr, nullptr}, *R[2] = {nullptr, nullptr};
+};
+
+struct Level {
+  int n = 0, nnz = 0, type = LT_FINEST, ncol = 0;
+  std::vector<int> cptr;            // host copy, colour class boundaries
+  int *rp = nullptr, *ci = nullptr; // CSR of off-diagonal weights (positive)
+  double *val = nullptr, *diag = nullptr;
+  float *val32 = nullptr, *diag32 = nullptr;
+  int* perm = nullptr;              // node order: perm[new] = natural id
+  std::vector<Tiles> tiles;         // per colour
+  Tiles all;                        // every row (residual)
+  // transfer from the previous level into this one
+  int* agg = nullptr;               // AGG: fine node -> this level's node
+  int *agg_ptr = nullptr, *members = nullptr;  // P^T as CSR (aggregate members ascending)
+  int* cidx = nullptr;              // ELIM: fine node -> this level's node or -1
+  int* cfine = nullptr;             // ELIM: this level's node -> fine node
+  int nF = 0;
+  double gamma_next = 1.0;          // cycle index for visits from this level to the next
+  // aggregation diagnostics (this level as the fine side), kept for parity tests
+  int K = 0, stage = 0;
+  double delta1 = 1, alpha1 = 0, alpha2 = -1;
+  double* tv = nullptr;
+  double* aff = nullptr;
+  uint8_t *ok = nullptr, *weak = nullptr, *hub = nullptr;
+  int* state = nullptr;
+  Vecs<double> v64;
+  Vecs<float> v32;
+};
+
+struct Hierarchy {
+  lamg_options o;
+  hipStream_t s = nullptr;
+  int n = 0;
+  int64_t m = 0;
+  std::vector<Level> lv;
+  double* cinv = nullptr;  // dense inverse of the augmented coarsest matrix (n_L x n_L)
+  int nL = 0;
+  double* red = nullptr;   // reduction scratch (partials + results)
+  double* hred = nullptr;  // pinned host mirror of reduction results
+  double* bsave = nullptr; // level-1 rhs (FP64, colour order)
+  double* x64 = nullptr;   // level-1 iterate (FP64, colour order)
+  double* r64 = nullptr;   // level-1 outer residual
+  double *colb = nullptr, *colx = nullptr;  // column staging of multi-RHS solves
+  std::vector<void*> owned;  // every device allocation, freed with the handle
+  double setup_ms = 0;
+  int64_t bytes_per_cycle = 0;
+};
+
+// ------------------------------------------------------------- allocation
+void* dalloc(Hierarchy* H, size_t bytes);
+template <class T>
+T* dnew(Hierarchy* H, size_t count) { return (T*)dalloc(H, count * sizeof(T) + 16); }
+
+// ----------------------------------------------------------- kernel entry
+// (declared here, defined in the .hip sources)
+namespace k {
+// reductions: fixed grid and tree, results deterministic run to run
+constexpr int RED_BLOCKS = 512, RED_THREADS = 256;
+}
+
+void build_tiles(Hierarchy* H, Level& L);
+// Relaxation and residual (FP64 / FP32), k vectors row-major for the multi-vector form.
+template <class T>
+void gs_colour(hipStream_t s, const Level& L, int c, const T* val, const T* diag, const T* b, T* x);
+template <class T>
+void gs_sweep(hipStream_t s, const Level& L, const T* val, const T* diag, const T* b, T* x);
+template <class T>
+void residual(hipStream_t s, const Level& L, const T* val, const T* diag, const T* b, const T* x, T* r);
+void gs_multi_sweep(hipStream_t s, const Level& L, const double* b, double* X, int K);
+
+// transfers
+template <class T>
+void restrict_agg(hipStream_t s, const Level& C, const T* r, T* bc, T mu);
+template <class T>
+void interp_agg(hipStream_t s, const Level& C, int nfine, const T* e, T* x);
+template <class T>
+void restrict_elim(hipStream_t s, const Level& F, const Level& C, const T* val, const T* diag, const T* r, T* bc);
+template <class T>
+void interp_elim(hipStream_t s, const Level& F, const Level& C, const T* val, const T* diag, const T* r, const T* e, T* x);
+template <class T>
+void fill(hipStream_t s, T* p, T v, int n);
+
+// recombination / mean / norms (partials in H->red)
+template <class T>
+void recombine(hipStream_t s, Hierarchy* H, const Level& L, Vecs<T>& v, int th);
+template <class T>
+void subtract_mean(hipStream_t s, Hierarchy* H, T* x, int n);
+void norm2_async(hipStream_t s, Hierarchy* H, const double* r, int n, double* dst_host);
+void coarsest_solve(hipStream_t s, Hierarchy* H, const double* b, double* x);
+void coarsest_solve32(hipStream_t s, Hierarchy* H, const float* b, float* x);
+void coarsest_factor(Hierarchy* H, const Level& L);
+
+// setup
+lamg_status build_finest(Hierarchy* H, int64_t n, int64_t m, const int32_t* eu, const int32_t* ev, const double* w);
+void colour_and_order(Hierarchy* H, Level& L, int level, std::vector<int>* inv_host_unused);
+int colour_greedy(hipStream_t s, int n, const int* rp, const int* ci, uint64_t seed, int level, int* col);
+bool try_eliminate(Hierarchy* H, int l);
+bool aggregate(Hierarchy* H, int l, int agg_index);
+void finish_levels(Hierarchy* H);
+
+// solve
+int64_t cycle_bytes(const Hierarchy* H, int prec);
+template <class T>
+void cycle(Hierarchy* H);
+
+}  // namespace lamg
+
+// The opaque handle of the C ABI.
+struct lamg_hierarchy {
+  lamg::Hierarchy H;
+};

@@ -1,0 +1,996 @@
+// Setup phase on the GPU (Section 4.1): Laplacian assembly, greedy colouring
+// by Jones-Plassmann rounds, colour-major renumbering, low-degree elimination
+// (Section 3.2), test vectors / affinity / energy-ratio test / hubs / weak
+// edges (Sections 3.3-3.4), staged aggregation, and Galerkin coarsening.
+// Every integer decision and every value that feeds one is computed in the
+// same floating-point order as the CPU reference: short rows left to right,
+// long rows as 64 strided partial sums and an xor butterfly, no contraction.
+#include <cstring>
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_scan.hpp>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "lamg_device.hpp"
+#include "lamg_internal.hpp"
+
+namespace lamg {
+
+void* dalloc(Hierarchy* H, size_t bytes) {
+  void* p = nullptr;
+  if (hipMalloc(&p, std::max<size_t>(bytes, 16)) != hipSuccess) throw DevError{hipErrorOutOfMemory};
+  H->owned.push_back(p);
+  return p;
+}
+
+namespace {
+
+// Temporary device buffers of one setup step, released at scope exit.
+struct Tmp {
+  std::vector<void*> ps;
+  ~Tmp() { for (void* p : ps) (void)hipFree(p); }
+  template <class T>
+  T* get(size_t count) {
+    void* p = nullptr;
+    if (hipMalloc(&p, std::max<size_t>(count * sizeof(T), 16)) != hipSuccess) throw DevError{hipErrorOutOfMemory};
+    ps.push_back(p);
+    return (T*)p;
+  }
+};
+
+inline dim3 grid1(int64_t n, int b = 256) { return dim3((unsigned)std::max<int64_t>(1, (n + b - 1) / b)); }
+
+unsigned bits_for(uint64_t maxkey) {
+  unsigned b = 1;
+  while (b < 64 && (maxkey >> b) != 0) ++b;
+  return b;
+}
+
+template <class K, class V>
+void sort_pairs(hipStream_t s, Tmp& tmp, const K* kin, K* kout, const V* vin, V* vout, int64_t n, unsigned endbit) {
+  if (n == 0) return;
+  size_t bytes = 0;
+  LAMG_HIP(rocprim::radix_sort_pairs(nullptr, bytes, kin, kout, vin, vout, (size_t)n, 0u, endbit, s));
+  void* t = tmp.get<char>(bytes);
+  LAMG_HIP(rocprim::radix_sort_pairs(t, bytes, kin, kout, vin, vout, (size_t)n, 0u, endbit, s));
+}
+template <class K>
+void sort_keys_double(hipStream_t s, Tmp& tmp, const K* kin, K* kout, int64_t n) {
+  size_t bytes = 0;
+  LAMG_HIP(rocprim::radix_sort_keys(nullptr, bytes, kin, kout, (size_t)n, 0u, (unsigned)(8 * sizeof(K)), s));
+  void* t = tmp.get<char>(bytes);
+  LAMG_HIP(rocprim::radix_sort_keys(t, bytes, kin, kout, (size_t)n, 0u, (unsigned)(8 * sizeof(K)), s));
+}
+// exclusive scan of n ints; out has n+1 entries (out[n] = total)
+void excl_scan(hipStream_t s, Tmp& tmp, const int* in, int* out, int64_t n) {
+  size_t bytes = 0;
+  LAMG_HIP(rocprim::exclusive_scan(nullptr, bytes, in, out, 0, (size_t)n + 1, rocprim::plus<int>(), s));
+  void* t = tmp.get<char>(bytes);
+  LAMG_HIP(rocprim::exclusive_scan(t, bytes, in, out, 0, (size_t)n + 1, rocprim::plus<int>(), s));
+}
+template <class T>
+T to_host(hipStream_t s, const T* p) {
+  T v;
+  LAMG_HIP(hipMemcpyAsync(&v, p, sizeof(T), hipMemcpyDeviceToHost, s));
+  LAMG_HIP(hipStreamSynchronize(s));
+  return v;
+}
+template <class T>
+std::vector<T> to_host_vec(hipStream_t s, const T* p, size_t n) {
+  std::vector<T> v(n);
+  if (n) {
+    LAMG_HIP(hipMemcpyAsync(v.data(), p, n * sizeof(T), hipMemcpyDeviceToHost, s));
+    LAMG_HIP(hipStreamSynchronize(s));
+  }
+  return v;
+}
+
+// ------------------------------------------------------------- primitives
+__global__ void k_iota(int* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = i;
+}
+__global__ void k_zero_i(int* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+// mark run heads of a sorted key array
+__global__ void k_heads(const uint64_t* __restrict__ key, int64_t n, int* __restrict__ head) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) head[i] = (i == 0 || key[i] != key[i - 1]) ? 1 : 0;
+}
+// sum each run of equal keys sequentially in list order
+__global__ void k_run_sums(const uint64_t* __restrict__ key, const double* __restrict__ v, int64_t n,
+                           const int* __restrict__ head, const int* __restrict__ pos, uint64_t* __restrict__ ukey,
+                           double* __restrict__ uval) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || !head[i]) return;
+  const uint64_t k0 = key[i];
+  double s = v[i];
+  for (int64_t j = i + 1; j < n && key[j] == k0; ++j) s += v[j];
+  ukey[pos[i]] = k0;
+  uval[pos[i]] = s;
+}
+// unique (row, col) keys -> CSR columns; row counts by atomics
+__global__ void k_split_keys(const uint64_t* __restrict__ ukey, int64_t nu, uint64_t ncols, int* __restrict__ ci,
+                             int* __restrict__ cnt) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nu) return;
+  const uint64_t k = ukey[i];
+  ci[i] = (int)(k % ncols);
+  atomicAdd(&cnt[k / ncols], 1);
+}
+
+// Row sums in the fixed order (diagonal = sum of the row's weights).
+__global__ void k_rowsum_short(int n, const int* __restrict__ rp, const double* __restrict__ val,
+                               double* __restrict__ out) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= n) return;
+  const int p0 = rp[u], len = rp[u + 1] - p0;
+  if (len > SHORT_ROW) return;
+  out[u] = dev::row_sum_seq<double>(len, [&](int t) { return val[p0 + t]; });
+}
+__global__ void k_rowsum_long(const int* __restrict__ rows, int nrows, const int* __restrict__ rp,
+                              const double* __restrict__ val, double* __restrict__ out) {
+  const int idx = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, lane = threadIdx.x & 63;
+  if (idx >= nrows) return;
+  const int u = rows[idx];
+  const int p0 = rp[u], len = rp[u + 1] - p0;
+  const double s = dev::row_sum_wave<double>(len, lane, [&](int t) { return val[p0 + t]; });
+  if (lane == 0) out[u] = s;
+}
+__global__ void k_collect_long(int n, const int* __restrict__ rp, int* __restrict__ list, int* __restrict__ cnt) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u < n && rp[u + 1] - rp[u] > SHORT_ROW) list[atomicAdd(cnt, 1)] = u;
+}
+
+// Long rows of a CSR, ascending (the order does not affect any result).
+std::vector<int> long_rows_host(const std::vector<int>& rph, int n) {
+  std::vector<int> v;
+  for (int u = 0; u < n; ++u)
+    if (rph[u + 1] - rph[u] > SHORT_ROW) v.push_back(u);
+  return v;
+}
+
+void row_sums(hipStream_t s, Tmp& tmp, int n, const int* rp, const double* val, double* out) {
+  hipLaunchKernelGGL(k_rowsum_short, grid1(n), dim3(256), 0, s, n, rp, val, out);
+  std::vector<int> rph = to_host_vec(s, rp, (size_t)n + 1);
+  std::vector<int> lr = long_rows_host(rph, n);
+  if (!lr.empty()) {
+    int* d = tmp.get<int>(lr.size());
+    LAMG_HIP(hipMemcpyAsync(d, lr.data(), lr.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_rowsum_long, grid1((int64_t)lr.size() * 64), dim3(256), 0, s, d, (int)lr.size(), rp, val, out);
+  }
+  LAMG_HIP(hipGetLastError());
+}
+
+// Merge (row, col, value) triples given as keys row*ncols + col: stable sort,
+// sum runs in list order, build the CSR and its diagonal.
+void merge_triples(Hierarchy* H, Tmp& tmp, Level& C, int nrows, uint64_t* keys, double* vals, int64_t nt) {
+  hipStream_t s = H->s;
+  uint64_t* ks = tmp.get<uint64_t>(nt);
+  double* vs = tmp.get<double>(nt);
+  const uint64_t maxkey = (uint64_t)nrows * (uint64_t)nrows;
+  sort_pairs(s, tmp, keys, ks, vals, vs, nt, bits_for(maxkey));
+  int* head = tmp.get<int>(nt + 1);
+  int* pos = tmp.get<int>(nt + 1);
+  hipLaunchKernelGGL(k_heads, grid1(nt), dim3(256), 0, s, ks, nt, head);
+  excl_scan(s, tmp, head, pos, nt);
+  const int nu = nt ? to_host(s, pos + nt) : 0;
+  uint64_t* uk = tmp.get<uint64_t>(nu);
+  C.n = nrows;
+  C.nnz = nu;
+  C.val = dnew<double>(H, nu);
+  hipLaunchKernelGGL(k_run_sums, grid1(nt), dim3(256), 0, s, ks, vs, nt, head, pos, uk, C.val);
+  C.ci = dnew<int>(H, nu);
+  int* cnt = tmp.get<int>((size_t)nrows + 1);
+  hipLaunchKernelGGL(k_zero_i, grid1(nrows + 1), dim3(256), 0, s, cnt, (int64_t)nrows + 1);
+  hipLaunchKernelGGL(k_split_keys, grid1(nu), dim3(256), 0, s, uk, (int64_t)nu, (uint64_t)nrows, C.ci, cnt);
+  C.rp = dnew<int>(H, (size_t)nrows + 1);
+  excl_scan(s, tmp, cnt, C.rp, nrows);
+  C.diag = dnew<double>(H, nrows);
+  row_sums(s, tmp, nrows, C.rp, C.val, C.diag);
+}
+
+// ------------------------------------------------------------ finest level
+__global__ void k_validate(int64_t m, int64_t n, const int32_t* __restrict__ eu, const int32_t* __restrict__ ev,
+                           const double* __restrict__ w, int* flags) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m) return;
+  const int a = eu[e], b = ev[e];
+  if (a < 0 || a >= n || b < 0 || b >= n || a == b) atomicOr(&flags[0], 1);
+  const double x = w[e];
+  if (!(x > 0) || !isfinite(x)) atomicOr(&flags[0], 2);
+}
+__global__ void k_edge_keys(int64_t m, int64_t n, const int32_t* __restrict__ eu, const int32_t* __restrict__ ev,
+                            uint64_t* __restrict__ key) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m) return;
+  const uint64_t a = (uint64_t)min(eu[e], ev[e]), b = (uint64_t)max(eu[e], ev[e]);
+  key[e] = a * (uint64_t)n + b;
+}
+__global__ void k_directed(int64_t nu, uint64_t n, const uint64_t* __restrict__ ukey, const double* __restrict__ uw,
+                           uint64_t* __restrict__ dkey, double* __restrict__ dval) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nu) return;
+  const uint64_t a = ukey[i] / n, b = ukey[i] % n;
+  dkey[2 * i] = a * n + b;
+  dkey[2 * i + 1] = b * n + a;
+  dval[2 * i] = uw[i];
+  dval[2 * i + 1] = uw[i];
+}
+// connected components by min-label hooking and pointer jumping
+__global__ void k_hook(int n, const int* __restrict__ rp, const int* __restrict__ ci, int* lab, int* changed) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= n) return;
+  int best = lab[u];
+  for (int t = rp[u]; t < rp[u + 1]; ++t) best = min(best, lab[ci[t]]);
+  if (best < lab[u]) {
+    atomicMin(&lab[lab[u]], best);
+    atomicMin(&lab[u], best);
+    *changed = 1;
+  }
+}
+__global__ void k_jump(int n, int* lab) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= n) return;
+  int l = lab[u];
+  while (lab[l] != l) l = lab[l];
+  lab[u] = l;
+}
+__global__ void k_count_nonzero(int n, const int* lab, int* cnt) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u < n && lab[u] != 0) atomicAdd(cnt, 1);
+}
+
+}  // namespace
+
+lamg_status build_finest(Hierarchy* H, int64_t n, int64_t m, const int32_t* eu, const int32_t* ev, const double* w) {
+  hipStream_t s = H->s;
+  Tmp tmp;
+  int* flags = tmp.get<int>(4);
+  LAMG_HIP(hipMemsetAsync(flags, 0, 4 * sizeof(int), s));
+  if (m > 0) hipLaunchKernelGGL(k_validate, grid1(m), dim3(256), 0, s, m, n, eu, ev, w, flags);
+  const int f = to_host(s, flags);
+  if (f & 1) return LAMG_E_INVALID_ARG;
+  if (f & 2) return LAMG_E_BAD_WEIGHT;
+  Level L;
+  L.type = LT_FINEST;
+  if (m > 0) {
+    uint64_t* key = tmp.get<uint64_t>(m);
+    uint64_t* ks = tmp.get<uint64_t>(m);
+    double* ws = tmp.get<double>(m);
+    hipLaunchKernelGGL(k_edge_keys, grid1(m), dim3(256), 0, s, m, n, eu, ev, key);
+    sort_pairs(s, tmp, (const uint64_t*)key, ks, w, ws, m, bits_for((uint64_t)n * (uint64_t)n));
+    int* head = tmp.get<int>(m + 1);
+    int* pos = tmp.get<int>(m + 1);
+    hipLaunchKernelGGL(k_heads, grid1(m), dim3(256), 0, s, ks, m, head);
+    excl_scan(s, tmp, head, pos, m);
+    const int nu = to_host(s, pos + m);
+    uint64_t* uk = tmp.get<uint64_t>(nu);
+    double* uw = tmp.get<double>(nu);
+    hipLaunchKernelGGL(k_run_sums, grid1(m), dim3(256), 0, s, ks, ws, m, head, pos, uk, uw);
+    uint64_t* dk = tmp.get<uint64_t>(2 * (size_t)nu);
+    double* dv = tmp.get<double>(2 * (size_t)nu);
+    hipLaunchKernelGGL(k_directed, grid1(nu), dim3(256), 0, s, (int64_t)nu, (uint64_t)n, uk, uw, dk, dv);
+    merge_triples(H, tmp, L, (int)n, dk, dv, 2 * (int64_t)nu);
+  } else {
+    L.n = (int)n;
+    L.nnz = 0;
+    L.rp = dnew<int>(H, n + 1);
+    hipLaunchKernelGGL(k_zero_i, grid1(n + 1), dim3(256), 0, s, L.rp, n + 1);
+    L.ci = dnew<int>(H, 1);
+    L.val = dnew<double>(H, 1);
+    L.diag = dnew<double>(H, n);
+    LAMG_HIP(hipMemsetAsync(L.diag, 0, n * sizeof(double), s));
+  }
+  // connectivity (Section 1: the graph must be connected)
+  int* lab = tmp.get<int>(n);
+  int* chg = tmp.get<int>(2);
+  hipLaunchKernelGGL(k_iota, grid1(n), dim3(256), 0, s, lab, (int)n);
+  for (int it = 0; it < 100000; ++it) {
+    LAMG_HIP(hipMemsetAsync(chg, 0, sizeof(int), s));
+    hipLaunchKernelGGL(k_hook, grid1(n), dim3(256), 0, s, (int)n, L.rp, L.ci, lab, chg);
+    hipLaunchKernelGGL(k_jump, grid1(n), dim3(256), 0, s, (int)n, lab);
+    if (!to_host(s, chg)) break;
+  }
+  LAMG_HIP(hipMemsetAsync(chg, 0, sizeof(int), s));
+  hipLaunchKernelGGL(k_count_nonzero, grid1(n), dim3(256), 0, s, (int)n, lab, chg);
+  if (to_host(s, chg) != 0) return LAMG_E_NOT_CONNECTED;
+  H->lv.push_back(L);
+  return LAMG_OK;
+}
+
+// ---------------------------------------------------------------- colouring
+namespace {
+__global__ void k_prio_hash(int n, uint64_t seed, uint64_t level, uint64_t* h) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u < n) h[u] = dev::hash5(seed, STREAM_COLOUR, level, 0, (uint64_t)u);
+}
+__device__ inline bool higher(int a, int b, const int* deg, const uint64_t* h) {
+  const int da = deg[a], db = deg[b];
+  if (da != db) return da > db;
+  const uint64_t ha = h[a], hb = h[b];
+  if (ha != hb) return ha < hb;
+  return a < b;
+}
+__global__ void k_degrees(int n, const int* __restrict__ rp, int* __restrict__ deg) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u < n) deg[u] = rp[u + 1] - rp[u];
+}
+// One Jones-Plassmann round: a node whose higher-priority neighbours are all
+// coloured takes the smallest colour none of them uses (greedy first fit in
+// priority order).  Colours written in the same round are final, so reading
+// them early gives the same answer.
+__global__ void k_colour_round(int n, const int* __restrict__ rp, const int* __restrict__ ci, const int* __restrict__ deg,
+                               const uint64_t* __restrict__ h, int* col, int* done, int* maxc) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= n) return;
+  if (__hip_atomic_load(&col[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= 0) return;
+  const int p0 = rp[u], p1 = rp[u + 1];
+  for (int base = 0;; base += 64) {
+    uint64_t mask = 0;
+    for (int t = p0; t < p1; ++t) {
+      const int v = ci[t];
+      if (!higher(v, u, deg, h)) continue;
+      const int cv = __hip_atomic_load(&col[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (cv < 0) return;  // not ready this round
+      if (cv >= base && cv < base + 64) mask |= 1ULL << (cv - base);
+    }
+    if (mask != ~0ULL) {
+      const int c = base + __builtin_ctzll(~mask);
+      __hip_atomic_store(&col[u], c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      atomicAdd(done, 1);
+      atomicMax(maxc, c);
+      return;
+    }
+  }
+}
+__global__ void k_inverse(int n, const int* __restrict__ perm, int* __restrict__ inv) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) inv[perm[i]] = i;
+}
+__global__ void k_count_colours(int n, const int* __restrict__ col, int* __restrict__ cnt) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u < n) atomicAdd(&cnt[col[u]], 1);
+}
+__global__ void k_perm_deg(int n, const int* __restrict__ perm, const int* __restrict__ rp, int* __restrict__ deg,
+                           const double* __restrict__ dold, double* __restrict__ dnew_) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int o = perm[i];
+  deg[i] = rp[o + 1] - rp[o];
+  dnew_[i] = dold[o];
+}
+__global__ void k_perm_keys(int n, const int* __restrict__ rp, const int* __restrict__ ci, const int* __restrict__ inv,
+                            uint64_t* __restrict__ key) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= n) return;
+  const uint64_t nu = (uint64_t)inv[u];
+  for (int t = rp[u]; t < rp[u + 1]; ++t) key[t] = nu * (uint64_t)n + (uint64_t)inv[ci[t]];
+}
+__global__ void k_key_cols(int64_t nnz, uint64_t n, const uint64_t* __restrict__ key, int* __restrict__ ci) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nnz) ci[i] = (int)(key[i] % n);
+}
+}  // namespace
+
+// Colour the level, renumber it into (colour, previous id) order, and build
+// its relaxation tiles.  Returns the inverse permutation (old -> new) in
+// `inv_dev` owned by the caller's temporaries.
+// Greedy first-fit colouring in priority order by Jones-Plassmann rounds;
+// returns the number of colours.
+int colour_greedy(hipStream_t s, int n, const int* rp, const int* ci, uint64_t seed, int level, int* col) {
+  Tmp tmp;
+  int* deg = tmp.get<int>(n);
+  uint64_t* h = tmp.get<uint64_t>(n);
+  int* ctr = tmp.get<int>(2);
+  hipLaunchKernelGGL(k_degrees, grid1(n), dim3(256), 0, s, n, rp, deg);
+  hipLaunchKernelGGL(k_prio_hash, grid1(n), dim3(256), 0, s, n, seed, (uint64_t)level, h);
+  LAMG_HIP(hipMemsetAsync(col, 0xff, (size_t)n * sizeof(int), s));
+  LAMG_HIP(hipMemsetAsync(ctr, 0, 2 * sizeof(int), s));
+  for (int round = 0;; ++round) {
+    for (int r = 0; r < 4; ++r)
+      hipLaunchKernelGGL(k_colour_round, grid1(n), dim3(256), 0, s, n, rp, ci, deg, h, col, ctr, ctr + 1);
+    LAMG_HIP(hipGetLastError());
+    if (to_host(s, ctr) >= n) break;
+    if (round > 1000000) throw DevError{hipErrorUnknown};
+  }
+  return to_host(s, ctr + 1) + 1;
+}
+
+static int* colour_order_impl(Hierarchy* H, Tmp& tmp, Level& L, int level) {
+  hipStream_t s = H->s;
+  const int n = L.n;
+  int* col = tmp.get<int>(n);
+  const int ncol = colour_greedy(s, n, L.rp, L.ci, (uint64_t)H->o.seed, level, col);
+  // permutation: stable sort of ids by colour
+  int* ids = tmp.get<int>(n);
+  int* cs = tmp.get<int>(n);
+  int* perm = dnew<int>(H, n);
+  hipLaunchKernelGGL(k_iota, grid1(n), dim3(256), 0, s, ids, n);
+  sort_pairs(s, tmp, (const unsigned*)col, (unsigned*)cs, (const int*)ids, perm, n, bits_for((uint64_t)ncol));
+  int* cc = tmp.get<int>(ncol + 1);
+  int* cptr = tmp.get<int>(ncol + 1);
+  hipLaunchKernelGGL(k_zero_i, grid1(ncol + 1), dim3(256), 0, s, cc, (int64_t)ncol + 1);
+  hipLaunchKernelGGL(k_count_colours, grid1(n), dim3(256), 0, s, n, col, cc);
+  excl_scan(s, tmp, cc, cptr, ncol);
+  L.ncol = ncol;
+  L.cptr = to_host_vec(s, cptr, (size_t)ncol + 1);
+  int* inv = tmp.get<int>(n);
+  hipLaunchKernelGGL(k_inverse, grid1(n), dim3(256), 0, s, n, perm, inv);
+  // permuted CSR: rows by perm, columns renamed and re-sorted
+  int* ndeg = tmp.get<int>(n + 1);
+  double* ndiag = dnew<double>(H, n);
+  hipLaunchKernelGGL(k_perm_deg, grid1(n), dim3(256), 0, s, n, perm, L.rp, ndeg, L.diag, ndiag);
+  int* nrp = dnew<int>(H, (size_t)n + 1);
+  excl_scan(s, tmp, ndeg, nrp, n);
+  if (L.nnz > 0) {
+    uint64_t* key = tmp.get<uint64_t>(L.nnz);
+    uint64_t* ks = tmp.get<uint64_t>(L.nnz);
+    double* nval = dnew<double>(H, L.nnz);
+    int* nci = dnew<int>(H, L.nnz);
+    hipLaunchKernelGGL(k_perm_keys, grid1(n), dim3(256), 0, s, n, L.rp, L.ci, inv, key);
+    sort_pairs(s, tmp, (const uint64_t*)key, ks, (const double*)L.val, nval, L.nnz,
+               bits_for((uint64_t)n * (uint64_t)n));
+    hipLaunchKernelGGL(k_key_cols, grid1(L.nnz), dim3(256), 0, s, (int64_t)L.nnz, (uint64_t)n, ks, nci);
+    L.ci = nci;
+    L.val = nval;
+  }
+  L.rp = nrp;
+  L.diag = ndiag;
+  L.perm = perm;
+  build_tiles(H, L);
+  LAMG_HIP(hipGetLastError());
+  return inv;
+}
+
+// Relaxation tiles per colour: consecutive short rows packed into stream
+// blocks (<= TILE_ROWS rows, <= TILE_NNZ entries), long rows listed apart.
+void build_tiles(Hierarchy* H, Level& L) {
+  hipStream_t s = H->s;
+  std::vector<int> rph = to_host_vec(s, L.rp, (size_t)L.n + 1);
+  L.tiles.assign(L.ncol, Tiles());
+  std::vector<int2> all_s;
+  std::vector<int> all_l;
+  for (int c = 0; c < L.ncol; ++c) {
+    std::vector<int2> blocks;
+    std::vector<int> lr;
+    int a = L.cptr[c];
+    const int e = L.cptr[c + 1];
+    while (a < e) {
+      if (rph[a + 1] - rph[a] > SHORT_ROW) { lr.push_back(a); ++a; continue; }
+      int b = a, nz = 0;
+      while (b < e && b - a < TILE_ROWS) {
+        const int d = rph[b + 1] - rph[b];
+        if (d > SHORT_ROW || nz + d > TILE_NNZ) break;
+        nz += d;
+        ++b;
+      }
+      blocks.push_back(make_int2(a, b));
+      a = b;
+    }
+    Tiles& t = L.tiles[c];
+    t.nstream = (int)blocks.size();
+    t.nlong = (int)lr.size();
+    t.nlong_blocks = (t.nlong + LONG_PER_BLOCK - 1) / LONG_PER_BLOCK;
+    t.stream = (int*)dnew<int2>(H, blocks.size());
+    t.longrows = dnew<int>(H, lr.size());
+    if (!blocks.empty())
+      LAMG_HIP(hipMemcpyAsync(t.stream, blocks.data(), blocks.size() * sizeof(int2), hipMemcpyHostToDevice, s));
+    if (!lr.empty())
+      LAMG_HIP(hipMemcpyAsync(t.longrows, lr.data(), lr.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    all_s.insert(all_s.end(), blocks.begin(), blocks.end());
+    all_l.insert(all_l.end(), lr.begin(), lr.end());
+  }
+  Tiles& t = L.all;
+  t.nstream = (int)all_s.size();
+  t.nlong = (int)all_l.size();
+  t.nlong_blocks = (t.nlong + LONG_PER_BLOCK - 1) / LONG_PER_BLOCK;
+  t.stream = (int*)dnew<int2>(H, all_s.size());
+  t.longrows = dnew<int>(H, all_l.size());
+  if (!all_s.empty())
+    LAMG_HIP(hipMemcpyAsync(t.stream, all_s.data(), all_s.size() * sizeof(int2), hipMemcpyHostToDevice, s));
+  if (!all_l.empty())
+    LAMG_HIP(hipMemcpyAsync(t.longrows, all_l.data(), all_l.size() * sizeof(int), hipMemcpyHostToDevice, s));
+  LAMG_HIP(hipStreamSynchronize(s));
+}
+
+void colour_and_order(Hierarchy* H, Level& L, int level, std::vector<int>*) {
+  Tmp tmp;
+  colour_order_impl(H, tmp, L, level);
+}
+
+// -------------------------------------------------------------- elimination
+namespace {
+// Section 3.2: in (colour, id) order, a node of degree <= maxdeg with no
+// neighbour in F joins F.  Nodes of one colour are pairwise non-adjacent, so
+// each colour class decides at once and later classes see its result.
+__global__ void k_elim_colour(int r0, int r1, const int* __restrict__ rp, const int* __restrict__ ci, int maxdeg,
+                              int* inF, int* cnt) {
+  const int u = r0 + blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= r1) return;
+  const int p0 = rp[u], p1 = rp[u + 1];
+  if (p1 - p0 > maxdeg) return;
+  for (int t = p0; t < p1; ++t)
+    if (inF[ci[t]]) return;
+  inF[u] = 1;
+  atomicAdd(cnt, 1);
+}
+__global__ void k_not(int n, const int* __restrict__ a, int* __restrict__ b) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u < n) b[u] = 1 - a[u];
+}
+// emission counts: C rows -> number of C neighbours; F rows -> deg (deg - 1)
+__global__ void k_schur_counts(int n, const int* __restrict__ rp, const int* __restrict__ ci, const int* __restrict__ inF,
+                               int* __restrict__ ccnt, int* __restrict__ fcnt) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= n) return;
+  const int d = rp[u + 1] - rp[u];
+  if (inF[u]) { ccnt[u] = 0; fcnt[u] = d * (d - 1); return; }
+  int c = 0;
+  for (int t = rp[u]; t < rp[u + 1]; ++t) c += inF[ci[t]] ? 0 : 1;
+  ccnt[u] = c;
+  fcnt[u] = 0;
+}
+// w^c_ij = w_ij + sum_f w_fi w_fj / a_ff (eq. elim), emitted C-C edges first,
+// then each F node's ordered neighbour pairs.
+__global__ void k_schur_emit(int n, uint64_t nc, const int* __restrict__ rp, const int* __restrict__ ci,
+                             const double* __restrict__ val, const double* __restrict__ diag, const int* __restrict__ inF,
+                             const int* __restrict__ crank, const int* __restrict__ coff, const int* __restrict__ foff,
+                             int ctot, uint64_t* __restrict__ key, double* __restrict__ v) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= n) return;
+  const int p0 = rp[u], p1 = rp[u + 1];
+  if (!inF[u]) {
+    int o = coff[u];
+    const uint64_t cu = (uint64_t)crank[u];
+    for (int t = p0; t < p1; ++t)
+      if (!inF[ci[t]]) { key[o] = cu * nc + (uint64_t)crank[ci[t]]; v[o] = val[t]; ++o; }
+    return;
+  }
+  int o = ctot + foff[u];
+  const double d = diag[u];
+  for (int a = p0; a < p1; ++a)
+    for (int b = p0; b < p1; ++b) {
+      if (a == b) continue;
+      key[o] = (uint64_t)crank[ci[a]] * nc + (uint64_t)crank[ci[b]];
+      v[o] = (val[a] * val[b]) / d;
+      ++o;
+    }
+}
+__global__ void k_elim_maps(int n, const int* __restrict__ inF, const int* __restrict__ crank,
+                            const int* __restrict__ cinv, int* __restrict__ cidx, int* __restrict__ cfine) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= n) return;
+  if (inF[u]) { cidx[u] = -1; return; }
+  const int c = cinv[crank[u]];
+  cidx[u] = c;
+  cfine[c] = u;
+}
+}  // namespace
+
+bool try_eliminate(Hierarchy* H, int l) {
+  hipStream_t s = H->s;
+  Tmp tmp;
+  const Level& F = H->lv[l];
+  const int n = F.n;
+  int* inF = tmp.get<int>(n);
+  int* cnt = tmp.get<int>(1);
+  LAMG_HIP(hipMemsetAsync(inF, 0, (size_t)n * sizeof(int), s));
+  LAMG_HIP(hipMemsetAsync(cnt, 0, sizeof(int), s));
+  for (int c = 0; c < F.ncol; ++c) {
+    const int r0 = F.cptr[c], r1 = F.cptr[c + 1];
+    if (r1 > r0)
+      hipLaunchKernelGGL(k_elim_colour, grid1(r1 - r0), dim3(256), 0, s, r0, r1, F.rp, F.ci, H->o.elim_max_degree, inF,
+                         cnt);
+  }
+  const int nF = to_host(s, cnt);
+  if (nF == 0 || (double)nF < H->o.elim_stop_frac * (double)n) return false;
+  int* isC = tmp.get<int>(n + 1);
+  int* crank = tmp.get<int>(n + 1);
+  hipLaunchKernelGGL(k_not, grid1(n), dim3(256), 0, s, n, inF, isC);
+  excl_scan(s, tmp, isC, crank, n);
+  const int nc = n - nF;
+  int* ccnt = tmp.get<int>(n + 1);
+  int* fcnt = tmp.get<int>(n + 1);
+  int* coff = tmp.get<int>(n + 1);
+  int* foff = tmp.get<int>(n + 1);
+  hipLaunchKernelGGL(k_schur_counts, grid1(n), dim3(256), 0, s, n, F.rp, F.ci, inF, ccnt, fcnt);
+  excl_scan(s, tmp, ccnt, coff, n);
+  excl_scan(s, tmp, fcnt, foff, n);
+  const int ctot = to_host(s, coff + n), ftot = to_host(s, foff + n);
+  const int64_t nt = (int64_t)ctot + ftot;
+  uint64_t* key = tmp.get<uint64_t>(nt);
+  double* v = tmp.get<double>(nt);
+  hipLaunchKernelGGL(k_schur_emit, grid1(n), dim3(256), 0, s, n, (uint64_t)nc, F.rp, F.ci, F.val, F.diag, inF, crank,
+                     coff, foff, ctot, key, v);
+  Level C;
+  C.type = LT_ELIM;
+  C.nF = nF;
+  merge_triples(H, tmp, C, nc, key, v, nt);
+  int* cinv = colour_order_impl(H, tmp, C, l + 1);
+  C.cidx = dnew<int>(H, n);
+  C.cfine = dnew<int>(H, nc);
+  hipLaunchKernelGGL(k_elim_maps, grid1(n), dim3(256), 0, s, n, inF, crank, cinv, C.cidx, C.cfine);
+  LAMG_HIP(hipStreamSynchronize(s));
+  H->lv.push_back(C);
+  return true;
+}
+
+// -------------------------------------------------------------- aggregation
+namespace {
+__global__ void k_tv_init(int n, int K, uint64_t seed, uint64_t level, double* X) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)n * K) return;
+  const int u = (int)(i / K), k = (int)(i % K);
+  X[i] = dev::unit_pm1(dev::hash5(seed, STREAM_TV, level, (uint64_t)k, (uint64_t)u));
+}
+// Node quantities: |X_u|^2, y*_k = (sum_v w_uv x_v)/a_uu, Emin_k =
+// 1/2 sum_v w_uv (x_v - y*_k)^2 (minimum of the local energy, Section 3.4.4),
+// sum_v w_uv, sum_v w_uv |E_v| (hub test), max_v w_uv (weak edges).
+struct NodeOut {
+  double *nrm, *ystar, *emin, *sw, *swd, *maxw;
+};
+__global__ void k_node_short(int n, int K, const int* __restrict__ rp, const int* __restrict__ ci,
+                             const double* __restrict__ val, const double* __restrict__ diag, const int* __restrict__ deg,
+                             const double* __restrict__ X, NodeOut o) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= n) return;
+  const int p0 = rp[u], len = rp[u + 1] - p0;
+  double s = 0;
+  for (int k = 0; k < K; ++k) s += X[(size_t)u * K + k] * X[(size_t)u * K + k];
+  o.nrm[u] = s;
+  double mw = 0;
+  for (int t = p0; t < p0 + len; ++t) mw = fmax(mw, val[t]);
+  o.maxw[u] = mw;
+  if (len > SHORT_ROW) return;
+  for (int k = 0; k < K; ++k) {
+    const double B = dev::row_sum_seq<double>(len, [&](int t) { return val[p0 + t] * X[(size_t)ci[p0 + t] * K + k]; });
+    const double y = B / diag[u];
+    const double S2 = dev::row_sum_seq<double>(len, [&](int t) {
+      const double d = X[(size_t)ci[p0 + t] * K + k] - y;
+      return val[p0 + t] * (d * d);
+    });
+    o.ystar[(size_t)u * K + k] = y;
+    o.emin[(size_t)u * K + k] = 0.5 * S2;
+  }
+  o.sw[u] = dev::row_sum_seq<double>(len, [&](int t) { return val[p0 + t]; });
+  o.swd[u] = dev::row_sum_seq<double>(len, [&](int t) { return val[p0 + t] * (double)deg[ci[p0 + t]]; });
+}
+__global__ void k_node_long(const int* __restrict__ rows, int nrows, int K, const int* __restrict__ rp,
+                            const int* __restrict__ ci, const double* __restrict__ val, const double* __restrict__ diag,
+                            const int* __restrict__ deg, const double* __restrict__ X, NodeOut o) {
+  const int idx = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, lane = threadIdx.x & 63;
+  if (idx >= nrows) return;
+  const int u = rows[idx];
+  const int p0 = rp[u], len = rp[u + 1] - p0;
+  for (int k = 0; k < K; ++k) {
+    const double B = dev::row_sum_wave<double>(len, lane, [&](int t) { return val[p0 + t] * X[(size_t)ci[p0 + t] * K + k]; });
+    const double y = B / diag[u];
+    const double S2 = dev::row_sum_wave<double>(len, lane, [&](int t) {
+      const double d = X[(size_t)ci[p0 + t] * K + k] - y;
+      return val[p0 + t] * (d * d);
+    });
+    if (lane == 0) {
+      o.ystar[(size_t)u * K + k] = y;
+      o.emin[(size_t)u * K + k] = 0.5 * S2;
+    }
+  }
+  const double sw = dev::row_sum_wave<double>(len, lane, [&](int t) { return val[p0 + t]; });
+  const double swd = dev::row_sum_wave<double>(len, lane, [&](int t) { return val[p0 + t] * (double)deg[ci[p0 + t]]; });
+  if (lane == 0) { o.sw[u] = sw; o.swd[u] = swd; }
+}
+// Per directed edge: affinity c_us (eq. cuv), energy-ratio admissibility
+// (eq. qut, ratio >= 1 form: a_uu (x_s - y*)^2 <= 2 (q_max - 1) Emin for all
+// test vectors), weak flag (w < ratio * max neighbouring weight).
+__global__ void k_edges(int n, int K, const int* __restrict__ rp, const int* __restrict__ ci,
+                        const double* __restrict__ val, const double* __restrict__ diag, const double* __restrict__ X,
+                        NodeOut o, double qfac, double wratio, double* __restrict__ aff, uint8_t* __restrict__ ok,
+                        uint8_t* __restrict__ weak) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= n) return;
+  const double nu = o.nrm[u], du = diag[u], mu = o.maxw[u];
+  for (int t = rp[u]; t < rp[u + 1]; ++t) {
+    const int s = ci[t];
+    double p = 0;
+    for (int k = 0; k < K; ++k) p += X[(size_t)u * K + k] * X[(size_t)s * K + k];
+    double c = 1.0;
+    const double ns = o.nrm[s];
+    if (nu > 0 && ns > 0) {
+      c = 1.0 - (p * p) / (nu * ns);
+      if (c < 0) c = 0;
+    }
+    aff[t] = c;
+    bool good = true;
+    for (int k = 0; k < K && good; ++k) {
+      const double d = X[(size_t)s * K + k] - o.ystar[(size_t)u * K + k];
+      good = (du * (d * d)) <= (qfac * o.emin[(size_t)u * K + k]);
+    }
+    ok[t] = good ? 1 : 0;
+    weak[t] = (val[t] < wratio * fmax(mu, o.maxw[s])) ? 1 : 0;
+  }
+}
+// Initial states: hubs (Section 3.4.1 footnote) are seeds; nodes whose every
+// edge is weak go to the dummy aggregate; others are undecided.
+__global__ void k_init_state(int n, const int* __restrict__ rp, const int* __restrict__ deg, NodeOut o,
+                             double hubf, const uint8_t* __restrict__ weak, int* __restrict__ st,
+                             uint8_t* __restrict__ hub, int* __restrict__ seedof) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= n) return;
+  seedof[u] = -1;
+  if ((double)deg[u] * o.sw[u] >= hubf * o.swd[u]) { hub[u] = 1; st[u] = ST_SEED; return; }
+  hub[u] = 0;
+  bool allweak = rp[u + 1] > rp[u];
+  for (int t = rp[u]; t < rp[u + 1]; ++t)
+    if (!weak[t]) { allweak = false; break; }
+  st[u] = allweak ? ST_DUMMY : ST_UNDECIDED;
+}
+__device__ inline bool candidate(int t, const int* ci, const int* st, const uint8_t* weak, const uint8_t* ok,
+                                 const double* aff, double delta) {
+  const int ss = st[ci[t]];
+  return (ss == ST_SEED || ss == ST_UNDECIDED) && !weak[t] && ok[t] && aff[t] <= delta;
+}
+// best candidate affinity of each undecided node (2.0 when none)
+__global__ void k_best(int n, const int* __restrict__ rp, const int* __restrict__ ci, const int* __restrict__ st,
+                       const uint8_t* __restrict__ weak, const uint8_t* __restrict__ ok, const double* __restrict__ aff,
+                       double* __restrict__ best, int* cnt) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= n) return;
+  double b = 2.0;
+  if (st[u] == ST_UNDECIDED)
+    for (int t = rp[u]; t < rp[u + 1]; ++t)
+      if (candidate(t, ci, st, weak, ok, aff, 1.0)) b = fmin(b, aff[t]);
+  best[u] = b;
+  if (b <= 1.0) atomicAdd(cnt, 1);
+}
+// One colour class of an aggregation stage (Section 3.4.2): each undecided
+// node joins its non-associate neighbour of smallest affinity (ties: smallest
+// id) among admissible non-weak candidates within the stage threshold.
+__global__ void k_agg_colour(int r0, int r1, const int* __restrict__ rp, const int* __restrict__ ci, int* st,
+                             int* __restrict__ seedof, const uint8_t* __restrict__ weak, const uint8_t* __restrict__ ok,
+                             const double* __restrict__ aff, double delta) {
+  const int u = r0 + blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= r1) return;
+  if (st[u] != ST_UNDECIDED) return;
+  int bt = -1;
+  for (int t = rp[u]; t < rp[u + 1]; ++t) {
+    const int ss = __hip_atomic_load(&st[ci[t]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if ((ss == ST_SEED || ss == ST_UNDECIDED) && !weak[t] && ok[t] && aff[t] <= delta)
+      if (bt < 0 || aff[t] < aff[bt]) bt = t;
+  }
+  if (bt < 0) return;
+  const int sd = ci[bt];
+  st[u] = ST_ASSOC;
+  seedof[u] = sd;
+  __hip_atomic_store(&st[sd], (int)ST_SEED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__global__ void k_count_states(int n, const int* __restrict__ st, int* cnt) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= n) return;
+  const int x = st[u];
+  if (x == ST_SEED || x == ST_UNDECIDED) atomicAdd(&cnt[0], 1);
+  else if (x == ST_DUMMY) { atomicAdd(&cnt[1], 1); atomicMin(&cnt[2], u); }
+}
+__global__ void k_finalise(int n, int* __restrict__ st, int dmin, int* __restrict__ rep) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= n) return;
+  if (st[u] == ST_UNDECIDED) st[u] = ST_SEED;
+  rep[u] = (st[u] == ST_SEED || u == dmin) ? 1 : 0;
+}
+__global__ void k_number(int n, const int* __restrict__ st, const int* __restrict__ seedof, const int* __restrict__ id,
+                         int dmin, int* __restrict__ agg) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= n) return;
+  const int x = st[u];
+  agg[u] = x == ST_SEED ? id[u] : (x == ST_ASSOC ? id[seedof[u]] : id[dmin]);
+}
+// Galerkin P^T A P (eq. galerkin): inter-aggregate fine edges, listed by fine
+// row and column order.
+__global__ void k_gal_counts(int n, const int* __restrict__ rp, const int* __restrict__ ci, const int* __restrict__ agg,
+                             int* __restrict__ cnt) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= n) return;
+  int c = 0;
+  const int a = agg[u];
+  for (int t = rp[u]; t < rp[u + 1]; ++t) c += agg[ci[t]] != a;
+  cnt[u] = c;
+}
+__global__ void k_gal_emit(int n, uint64_t nc, const int* __restrict__ rp, const int* __restrict__ ci,
+                           const double* __restrict__ val, const int* __restrict__ agg, const int* __restrict__ off,
+                           uint64_t* __restrict__ key, double* __restrict__ v) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= n) return;
+  const int a = agg[u];
+  int o = off[u];
+  for (int t = rp[u]; t < rp[u + 1]; ++t) {
+    const int b = agg[ci[t]];
+    if (b == a) continue;
+    key[o] = (uint64_t)a * nc + (uint64_t)b;
+    v[o] = val[t];
+    ++o;
+  }
+}
+__global__ void k_map(int n, const int* __restrict__ a, const int* __restrict__ inv, int* __restrict__ out) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u < n) out[u] = inv[a[u]];
+}
+__global__ void k_copy_u8(int64_t n, const int* __restrict__ a, uint8_t* __restrict__ b) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (uint8_t)a[i];
+}
+}  // namespace
+
+bool aggregate(Hierarchy* H, int l, int agg_index) {
+  hipStream_t s = H->s;
+  Tmp tmp;
+  Level& F = H->lv[l];
+  const int n = F.n;
+  const int K = std::min(H->o.tv_k_max, H->o.tv_k_min + 2 * agg_index);
+  F.K = K;
+  // test vectors: U[-1,1) then tv_sweeps GS sweeps on A x = 0 (Section 3.3.1)
+  F.tv = dnew<double>(H, (size_t)n * K);
+  hipLaunchKernelGGL(k_tv_init, grid1((int64_t)n * K), dim3(256), 0, s, n, K, (uint64_t)H->o.seed, (uint64_t)l, F.tv);
+  for (int sw = 0; sw < H->o.tv_sweeps; ++sw) gs_multi_sweep(s, F, nullptr, F.tv, K);
+  int* deg = tmp.get<int>(n);
+  hipLaunchKernelGGL(k_degrees, grid1(n), dim3(256), 0, s, n, F.rp, deg);
+  NodeOut o;
+  o.nrm = tmp.get<double>(n);
+  o.ystar = tmp.get<double>((size_t)n * K);
+  o.emin = tmp.get<double>((size_t)n * K);
+  o.sw = tmp.get<double>(n);
+  o.swd = tmp.get<double>(n);
+  o.maxw = tmp.get<double>(n);
+  hipLaunchKernelGGL(k_node_short, grid1(n), dim3(256), 0, s, n, K, F.rp, F.ci, F.val, F.diag, deg, F.tv, o);
+  if (F.all.nlong)
+    hipLaunchKernelGGL(k_node_long, grid1((int64_t)F.all.nlong * 64), dim3(256), 0, s, F.all.longrows, F.all.nlong, K,
+                       F.rp, F.ci, F.val, F.diag, deg, F.tv, o);
+  const int64_t E2 = F.nnz;
+  F.aff = dnew<double>(H, E2);
+  F.ok = dnew<uint8_t>(H, E2);
+  F.weak = dnew<uint8_t>(H, E2);
+  F.hub = dnew<uint8_t>(H, n);
+  F.state = dnew<int>(H, n);
+  const double qfac = 2.0 * (H->o.q_max - 1.0);
+  hipLaunchKernelGGL(k_edges, grid1(n), dim3(256), 0, s, n, K, F.rp, F.ci, F.val, F.diag, F.tv, o, qfac,
+                     H->o.weak_edge_ratio, F.aff, F.ok, F.weak);
+  int* st = F.state;
+  int* seedof = tmp.get<int>(n);
+  hipLaunchKernelGGL(k_init_state, grid1(n), dim3(256), 0, s, n, F.rp, deg, o, H->o.hub_factor, F.weak, st, F.hub,
+                     seedof);
+  // stage-1 threshold: quantile of the best candidate affinities
+  double* best = tmp.get<double>(n);
+  double* bsorted = tmp.get<double>(n);
+  int* cnt = tmp.get<int>(4);
+  LAMG_HIP(hipMemsetAsync(cnt, 0, 4 * sizeof(int), s));
+  hipLaunchKernelGGL(k_best, grid1(n), dim3(256), 0, s, n, F.rp, F.ci, st, F.weak, F.ok, F.aff, best, cnt);
+  sort_keys_double(s, tmp, (const double*)best, bsorted, n);
+  const int nbest = to_host(s, cnt);
+  double delta1 = 1.0;
+  if (nbest > 0) {
+    const size_t idx = (size_t)((double)(nbest - 1) * H->o.stage1_quantile);
+    delta1 = to_host(s, bsorted + idx);
+  }
+  F.delta1 = delta1;
+  const double amax = 0.7 / H->o.gamma;
+  int dmin = -1;
+  auto run_stage = [&](double delta) {
+    for (int c = 0; c < F.ncol; ++c) {
+      const int r0 = F.cptr[c], r1 = F.cptr[c + 1];
+      if (r1 > r0)
+        hipLaunchKernelGGL(k_agg_colour, grid1(r1 - r0), dim3(256), 0, s, r0, r1, F.rp, F.ci, st, seedof, F.weak, F.ok,
+                           F.aff, delta);
+    }
+    int h0[3] = {0, 0, 0x7fffffff};
+    LAMG_HIP(hipMemcpyAsync(cnt, h0, 3 * sizeof(int), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_count_states, grid1(n), dim3(256), 0, s, n, st, cnt);
+    int h1[3];
+    LAMG_HIP(hipMemcpyAsync(h1, cnt, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
+    LAMG_HIP(hipStreamSynchronize(s));
+    dmin = h1[1] > 0 ? h1[2] : -1;
+    return (double)(h1[0] + (h1[1] > 0 ? 1 : 0)) / (double)n;
+  };
+  F.alpha1 = run_stage(delta1);
+  F.stage = 1;
+  F.alpha2 = -1;
+  if (F.alpha1 > amax) {
+    int* st1 = tmp.get<int>(n);
+    int* so1 = tmp.get<int>(n);
+    LAMG_HIP(hipMemcpyAsync(st1, st, (size_t)n * sizeof(int), hipMemcpyDeviceToDevice, s));
+    LAMG_HIP(hipMemcpyAsync(so1, seedof, (size_t)n * sizeof(int), hipMemcpyDeviceToDevice, s));
+    const int dmin1 = dmin;
+    F.alpha2 = run_stage(1.0);
+    if (std::fabs(F.alpha1 - amax) <= std::fabs(F.alpha2 - amax)) {
+      LAMG_HIP(hipMemcpyAsync(st, st1, (size_t)n * sizeof(int), hipMemcpyDeviceToDevice, s));
+      LAMG_HIP(hipMemcpyAsync(seedof, so1, (size_t)n * sizeof(int), hipMemcpyDeviceToDevice, s));
+      dmin = dmin1;
+      F.stage = 1;
+    } else {
+      F.stage = 2;
+    }
+  }
+  int* rep = tmp.get<int>(n + 1);
+  int* id = tmp.get<int>(n + 1);
+  hipLaunchKernelGGL(k_finalise, grid1(n), dim3(256), 0, s, n, st, dmin, rep);
+  excl_scan(s, tmp, rep, id, n);
+  const int nc = to_host(s, id + n);
+  if (nc >= n) return false;  // no coarsening possible
+  int* aggn = tmp.get<int>(n);
+  hipLaunchKernelGGL(k_number, grid1(n), dim3(256), 0, s, n, st, seedof, id, dmin, aggn);
+  // Galerkin coarse operator
+  int* gcnt = tmp.get<int>(n + 1);
+  int* goff = tmp.get<int>(n + 1);
+  hipLaunchKernelGGL(k_gal_counts, grid1(n), dim3(256), 0, s, n, F.rp, F.ci, aggn, gcnt);
+  excl_scan(s, tmp, gcnt, goff, n);
+  const int nt = to_host(s, goff + n);
+  uint64_t* key = tmp.get<uint64_t>(nt);
+  double* v = tmp.get<double>(nt);
+  hipLaunchKernelGGL(k_gal_emit, grid1(n), dim3(256), 0, s, n, (uint64_t)nc, F.rp, F.ci, F.val, aggn, goff, key, v);
+  Level C;
+  C.type = LT_AGG;
+  merge_triples(H, tmp, C, nc, key, v, nt);
+  int* cinv = colour_order_impl(H, tmp, C, l + 1);
+  C.agg = dnew<int>(H, n);
+  hipLaunchKernelGGL(k_map, grid1(n), dim3(256), 0, s, n, aggn, cinv, C.agg);
+  // P^T as CSR: members of each aggregate in ascending fine id
+  int* ids = tmp.get<int>(n);
+  int* ks = tmp.get<int>(n);
+  C.members = dnew<int>(H, n);
+  hipLaunchKernelGGL(k_iota, grid1(n), dim3(256), 0, s, ids, n);
+  sort_pairs(s, tmp, (const unsigned*)C.agg, (unsigned*)ks, (const int*)ids, C.members, n, bits_for((uint64_t)nc));
+  int* acnt = tmp.get<int>(nc + 1);
+  hipLaunchKernelGGL(k_zero_i, grid1(nc + 1), dim3(256), 0, s, acnt, (int64_t)nc + 1);
+  hipLaunchKernelGGL(k_count_colours, grid1(n), dim3(256), 0, s, n, C.agg, acnt);
+  C.agg_ptr = dnew<int>(H, (size_t)nc + 1);
+  excl_scan(s, tmp, acnt, C.agg_ptr, nc);
+  LAMG_HIP(hipStreamSynchronize(s));
+  H->lv.push_back(C);
+  return true;
+}
+
+// Cycle indices (Section 4.2, eq. cycle_index with gamma^l >= 1), FP32 level
+// copies, work vectors and the coarsest factor.
+namespace {
+__global__ void k_to_f32(int64_t n, const double* __restrict__ a, float* __restrict__ b) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (float)a[i];
+}
+}  // namespace
+
+void finish_levels(Hierarchy* H) {
+  hipStream_t s = H->s;
+  const double E1 = (double)H->lv[0].nnz;
+  for (size_t l = 0; l + 1 < H->lv.size(); ++l) {
+    Level& F = H->lv[l];
+    const Level& C = H->lv[l + 1];
+    if (C.type == LT_ELIM) { F.gamma_next = 1.0; continue; }
+    const double El = (double)F.nnz, Ec = (double)C.nnz;
+    if (El > 0.1 * E1) F.gamma_next = H->o.gamma;
+    else if (Ec <= 0) F.gamma_next = 1.0;
+    else F.gamma_next = std::max(1.0, std::min(2.0, 0.7 * El / Ec));
+  }
+  for (Level& L : H->lv) {
+    L.val32 = dnew<float>(H, std::max(L.nnz, 1));
+    L.diag32 = dnew<float>(H, L.n);
+    if (L.nnz) hipLaunchKernelGGL(k_to_f32, grid1(L.nnz), dim3(256), 0, s, (int64_t)L.nnz, L.val, L.val32);
+    hipLaunchKernelGGL(k_to_f32, grid1(L.n), dim3(256), 0, s, (int64_t)L.n, L.diag, L.diag32);
+    auto mk64 = [&](Vecs<double>& v) {
+      v.x = dnew<double>(H, L.n); v.b = dnew<double>(H, L.n); v.r = dnew<double>(H, L.n);
+      for (int i = 0; i < 2; ++i) { v.X[i] = dnew<double>(H, L.n); v.R[i] = dnew<double>(H, L.n); }
+    };
+    auto mk32 = [&](Vecs<float>& v) {
+      v.x = dnew<float>(H, L.n); v.b = dnew<float>(H, L.n); v.r = dnew<float>(H, L.n);
+      for (int i = 0; i < 2; ++i) { v.X[i] = dnew<float>(H, L.n); v.R[i] = dnew<float>(H, L.n); }
+    };
+    mk64(L.v64);
+    mk32(L.v32);
+  }
+  coarsest_factor(H, H->lv.back());
+  H->red = dnew<double>(H, k::RED_BLOCKS * 8 + 16);
+  LAMG_HIP(hipHostMalloc((void**)&H->hred, 64 * sizeof(double), hipHostMallocDefault));
+  LAMG_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace lamg

@@ -1,0 +1,481 @@
+// Solve-phase kernels: multicolour Gauss-Seidel and residual over tiled CSR
+// rows, aggregation / elimination transfers, deterministic reductions for
+// iterate recombination, mean removal and norms, and the coarsest solve.
+#include <algorithm>
+#include <cmath>
+
+#include "lamg_device.hpp"
+#include "lamg_internal.hpp"
+
+namespace lamg {
+
+// ---------------------------------------------------------------- relaxation
+// One pass over a set of rows of a colour-ordered level.
+//   MODE 0: Gauss-Seidel update x_u <- (b_u + sum_v w_uv x_v) / a_uu (eq. gs)
+//   MODE 1: residual r_u <- (b_u + sum_v w_uv x_v) - a_uu x_u
+// Stream blocks stage the products w_uv * x_v of up to TILE_NNZ entries of
+// consecutive short rows in LDS with coalesced loads, then one thread per row
+// sums them left to right.  Long-row blocks give each row a wavefront that
+// sums with stride 64 and folds with an xor butterfly.  A GS pass only ever
+// covers one colour class, whose rows are pairwise non-adjacent, so the rows
+// it writes are never read in the same launch.
+template <class T, int MODE>
+__global__ __launch_bounds__(RELAX_THREADS) void k_relax(
+    const int* __restrict__ rp, const int* __restrict__ ci, const T* __restrict__ val,
+    const T* __restrict__ diag, const T* __restrict__ b, T* x, T* __restrict__ r,
+    const int2* __restrict__ sblk, int nstream, const int* __restrict__ longrows, int nlong) {
+  __shared__ T prod[TILE_NNZ];
+  __shared__ int srp[TILE_ROWS + 1];
+  const int bid = blockIdx.x;
+  if (bid < nstream) {
+    const int2 rr = sblk[bid];
+    const int nr = rr.y - rr.x;
+    for (int i = threadIdx.x; i <= nr; i += RELAX_THREADS) srp[i] = rp[rr.x + i];
+    __syncthreads();
+    const int base = srp[0];
+    const int cnt = srp[nr] - base;
+    for (int j = threadIdx.x; j < cnt; j += RELAX_THREADS) prod[j] = val[base + j] * x[ci[base + j]];
+    __syncthreads();
+    if (threadIdx.x < nr) {
+      const int u = rr.x + threadIdx.x;
+      const int j1 = srp[threadIdx.x + 1] - base;
+      T s = 0;
+      for (int j = srp[threadIdx.x] - base; j < j1; ++j) s += prod[j];
+      const T bu = b ? b[u] : T(0);
+      if (MODE == 0) x[u] = (bu + s) / diag[u];
+      else r[u] = (bu + s) - diag[u] * x[u];
+    }
+    return;
+  }
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int idx = (bid - nstream) * LONG_PER_BLOCK + wv;
+  if (idx >= nlong) return;
+  const int u = longrows[idx];
+  const int p0 = rp[u], len = rp[u + 1] - p0;
+  T s = 0;
+  for (int t = lane; t < len; t += 64) s += val[p0 + t] * x[ci[p0 + t]];
+  s = dev::wave_fold(s);
+  if (lane == 0) {
+    const T bu = b ? b[u] : T(0);
+    if (MODE == 0) x[u] = (bu + s) / diag[u];
+    else r[u] = (bu + s) - diag[u] * x[u];
+  }
+}
+
+template <class T, int MODE>
+static void launch_relax(hipStream_t s, const Level& L, const Tiles& t, const T* val, const T* diag,
+                         const T* b, T* x, T* r) {
+  const int grid = t.nstream + t.nlong_blocks;
+  if (grid == 0) return;
+  hipLaunchKernelGGL((k_relax<T, MODE>), dim3(grid), dim3(RELAX_THREADS), 0, s, L.rp, L.ci, val, diag, b, x, r,
+                     (const int2*)t.stream, t.nstream, t.longrows, t.nlong);
+  LAMG_HIP(hipGetLastError());
+}
+
+template <class T>
+void gs_colour(hipStream_t s, const Level& L, int c, const T* val, const T* diag, const T* b, T* x) {
+  launch_relax<T, 0>(s, L, L.tiles[c], val, diag, b, x, (T*)nullptr);
+}
+template <class T>
+void gs_sweep(hipStream_t s, const Level& L, const T* val, const T* diag, const T* b, T* x) {
+  for (int c = 0; c < L.ncol; ++c) gs_colour<T>(s, L, c, val, diag, b, x);
+}
+template <class T>
+void residual(hipStream_t s, const Level& L, const T* val, const T* diag, const T* b, const T* x, T* r) {
+  launch_relax<T, 1>(s, L, L.all, val, diag, b, (T*)x, r);
+}
+template void gs_colour<double>(hipStream_t, const Level&, int, const double*, const double*, const double*, double*);
+template void gs_colour<float>(hipStream_t, const Level&, int, const float*, const float*, const float*, float*);
+template void gs_sweep<double>(hipStream_t, const Level&, const double*, const double*, const double*, double*);
+template void gs_sweep<float>(hipStream_t, const Level&, const float*, const float*, const float*, float*);
+template void residual<double>(hipStream_t, const Level&, const double*, const double*, const double*, const double*, double*);
+template void residual<float>(hipStream_t, const Level&, const float*, const float*, const float*, const float*, float*);
+
+// Multi-vector GS on A X = 0 or A X = B for K <= 10 vectors stored n x K
+// row-major (test-vector relaxation).  Thread per short row, K running sums.
+constexpr int KMAX = 10;
+__global__ __launch_bounds__(256) void k_gs_multi_short(const int* __restrict__ rp, const int* __restrict__ ci,
+                                                        const double* __restrict__ val, const double* __restrict__ diag,
+                                                        const double* __restrict__ B, double* X, int K, int r0, int r1) {
+  const int u = r0 + blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= r1) return;
+  const int p0 = rp[u], len = rp[u + 1] - p0;
+  if (len > SHORT_ROW) return;
+  double s[KMAX];
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k) s[k] = 0;
+  for (int t = 0; t < len; ++t) {
+    const double w = val[p0 + t];
+    const double* xv = X + (size_t)ci[p0 + t] * K;
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k)
+      if (k < K) s[k] += w * xv[k];
+  }
+  const double d = diag[u];
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k)
+    if (k < K) {
+      const double bu = B ? B[(size_t)u * K + k] : 0.0;
+      X[(size_t)u * K + k] = (bu + s[k]) / d;
+    }
+}
+__global__ __launch_bounds__(256) void k_gs_multi_long(const int* __restrict__ rp, const int* __restrict__ ci,
+                                                       const double* __restrict__ val, const double* __restrict__ diag,
+                                                       const double* __restrict__ B, double* X, int K,
+                                                       const int* __restrict__ longrows, int nlong) {
+  const int idx = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (idx >= nlong) return;
+  const int u = longrows[idx];
+  const int p0 = rp[u], len = rp[u + 1] - p0;
+  for (int k = 0; k < K; ++k) {
+    double s = 0;
+    for (int t = lane; t < len; t += 64) s += val[p0 + t] * X[(size_t)ci[p0 + t] * K + k];
+    s = dev::wave_fold(s);
+    if (lane == 0) {
+      const double bu = B ? B[(size_t)u * K + k] : 0.0;
+      X[(size_t)u * K + k] = (bu + s) / diag[u];
+    }
+  }
+}
+
+void gs_multi_sweep(hipStream_t s, const Level& L, const double* b, double* X, int K) {
+  for (int c = 0; c < L.ncol; ++c) {
+    const int r0 = L.cptr[c], r1 = L.cptr[c + 1];
+    if (r1 > r0)
+      hipLaunchKernelGGL(k_gs_multi_short, dim3((r1 - r0 + 255) / 256), dim3(256), 0, s, L.rp, L.ci, L.val, L.diag, b,
+                         X, K, r0, r1);
+    const Tiles& t = L.tiles[c];
+    if (t.nlong)
+      hipLaunchKernelGGL(k_gs_multi_long, dim3((t.nlong + 3) / 4), dim3(256), 0, s, L.rp, L.ci, L.val, L.diag, b, X, K,
+                         t.longrows, t.nlong);
+  }
+  LAMG_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------- transfers
+// Aggregation restriction b^c_U = mu * sum_{u in T_U} r_u (eq. galerkin2),
+// members summed in ascending id order.
+template <class T>
+__global__ void k_restrict_agg(int nc, const int* __restrict__ aptr, const int* __restrict__ mem,
+                               const T* __restrict__ r, T* __restrict__ bc, T mu) {
+  const int U = blockIdx.x * blockDim.x + threadIdx.x;
+  if (U >= nc) return;
+  T s = 0;
+  for (int j = aptr[U]; j < aptr[U + 1]; ++j) s += r[mem[j]];
+  bc[U] = mu * s;
+}
+// Caliber-1 interpolation x_u += e_{agg(u)} (eq. correction).
+template <class T>
+__global__ void k_interp_agg(int n, const int* __restrict__ agg, const T* __restrict__ e, T* __restrict__ x) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u < n) x[u] += e[agg[u]];
+}
+// Elimination restriction P^T r (eq. elim): r_c + sum_{f in F, adjacent}
+// (w_cf / a_ff) r_f in column order.
+template <class T>
+__global__ void k_restrict_elim(int nc, const int* __restrict__ cfine, const int* __restrict__ cidx,
+                                const int* __restrict__ rp, const int* __restrict__ ci, const T* __restrict__ val,
+                                const T* __restrict__ diag, const T* __restrict__ r, T* __restrict__ bc) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  const int u = cfine[c];
+  T s = r[u];
+  for (int t = rp[u]; t < rp[u + 1]; ++t) {
+    const int f = ci[t];
+    if (cidx[f] < 0) s += (val[t] / diag[f]) * r[f];
+  }
+  bc[c] = s;
+}
+// Exact elimination correction: e_C = e^c, e_F = (r_F + W_FC e^c) / a_FF.
+template <class T>
+__global__ void k_interp_elim(int n, const int* __restrict__ cidx, const int* __restrict__ rp, const int* __restrict__ ci,
+                              const T* __restrict__ val, const T* __restrict__ diag, const T* __restrict__ r,
+                              const T* __restrict__ e, T* __restrict__ x) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= n) return;
+  const int c = cidx[u];
+  if (c >= 0) { x[u] += e[c]; return; }
+  T s = r[u];
+  for (int t = rp[u]; t < rp[u + 1]; ++t) s += val[t] * e[cidx[ci[t]]];
+  x[u] += s / diag[u];
+}
+template <class T>
+__global__ void k_fill(T* p, T v, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+static inline dim3 g1(int n, int b = 256) { return dim3((unsigned)std::max(1, (n + b - 1) / b)); }
+
+template <class T>
+void restrict_agg(hipStream_t s, const Level& C, const T* r, T* bc, T mu) {
+  hipLaunchKernelGGL(k_restrict_agg<T>, g1(C.n), dim3(256), 0, s, C.n, C.agg_ptr, C.members, r, bc, mu);
+}
+template <class T>
+void interp_agg(hipStream_t s, const Level& C, int nfine, const T* e, T* x) {
+  hipLaunchKernelGGL(k_interp_agg<T>, g1(nfine), dim3(256), 0, s, nfine, C.agg, e, x);
+}
+template <class T>
+void restrict_elim(hipStream_t s, const Level& F, const Level& C, const T* val, const T* diag, const T* r, T* bc) {
+  hipLaunchKernelGGL(k_restrict_elim<T>, g1(C.n), dim3(256), 0, s, C.n, C.cfine, C.cidx, F.rp, F.ci, val, diag, r, bc);
+}
+template <class T>
+void interp_elim(hipStream_t s, const Level& F, const Level& C, const T* val, const T* diag, const T* r, const T* e,
+                 T* x) {
+  hipLaunchKernelGGL(k_interp_elim<T>, g1(F.n), dim3(256), 0, s, F.n, C.cidx, F.rp, F.ci, val, diag, r, e, x);
+}
+template <class T>
+void fill(hipStream_t s, T* p, T v, int n) {
+  if (n > 0) hipLaunchKernelGGL(k_fill<T>, g1(n), dim3(256), 0, s, p, v, n);
+}
+#define INST(T)                                                                                         \
+  template void restrict_agg<T>(hipStream_t, const Level&, const T*, T*, T);                           \
+  template void interp_agg<T>(hipStream_t, const Level&, int, const T*, T*);                           \
+  template void restrict_elim<T>(hipStream_t, const Level&, const Level&, const T*, const T*, const T*, T*); \
+  template void interp_elim<T>(hipStream_t, const Level&, const Level&, const T*, const T*, const T*, const T*, T*); \
+  template void fill<T>(hipStream_t, T*, T, int);
+INST(double)
+INST(float)
+template void fill<int>(hipStream_t, int*, int, int);
+#undef INST
+
+// ---------------------------------------------------------------- reductions
+// Layout of H->red: [0, RED_BLOCKS * 8) block partials (8 slots each);
+// [RED_BLOCKS * 8, +16) results.
+constexpr int NSLOT = 8;
+static inline double* red_part(Hierarchy* H) { return H->red; }
+static inline double* red_res(Hierarchy* H) { return H->red + k::RED_BLOCKS * NSLOT; }
+
+template <int NV>
+__device__ inline void block_sum_store(double (&v)[NV], double* out) {
+  __shared__ double sh[NV][k::RED_THREADS];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) sh[i][threadIdx.x] = v[i];
+  __syncthreads();
+  for (int w = k::RED_THREADS / 2; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w)
+#pragma unroll
+      for (int i = 0; i < NV; ++i) sh[i][threadIdx.x] += sh[i][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int i = 0; i < NV; ++i) out[i] = sh[i][0];
+}
+
+// Recombination dot products with d_i = R_i - r: G00, G01, G11, g0, g1, r.r
+template <class T>
+__global__ __launch_bounds__(k::RED_THREADS) void k_recomb_dots(int n, int th, const T* __restrict__ r,
+                                                                const T* __restrict__ R0, const T* __restrict__ R1,
+                                                                double* part) {
+  double v[6] = {0, 0, 0, 0, 0, 0};
+  for (int u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += gridDim.x * blockDim.x) {
+    const double ru = (double)r[u];
+    const double d0 = (double)(R0[u] - r[u]);
+    const double d1 = th > 1 ? (double)(R1[u] - r[u]) : 0.0;
+    v[0] += d0 * d0;
+    v[1] += d0 * d1;
+    v[2] += d1 * d1;
+    v[3] += d0 * ru;
+    v[4] += d1 * ru;
+    v[5] += ru * ru;
+  }
+  block_sum_store<6>(v, part + blockIdx.x * NSLOT);
+}
+// Sum the block partials in a fixed order and solve the th x th normal
+// equations of min || r + sum_i alpha_i d_i || (eq. recomb).  A direction is
+// dropped when its Gram entry is negligible or the 2x2 system is singular.
+__global__ void k_recomb_alpha(int nblk, int th, const double* part, double* res) {
+  __shared__ double tot[6];
+  if (threadIdx.x < 6) {
+    double s = 0;
+    for (int b = 0; b < nblk; ++b) s += part[b * NSLOT + threadIdx.x];
+    tot[threadIdx.x] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  const double G00 = tot[0], G01 = tot[1], G11 = tot[2], g0 = tot[3], g1 = tot[4], rr = tot[5];
+  const double tiny = 1e-28 * rr;
+  double a0 = 0, a1 = 0;
+  if (th == 1) {
+    if (G00 > tiny) a0 = -g0 / G00;
+  } else {
+    const double det = G00 * G11 - G01 * G01;
+    if (G00 > tiny && G11 > tiny && det > 1e-12 * G00 * G11) {
+      a0 = (-g0 * G11 + g1 * G01) / det;
+      a1 = (-g1 * G00 + g0 * G01) / det;
+    } else if (G00 >= G11) {
+      if (G00 > tiny) a0 = -g0 / G00;
+    } else {
+      if (G11 > tiny) a1 = -g1 / G11;
+    }
+  }
+  res[0] = a0;
+  res[1] = a1;
+}
+template <class T>
+__global__ void k_recomb_update(int n, int th, const double* __restrict__ res, const T* __restrict__ X0,
+                                const T* __restrict__ X1, T* __restrict__ x) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= n) return;
+  const double a0 = res[0], a1 = res[1];
+  const double xu = (double)x[u];
+  double y = xu;
+  y += a0 * ((double)X0[u] - xu);
+  if (th > 1) y += a1 * ((double)X1[u] - xu);
+  x[u] = (T)y;
+}
+
+static inline int red_grid(int n) {
+  return std::max(1, std::min(k::RED_BLOCKS, (n + k::RED_THREADS - 1) / k::RED_THREADS));
+}
+
+template <class T>
+void recombine(hipStream_t s, Hierarchy* H, const Level& L, Vecs<T>& v, int th) {
+  const T* val;
+  const T* dg;
+  if constexpr (sizeof(T) == 8) { val = (const T*)L.val; dg = (const T*)L.diag; }
+  else { val = (const T*)L.val32; dg = (const T*)L.diag32; }
+  residual<T>(s, L, val, dg, v.b, v.x, v.r);
+  const int nb = red_grid(L.n);
+  hipLaunchKernelGGL(k_recomb_dots<T>, dim3(nb), dim3(k::RED_THREADS), 0, s, L.n, th, v.r, v.R[0], v.R[1],
+                     red_part(H));
+  hipLaunchKernelGGL(k_recomb_alpha, dim3(1), dim3(64), 0, s, nb, th, red_part(H), red_res(H));
+  hipLaunchKernelGGL(k_recomb_update<T>, g1(L.n), dim3(256), 0, s, L.n, th, red_res(H), v.X[0], v.X[1], v.x);
+  LAMG_HIP(hipGetLastError());
+}
+template void recombine<double>(hipStream_t, Hierarchy*, const Level&, Vecs<double>&, int);
+template void recombine<float>(hipStream_t, Hierarchy*, const Level&, Vecs<float>&, int);
+
+template <class T>
+__global__ __launch_bounds__(k::RED_THREADS) void k_sum(int n, const T* __restrict__ x, double* part) {
+  double v[1] = {0};
+  for (int u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += gridDim.x * blockDim.x) v[0] += (double)x[u];
+  block_sum_store<1>(v, part + blockIdx.x * NSLOT);
+}
+template <class T>
+__global__ __launch_bounds__(k::RED_THREADS) void k_sumsq(int n, const T* __restrict__ x, double* part) {
+  double v[1] = {0};
+  for (int u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += gridDim.x * blockDim.x) {
+    const double t = (double)x[u];
+    v[0] += t * t;
+  }
+  block_sum_store<1>(v, part + blockIdx.x * NSLOT);
+}
+__global__ void k_finish(int nblk, const double* part, double* res, int slot, double scale) {
+  if (threadIdx.x != 0) return;
+  double s = 0;
+  for (int b = 0; b < nblk; ++b) s += part[b * NSLOT];
+  res[slot] = s * scale;
+}
+template <class T>
+__global__ void k_sub_mean(int n, const double* __restrict__ res, int slot, T* __restrict__ x) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u < n) x[u] = (T)((double)x[u] - res[slot]);
+}
+
+template <class T>
+void subtract_mean(hipStream_t s, Hierarchy* H, T* x, int n) {
+  const int nb = red_grid(n);
+  hipLaunchKernelGGL(k_sum<T>, dim3(nb), dim3(k::RED_THREADS), 0, s, n, x, red_part(H));
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, s, nb, red_part(H), red_res(H), 4, 1.0 / (double)n);
+  hipLaunchKernelGGL(k_sub_mean<T>, g1(n), dim3(256), 0, s, n, red_res(H), 4, x);
+  LAMG_HIP(hipGetLastError());
+}
+template void subtract_mean<double>(hipStream_t, Hierarchy*, double*, int);
+template void subtract_mean<float>(hipStream_t, Hierarchy*, float*, int);
+
+// ||r||^2 into the pinned host slot (copied asynchronously; caller syncs).
+void norm2_async(hipStream_t s, Hierarchy* H, const double* r, int n, double* dst_host) {
+  const int nb = red_grid(n);
+  hipLaunchKernelGGL(k_sumsq<double>, dim3(nb), dim3(k::RED_THREADS), 0, s, n, r, red_part(H));
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, s, nb, red_part(H), red_res(H), 5, 1.0);
+  LAMG_HIP(hipMemcpyAsync(dst_host, red_res(H) + 5, sizeof(double), hipMemcpyDeviceToHost, s));
+}
+
+// --------------------------------------------------------------- coarsest
+// x = M^-1 b with M = A_L + (mean diag / n_L) 1 1^T, whose inverse is formed
+// at setup.  One workgroup; b staged in LDS.
+template <class T>
+__global__ __launch_bounds__(256) void k_dense_solve(int n, const double* __restrict__ Minv, const T* __restrict__ b,
+                                                     T* __restrict__ x) {
+  extern __shared__ double sb[];
+  for (int j = threadIdx.x; j < n; j += blockDim.x) sb[j] = (double)b[j];
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    double s = 0;
+    const double* row = Minv + (size_t)i * n;
+    for (int j = 0; j < n; ++j) s += row[j] * sb[j];
+    x[i] = (T)s;
+  }
+}
+void coarsest_solve(hipStream_t s, Hierarchy* H, const double* b, double* x) {
+  hipLaunchKernelGGL(k_dense_solve<double>, dim3(1), dim3(256), H->nL * sizeof(double), s, H->nL, H->cinv, b, x);
+}
+void coarsest_solve32(hipStream_t s, Hierarchy* H, const float* b, float* x) {
+  hipLaunchKernelGGL(k_dense_solve<float>, dim3(1), dim3(256), H->nL * sizeof(double), s, H->nL, H->cinv, b, x);
+}
+
+// Dense augmented matrix, Cholesky factor and inverse (single workgroup).
+__global__ void k_dense_build(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                              const double* __restrict__ val, const double* __restrict__ diag, double* M) {
+  __shared__ double cfac;
+  if (threadIdx.x == 0) {
+    double s = 0;
+    for (int u = 0; u < n; ++u) s += diag[u];
+    double dbar = s / (double)n;
+    if (!(dbar > 0)) dbar = 1.0;
+    cfac = dbar / (double)n;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n * n; i += blockDim.x) M[i] = cfac;
+  __syncthreads();
+  for (int u = threadIdx.x; u < n; u += blockDim.x) {
+    M[(size_t)u * n + u] += diag[u];
+    for (int t = rp[u]; t < rp[u + 1]; ++t) M[(size_t)u * n + ci[t]] -= val[t];
+  }
+}
+__global__ void k_cholesky_inverse(int n, double* M, double* Y, double* Minv) {
+  for (int j = 0; j < n; ++j) {
+    if (threadIdx.x == 0) M[(size_t)j * n + j] = sqrt(M[(size_t)j * n + j]);
+    __syncthreads();
+    const double djj = M[(size_t)j * n + j];
+    for (int i = j + 1 + threadIdx.x; i < n; i += blockDim.x) M[(size_t)i * n + j] /= djj;
+    __syncthreads();
+    const int m = n - j - 1;
+    for (int p = threadIdx.x; p < m * m; p += blockDim.x) {
+      const int i = j + 1 + p / m, kk = j + 1 + p % m;
+      if (kk <= i) M[(size_t)i * n + kk] -= M[(size_t)i * n + j] * M[(size_t)kk * n + j];
+    }
+    __syncthreads();
+  }
+  // column t of the inverse: L y = e_t, L^T z = y
+  for (int t = threadIdx.x; t < n; t += blockDim.x) {
+    double* y = Y + (size_t)t * n;
+    for (int i = 0; i < n; ++i) {
+      double s = (i == t) ? 1.0 : 0.0;
+      for (int q = 0; q < i; ++q) s -= M[(size_t)i * n + q] * y[q];
+      y[i] = s / M[(size_t)i * n + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      double s = y[i];
+      for (int q = i + 1; q < n; ++q) s -= M[(size_t)q * n + i] * y[q];
+      y[i] = s / M[(size_t)i * n + i];
+    }
+    for (int i = 0; i < n; ++i) Minv[(size_t)i * n + t] = y[i];
+  }
+}
+
+void coarsest_factor(Hierarchy* H, const Level& L) {
+  const int n = L.n;
+  H->nL = n;
+  double* M = dnew<double>(H, (size_t)n * n);
+  double* Y = dnew<double>(H, (size_t)n * n);
+  H->cinv = dnew<double>(H, (size_t)n * n);
+  hipLaunchKernelGGL(k_dense_build, dim3(1), dim3(256), 0, H->s, n, L.rp, L.ci, L.val, L.diag, M);
+  hipLaunchKernelGGL(k_cholesky_inverse, dim3(1), dim3(256), 0, H->s, n, M, Y, H->cinv);
+  LAMG_HIP(hipGetLastError());
+}
+
+}  // namespace lamg

@@ -1,0 +1,270 @@
+"""Python binding of the LAMG HIP library (include/lamg.h, include/lamg_test.h).
+
+Argument marshalling only: every step of setup and solve runs in the HIP
+kernels of ``libpaper_lamg.so``.  PyTorch supplies device memory and the
+current stream.  There is no CPU fallback: loading fails loudly when the
+library is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpaper_lamg.so")
+
+OK, E_INVALID_ARG, E_BAD_WEIGHT, E_NOT_CONNECTED, E_NOT_CONVERGED, E_BREAKDOWN, E_OUT_OF_MEMORY, E_DEVICE = range(8)
+FP64, FP32_REFINE = 0, 1
+EC_RECOMBINE, EC_FLAT_MU = 0, 1
+
+
+class Options(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("gamma", C.c_double), ("nu_pre", C.c_int), ("nu_post", C.c_int),
+                ("tv_k_min", C.c_int), ("tv_k_max", C.c_int), ("tv_sweeps", C.c_int),
+                ("q_max", C.c_double), ("mu", C.c_double), ("hub_factor", C.c_double),
+                ("elim_max_degree", C.c_int), ("coarsest_max_n", C.c_int),
+                ("weak_edge_ratio", C.c_double), ("elim_stop_frac", C.c_double), ("stage1_quantile", C.c_double),
+                ("ec", C.c_int), ("precision", C.c_int), ("tol", C.c_double), ("max_cycles", C.c_int),
+                ("warm_start", C.c_int), ("seed", C.c_uint64), ("stream", C.c_void_p)]
+
+
+class Info(C.Structure):
+    _fields_ = [("cycles", C.c_int32), ("levels", C.c_int32), ("rel_residual", C.c_double), ("acf", C.c_double),
+                ("removed_mean", C.c_double), ("setup_ms", C.c_double), ("solve_ms", C.c_double),
+                ("bytes_moved", C.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class LamgError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {lib().lamg_status_str(status).decode()} (status {status})")
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"LAMG HIP library not built: {LIB_PATH} (run __graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, u64, d = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_double
+        sig = {
+            "lamg_options_default": (None, [C.POINTER(Options)]),
+            "lamg_setup": (C.c_int, [i64, i64, vp, vp, vp, C.POINTER(Options), C.POINTER(vp)]),
+            "lamg_solve": (C.c_int, [vp, vp, vp, C.POINTER(Info)]),
+            "lamg_solve_batch": (C.c_int, [i32, C.POINTER(vp), C.POINTER(i32), C.POINTER(vp), C.POINTER(vp),
+                                           C.POINTER(Info)]),
+            "lamg_set_solve_options": (C.c_int, [vp, C.POINTER(Options)]),
+            "lamg_free": (None, [vp]),
+            "lamg_status_str": (C.c_char_p, [C.c_int]),
+            "lamg_t_num_levels": (C.c_int, [vp]),
+            "lamg_t_level_dims": (C.c_int, [vp, C.c_int, C.POINTER(i64)]),
+            "lamg_t_level_gamma": (d, [vp, C.c_int]),
+            "lamg_t_level_export": (C.c_int, [vp, C.c_int, vp, vp, vp, vp, vp, vp]),
+            "lamg_t_transfer_export": (C.c_int, [vp, C.c_int, vp]),
+            "lamg_t_agg_export": (C.c_int, [vp, C.c_int, vp, vp, vp, vp, vp, vp, vp]),
+            "lamg_t_cycle": (C.c_int, [vp, vp, vp]),
+            "lamg_t_coarsest_solve": (C.c_int, [vp, vp, vp]),
+            "lamg_t_gs": (C.c_int, [i32, vp, vp, vp, vp, i32, vp, vp, vp, i32, vp]),
+            "lamg_t_gs32": (C.c_int, [i32, vp, vp, vp, vp, i32, vp, vp, vp, i32, vp]),
+            "lamg_t_residual": (C.c_int, [i32, vp, vp, vp, vp, vp, vp, vp, vp]),
+            "lamg_t_colour": (C.c_int, [i32, vp, vp, u64, i32, vp, vp]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols() -> list[str]:
+    return [n for n in ("lamg_options_default", "lamg_setup", "lamg_solve", "lamg_solve_batch",
+                        "lamg_set_solve_options", "lamg_free", "lamg_status_str") if hasattr(lib(), n)]
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _check(rc: int, where: str):
+    if rc != OK:
+        raise LamgError(rc, where)
+
+
+def options(**kw) -> Options:
+    o = Options()
+    lib().lamg_options_default(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def _dev(t, dtype):
+    if not isinstance(t, torch.Tensor):
+        t = torch.as_tensor(np.asarray(t))
+    return t.to(device="cuda", dtype=dtype).contiguous()
+
+
+class Hierarchy:
+    """A LAMG hierarchy of the Laplacian of a weighted undirected graph.
+
+    ``eu, ev`` (int32) and ``w`` (float64) describe the edges (any order;
+    duplicates of a pair are summed).  Arrays are moved to the GPU if needed.
+    """
+
+    def __init__(self, n: int, eu, ev, w, **opts):
+        eu, ev, w = _dev(eu, torch.int32), _dev(ev, torch.int32), _dev(w, torch.float64)
+        self.opts = options(stream=_stream(), **opts)
+        h = C.c_void_p()
+        rc = lib().lamg_setup(int(n), int(eu.numel()), _ptr(eu), _ptr(ev), _ptr(w), C.byref(self.opts), C.byref(h))
+        _check(rc, "lamg_setup")
+        self.h = h
+        self.n = int(n)
+        self.m = int(eu.numel())
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().lamg_free(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def set_solve_options(self, **kw):
+        for k, v in kw.items():
+            setattr(self.opts, k, v)
+        self.opts.stream = _stream()
+        _check(lib().lamg_set_solve_options(self.h, C.byref(self.opts)), "lamg_set_solve_options")
+
+    def solve(self, b, x=None, check: bool = True, **kw):
+        """Solve A x = b - mean(b).  Returns (x, info dict)."""
+        if kw:
+            self.set_solve_options(**kw)
+        b = _dev(b, torch.float64)
+        warm = x is not None
+        x = _dev(x, torch.float64).clone() if warm else torch.empty(self.n, dtype=torch.float64, device="cuda")
+        if bool(self.opts.warm_start) != warm:
+            self.set_solve_options(warm_start=int(warm))
+        info = Info()
+        rc = lib().lamg_solve(self.h, _ptr(b), _ptr(x), C.byref(info))
+        if check and rc not in (OK, E_NOT_CONVERGED):
+            _check(rc, "lamg_solve")
+        d = info.as_dict()
+        d["status"] = rc
+        return x, d
+
+    # ------------------------------------------------------ inspection (tests)
+    @property
+    def num_levels(self) -> int:
+        return lib().lamg_t_num_levels(self.h)
+
+    def dims(self, l: int) -> dict:
+        d = (C.c_int64 * 8)()
+        _check(lib().lamg_t_level_dims(self.h, l, d), "lamg_t_level_dims")
+        return dict(n=d[0], nnz=d[1], type=d[2], ncol=d[3], nF=d[4], K=d[5], stage=d[6], nlong=d[7],
+                    gamma=float(lib().lamg_t_level_gamma(self.h, l)))
+
+    def level(self, l: int) -> dict:
+        d = self.dims(l)
+        n, nnz, ncol = d["n"], d["nnz"], d["ncol"]
+        rp = np.zeros(n + 1, np.int32)
+        ci = np.zeros(nnz, np.int32)
+        val = np.zeros(nnz)
+        diag = np.zeros(n)
+        cptr = np.zeros(ncol + 1, np.int32)
+        perm = np.zeros(n, np.int32)
+        vp = lambda a: C.c_void_p(a.ctypes.data)
+        _check(lib().lamg_t_level_export(self.h, l, vp(rp), vp(ci), vp(val), vp(diag), vp(cptr), vp(perm)),
+               "lamg_t_level_export")
+        d.update(rp=rp, ci=ci, val=val, diag=diag, cptr=cptr, perm=perm)
+        if l > 0:
+            tr = np.zeros(self.dims(l - 1)["n"], np.int32)
+            _check(lib().lamg_t_transfer_export(self.h, l, vp(tr)), "lamg_t_transfer_export")
+            d["transfer"] = tr
+        return d
+
+    def agg_diag(self, l: int) -> dict:
+        d = self.dims(l)
+        n, nnz, K = d["n"], d["nnz"], d["K"]
+        tv = np.zeros(n * K)
+        aff = np.zeros(nnz)
+        ok = np.zeros(nnz, np.uint8)
+        weak = np.zeros(nnz, np.uint8)
+        hub = np.zeros(n, np.uint8)
+        st = np.zeros(n, np.int32)
+        scal = np.zeros(4)
+        vp = lambda a: C.c_void_p(a.ctypes.data)
+        _check(lib().lamg_t_agg_export(self.h, l, vp(tv), vp(aff), vp(ok), vp(weak), vp(hub), vp(st), vp(scal)),
+               "lamg_t_agg_export")
+        return dict(tv=tv.reshape(n, K), aff=aff, ok=ok, weak=weak, hub=hub, state=st, delta1=scal[0],
+                    alpha1=scal[1], alpha2=scal[2], stage=int(scal[3]), K=K)
+
+    def cycle(self, b_perm, x_perm):
+        b = _dev(b_perm, torch.float64)
+        x = _dev(x_perm, torch.float64).clone()
+        _check(lib().lamg_t_cycle(self.h, _ptr(b), _ptr(x)), "lamg_t_cycle")
+        return x
+
+    def coarsest_solve(self, b):
+        b = _dev(b, torch.float64)
+        x = torch.zeros_like(b)
+        _check(lib().lamg_t_coarsest_solve(self.h, _ptr(b), _ptr(x)), "lamg_t_coarsest_solve")
+        return x
+
+
+def solve_batch(hs: list[Hierarchy], Bs: list, Xs: list | None = None):
+    """Batched solves: Bs[i] is [n_i] or [n_i, k_i] (row-major)."""
+    cnt = len(hs)
+    Bd = [_dev(b, torch.float64) for b in Bs]
+    warm = Xs is not None
+    Xd = [_dev(x, torch.float64).clone() for x in Xs] if warm else [torch.empty_like(b) for b in Bd]
+    for h in hs:
+        if bool(h.opts.warm_start) != warm:
+            h.set_solve_options(warm_start=int(warm))
+    nrhs = (C.c_int32 * cnt)(*[1 if b.dim() == 1 else b.shape[1] for b in Bd])
+    hp = (C.c_void_p * cnt)(*[h.h.value for h in hs])
+    bp = (C.c_void_p * cnt)(*[b.data_ptr() for b in Bd])
+    xp = (C.c_void_p * cnt)(*[x.data_ptr() for x in Xd])
+    infos = (Info * cnt)()
+    rc = lib().lamg_solve_batch(cnt, hp, nrhs, bp, xp, infos)
+    if rc not in (OK, E_NOT_CONVERGED):
+        _check(rc, "lamg_solve_batch")
+    return Xd, [i.as_dict() for i in infos], rc
+
+
+# ------------------------------------------------------------ kernel entries
+def gs(rp, ci, val, diag, cptr, b, x, sweeps=1):
+    """Multicolour GS sweeps on a colour-major DEVICE CSR (test entry point)."""
+    n = x.numel()
+    cp = np.ascontiguousarray(cptr, np.int32)
+    f = lib().lamg_t_gs if x.dtype == torch.float64 else lib().lamg_t_gs32
+    _check(f(n, _ptr(rp), _ptr(ci), _ptr(val), _ptr(diag), cp.shape[0] - 1, C.c_void_p(cp.ctypes.data), _ptr(b),
+             _ptr(x), sweeps, _stream()), "lamg_t_gs")
+    return x
+
+
+def residual(rp, ci, val, diag, b, x):
+    r = torch.empty_like(x)
+    _check(lib().lamg_t_residual(x.numel(), _ptr(rp), _ptr(ci), _ptr(val), _ptr(diag), _ptr(b), _ptr(x), _ptr(r),
+                                 _stream()), "lamg_t_residual")
+    return r
+
+
+def colour(rp, ci, n, seed=0, level=0):
+    out = torch.empty(n, dtype=torch.int32, device="cuda")
+    _check(lib().lamg_t_colour(n, _ptr(rp), _ptr(ci), seed, level, _ptr(out), _stream()), "lamg_t_colour")
+    return out

@@ -1,0 +1,213 @@
+"""Parity of the HIP path with the CPU oracle on identical seeded inputs.
+
+Integer outputs (colours, node orders, elimination sets, aggregates, coarse
+sparsity) must agree bit for bit.  Every floating-point value that feeds a
+decision is computed in the same order on both sides, so values are
+compared bit for bit as well; solve results are compared through the
+relative residual (<= tol) and the distance between the two solutions.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_1108_1310_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _graphs():
+    from test_oracle_pins import random_graph
+    out = {}
+    eu, ev, w = random_graph(3000, 6000, 7)
+    out["random3k"] = (3000, eu, ev, w)
+    g = W.grid2d(64)
+    out["grid64"] = (g.n, g.eu, g.ev, g.w)
+    g = W.chung_lu(1 << 14)
+    out["chung_lu16k"] = (g.n, g.eu, g.ev, g.w)
+    g = W.rgg(1 << 14)
+    out["rgg16k"] = (g.n, g.eu, g.ev, g.w)
+    g = W.grid3d_aniso(16)
+    out["grid3d16"] = (g.n, g.eu, g.ev, g.w)
+    return out
+
+
+GRAPHS = None
+
+
+def graphs():
+    global GRAPHS
+    if GRAPHS is None:
+        GRAPHS = _graphs()
+    return GRAPHS
+
+
+@pytest.fixture(scope="module")
+def lg():
+    from paper_1108_1310_amd import lamg
+    lamg.lib()
+    return lamg
+
+
+def _print_case(name):
+    print(f"[case] {name}", flush=True)
+
+
+@pytest.mark.parametrize("name", ["random3k", "grid64", "chung_lu16k", "rgg16k", "grid3d16"])
+def test_hierarchy_bit_exact(ora, lg, name):
+    _print_case(name)
+    n, eu, ev, w = graphs()[name]
+    Ho = ora.Hierarchy(n, eu, ev, w)
+    Hg = lg.Hierarchy(n, eu, ev, w)
+    assert Hg.num_levels == Ho.num_levels
+    for l in range(Ho.num_levels):
+        do, dg = Ho.dims(l), Hg.dims(l)
+        for k in ("n", "nnz", "type", "ncol", "nF", "K", "stage"):
+            assert do[k] == dg[k], (l, k, do[k], dg[k])
+        assert do["gamma"] == dg["gamma"]
+        Lo, Lg = Ho.level(l), Hg.level(l)
+        assert np.array_equal(Lo.A.ptr, Lg["rp"]), l
+        assert np.array_equal(Lo.A.col, Lg["ci"]), l
+        assert np.array_equal(Lo.cptr, Lg["cptr"]), l
+        assert np.array_equal(Lo.perm, Lg["perm"]), l
+        assert np.array_equal(Lo.A.val, Lg["val"]), l
+        assert np.array_equal(Lo.A.diag, Lg["diag"]), l
+        if l > 0:
+            assert np.array_equal(Lo.transfer, Lg["transfer"]), l
+        if l + 1 < Ho.num_levels and Ho.dims(l + 1)["type"] == 2:
+            Do, Dg = Ho.agg_diag(l), Hg.agg_diag(l)
+            assert np.array_equal(Do["tv"], Dg["tv"]), l
+            assert np.array_equal(Do["aff"], Dg["aff"]), l
+            for k in ("ok", "weak", "hub", "state"):
+                assert np.array_equal(Do[k], Dg[k]), (l, k)
+            for k in ("delta1", "alpha1", "alpha2", "stage"):
+                assert Do[k] == Dg[k], (l, k)
+
+
+def test_colouring_kernel_bit_exact(ora, lg):
+    _print_case("colour random3k")
+    n, eu, ev, w = graphs()["random3k"]
+    A = ora.laplacian(n, eu, ev, w)
+    rp = torch.tensor(A.ptr.astype(np.int32), device="cuda")
+    ci = torch.tensor(A.col, device="cuda")
+    for seed, level in ((0, 0), (5, 3)):
+        cg = lg.colour(rp, ci, n, seed=seed, level=level).cpu().numpy()
+        assert np.array_equal(cg, ora.colour(A, seed=seed, level=level))
+
+
+@pytest.mark.parametrize("name", ["grid64", "chung_lu16k"])
+def test_relaxation_kernels_bit_exact(ora, lg, name):
+    """Multicolour GS sweeps (FP64, FP32) and the residual on the oracle's
+    colour-ordered finest level, including rows longer than 64 entries."""
+    _print_case(name)
+    n, eu, ev, w = graphs()[name]
+    Ho = ora.Hierarchy(n, eu, ev, w)
+    L = Ho.level(0)
+    A = L.A
+    rng = np.random.default_rng(1)
+    b = rng.standard_normal(n)
+    x0 = rng.standard_normal(n)
+    d = lambda a, t=torch.float64: torch.tensor(a, dtype=t, device="cuda")
+    rp, ci = d(A.ptr.astype(np.int32), torch.int32), d(A.col, torch.int32)
+    xg = lg.gs(rp, ci, d(A.val), d(A.diag), L.cptr, d(b), d(x0), sweeps=3).cpu().numpy()
+    xo = ora.gs(A, b, x0, sweeps=3)
+    assert np.array_equal(xg, xo)
+    rg = lg.residual(rp, ci, d(A.val), d(A.diag), d(b), d(xo)).cpu().numpy()
+    assert np.array_equal(rg, ora.residual(A, b, xo))
+    v32, d32 = A.val.astype(np.float32), A.diag.astype(np.float32)
+    xg32 = lg.gs(rp, ci, d(v32, torch.float32), d(d32, torch.float32), L.cptr, d(b, torch.float32),
+                 d(x0, torch.float32), sweeps=2).cpu().numpy()
+    xo32 = ora.gs32(A, v32, d32, b.astype(np.float32), x0.astype(np.float32), sweeps=2)
+    assert np.array_equal(xg32, xo32)
+
+
+@pytest.mark.parametrize("name", ["random3k", "grid64", "chung_lu16k", "rgg16k"])
+def test_one_cycle_matches_oracle(ora, lg, name):
+    _print_case(name)
+    n, eu, ev, w = graphs()[name]
+    Ho = ora.Hierarchy(n, eu, ev, w)
+    Hg = lg.Hierarchy(n, eu, ev, w)
+    rng = np.random.default_rng(3)
+    b = rng.standard_normal(n)
+    b -= b.mean()
+    x0 = np.zeros(n)
+    xo = Ho.cycle(b, x0)
+    xg = Hg.cycle(b, x0).cpu().numpy()
+    assert np.linalg.norm(xg - xo) <= 1e-12 * np.linalg.norm(xo)
+    xo2 = Ho.cycle(b, xo)
+    xg2 = Hg.cycle(b, xg).cpu().numpy()
+    assert np.linalg.norm(xg2 - xo2) <= 1e-11 * np.linalg.norm(xo2)
+
+
+@pytest.mark.parametrize("name", ["random3k", "grid64", "chung_lu16k", "rgg16k", "grid3d16"])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_solve_matches_oracle(ora, lg, name, precision):
+    _print_case(f"{name} precision={precision}")
+    n, eu, ev, w = graphs()[name]
+    Ho = ora.Hierarchy(n, eu, ev, w)
+    Hg = lg.Hierarchy(n, eu, ev, w)
+    b = W.rhs_normal(n, 1, 11) + 0.25
+    xo, io, _ = Ho.solve(b, precision=precision)
+    xg, ig = Hg.solve(torch.tensor(b, device="cuda"), precision=precision)
+    xg = xg.cpu().numpy()
+    assert ig["status"] == 0 and io["status"] == 0
+    assert ig["rel_residual"] <= 1e-8
+    A = ora.laplacian(n, eu, ev, w)
+    bp = b - b.mean()
+    r = ora.residual(A, bp, xg)
+    assert np.linalg.norm(r) <= 1.0000001e-8 * np.linalg.norm(bp)
+    assert abs(xg.mean()) <= 1e-12 * np.abs(xg).max()
+    assert abs(ig["removed_mean"] - b.mean()) <= 1e-15
+    assert abs(ig["cycles"] - io["cycles"]) <= 1
+    assert np.linalg.norm(xg - xo) <= 1e-6 * np.linalg.norm(xo)
+
+
+def test_coarsest_solve_matches(ora, lg):
+    _print_case("coarsest")
+    n, eu, ev, w = graphs()["grid64"]
+    Ho = ora.Hierarchy(n, eu, ev, w)
+    Hg = lg.Hierarchy(n, eu, ev, w)
+    nL = Ho.dims(Ho.num_levels - 1)["n"]
+    b = np.random.default_rng(2).standard_normal(nL)
+    b -= b.mean()
+    xo = Ho.coarsest_solve(b)
+    xg = Hg.coarsest_solve(torch.tensor(b, device="cuda")).cpu().numpy()
+    assert np.linalg.norm(xg - xo) <= 1e-10 * np.linalg.norm(xo)
+
+
+def test_input_errors(lg):
+    _print_case("errors")
+    d = lambda a, t: torch.tensor(a, dtype=t, device="cuda")
+    cases = [
+        (4, [0, 1], [1, 4], [1.0, 1.0], lg.E_INVALID_ARG),    # index out of range
+        (4, [0, 1], [1, 1], [1.0, 1.0], lg.E_INVALID_ARG),    # self-loop
+        (3, [0, 1], [1, 2], [1.0, -1.0], lg.E_BAD_WEIGHT),    # negative weight
+        (3, [0, 1], [1, 2], [1.0, float("nan")], lg.E_BAD_WEIGHT),
+        (4, [0, 2], [1, 3], [1.0, 1.0], lg.E_NOT_CONNECTED),  # two components
+    ]
+    for n, eu, ev, w, want in cases:
+        with pytest.raises(lg.LamgError) as ei:
+            lg.Hierarchy(n, d(eu, torch.int32), d(ev, torch.int32), d(w, torch.float64))
+        assert ei.value.status == want
+    # a single node and a single edge are valid problems
+    H = lg.Hierarchy(1, d([], torch.int32), d([], torch.int32), d([], torch.float64))
+    x, info = H.solve(torch.tensor([3.0], device="cuda"))
+    assert x.item() == 0.0 and info["status"] == 0
+    H = lg.Hierarchy(2, d([0], torch.int32), d([1], torch.int32), d([2.0], torch.float64))
+    x, info = H.solve(torch.tensor([1.0, -1.0], device="cuda"))
+    assert np.allclose(x.cpu().numpy(), [0.25, -0.25], atol=1e-14)
+    # non-finite right-hand side: breakdown, reported not raised
+    x, info = H.solve(torch.tensor([float("nan"), 1.0], device="cuda"), check=False)
+    assert info["status"] == lg.E_BREAKDOWN
+
+
+def test_multi_rhs_equals_single(ora, lg):
+    _print_case("multi-rhs")
+    n, eu, ev, w = graphs()["grid64"]
+    Hg = lg.Hierarchy(n, eu, ev, w)
+    B = W.rhs_normal(n, 4, 5)
+    X, infos, rc = lg.solve_batch([Hg], [torch.tensor(B, device="cuda")])
+    assert rc == 0
+    X = X[0].cpu().numpy()
+    for j in range(4):
+        xj, ij = Hg.solve(torch.tensor(B[:, j].copy(), device="cuda"))
+        assert np.linalg.norm(X[:, j] - xj.cpu().numpy()) <= 1e-12 * np.linalg.norm(X[:, j])
