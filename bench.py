@@ -1,0 +1,168 @@
+"""LAMG solve benchmark on one MI355X.
+
+One step = one complete solve of A x = b to a relative residual of 1e-8 on
+the Chung-Lu power-law graph (n0 = 2^20, exponent 2.1, mean degree 16,
+largest component, weights U[0.1, 1], one zero-sum N(0,1) right-hand side),
+with the hierarchy built once beforehand (setup is reported separately).
+The FP64 path is the headline; FP32 cycles with FP64 refinement are timed on
+the same hierarchy and reported beside it.
+
+value = edges * cycles / second over the timed steps (edges = m of the input
+graph); GB/s = algorithmic bytes of the timed cycles / time.  The roofline
+object covers the dominant kernel (the multicolour Gauss-Seidel relaxation),
+timed live with HIP events around each of its launches on the solve stream.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=5)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--workload", default="chung_lu_2p20", choices=["chung_lu_2p20", "grid2d_64", "rgg_2p20"])
+    p.add_argument("--no-cpu", action="store_true", help="skip the CPU reference baseline")
+    p.add_argument("--no-fp32", action="store_true")
+    return p.parse_args()
+
+
+def workload(name):
+    from paper_1108_1310_amd import workloads as W
+    g, b = W.config(name)
+    return g, b
+
+
+def timed_solves(H, b, precision, steps, warmup, lamg):
+    import torch
+    H.set_solve_options(precision=precision)
+    for _ in range(warmup):
+        H.solve(b)
+    torch.cuda.synchronize()
+    kid = 0 if precision == lamg.FP64 else 2
+    lamg.prof_enable(True)
+    cycles, byts, worst = 0, 0, 0.0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        x, info = H.solve(b)
+        cycles += info["cycles"]
+        byts += info["bytes_moved"]
+        worst = max(worst, info["rel_residual"])
+        if info["status"] != 0:
+            raise RuntimeError(f"solve status {info['status']}")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = lamg.prof_read(kid)
+    lamg.prof_enable(False)
+    return dict(seconds=dt, cycles=cycles, bytes=byts, rel_residual=worst, prof=prof, x=x)
+
+
+def cpu_baseline(name):
+    """The CPU reference (serial C++) on a bounded sample of the same workload recipe."""
+    from oracle import oracle as O
+    from paper_1108_1310_amd import workloads as W
+    if name == "chung_lu_2p20":
+        g = W.chung_lu(1 << 17)
+        b = W.rhs_normal(g.n, 1, W.SEEDS["chung_lu"])
+        sample = "Chung-Lu recipe at n0 = 2^17 (1/8 of the workload), FP64 solve to 1e-8, 1 thread"
+    elif name == "rgg_2p20":
+        g = W.rgg(1 << 17)
+        b = W.rhs_normal(g.n, 1, W.SEEDS["rgg"])
+        sample = "RGG recipe at 2^17 points, FP64 solve to 1e-8, 1 thread"
+    else:
+        g, b = W.config(name)
+        sample = "full workload, FP64 solve to 1e-8, 1 thread"
+    H = O.Hierarchy(g.n, g.eu, g.ev, g.w)
+    t0 = time.perf_counter()
+    x, info, _ = H.solve(b)
+    dt = time.perf_counter() - t0
+    return {"value": g.m * info["cycles"] / dt, "unit": "edges*cycles/s", "cores": 1, "kind": "oracle",
+            "sample": sample, "cycles": info["cycles"], "solve_s": dt, "edges": g.m}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU path is not part of "
+              "this build", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1108_1310_amd import lamg
+    torch.cuda.set_device(0)
+    print(f"[bench] generating {a.workload}", file=sys.stderr, flush=True)
+    g, b = workload(a.workload)
+    bd = torch.tensor(b, device="cuda")
+    print(f"[bench] setup n={g.n} m={g.m}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    H = lamg.Hierarchy(g.n, g.eu, g.ev, g.w)
+    torch.cuda.synchronize()
+    setup_ms = (time.perf_counter() - t0) * 1e3
+    levels = [H.dims(l) for l in range(H.num_levels)]
+    print(f"[bench] setup {setup_ms:.1f} ms, {len(levels)} levels", file=sys.stderr, flush=True)
+
+    r64 = timed_solves(H, bd, lamg.FP64, a.steps, a.warmup, lamg)
+    print(f"[bench] fp64 {r64['seconds']:.3f}s cycles={r64['cycles']}", file=sys.stderr, flush=True)
+    out32 = None
+    if not a.no_fp32:
+        r32 = timed_solves(H, bd, lamg.FP32_REFINE, a.steps, a.warmup, lamg)
+        x64 = r64["x"].double()
+        err = float(torch.linalg.norm(r32["x"] - x64) / torch.linalg.norm(x64))
+        out32 = {"value": g.m * r32["cycles"] / r32["seconds"], "ms_per_step": r32["seconds"] * 1e3 / a.steps,
+                 "cycles_per_solve": r32["cycles"] / a.steps, "gbps": r32["bytes"] / r32["seconds"] / 1e9,
+                 "rel_residual": r32["rel_residual"], "err_vs_fp64": err,
+                 "gs_kernel": {"gbps": r32["prof"]["bytes"] / (r32["prof"]["ms"] * 1e6) if r32["prof"]["ms"] else None,
+                               "avg_us": 1e3 * r32["prof"]["ms"] / max(1, r32["prof"]["launches"]),
+                               "launches_per_step": r32["prof"]["launches"] / a.steps}}
+        print(f"[bench] fp32+refine {r32['seconds']:.3f}s cycles={r32['cycles']}", file=sys.stderr, flush=True)
+
+    p = r64["prof"]
+    achieved = p["bytes"] / (p["ms"] * 1e6) if p["ms"] > 0 else 0.0
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_relax<double,0> (multicolour GS)",
+                "avg_launch_us": 1e3 * p["ms"] / max(1, p["launches"]), "launches": p["launches"],
+                "bytes_per_launch": p["bytes"] / max(1, p["launches"])}
+    cpu = None
+    if not a.no_cpu:
+        print("[bench] cpu baseline", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(a.workload)
+    value = g.m * r64["cycles"] / r64["seconds"]
+    rec = {
+        "metric": "edges*cycles/s to 1e-8 rel. residual (FP64; FP32+refine beside)",
+        "value": value,
+        "unit": "edges*cycles/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": r64["seconds"] * 1e3 / a.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": a.workload, "n": g.n, "m": g.m, "precision": "fp64", "tol": 1e-8,
+                   "levels": len(levels), "setup_ms": setup_ms},
+        "gbps": r64["bytes"] / r64["seconds"] / 1e9,
+        "cycles_per_solve": r64["cycles"] / a.steps,
+        "rel_residual": r64["rel_residual"],
+        "edges_solved_per_s": g.m * a.steps / r64["seconds"],
+        "fp32_refine": out32,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -57,6 +57,11 @@ typedef struct lamg_options {
   double weak_edge_ratio;   /* edge weak if w < ratio * max neighbouring weight, 1e-3 */
   double elim_stop_frac;    /* stop eliminating when |F| < frac * n, 0.05 */
   double stage1_quantile;   /* stage-1 affinity threshold quantile, 1.0 */
+  double relax_fast_ratio;  /* stop coarsening when the last test-vector sweep
+                               leaves at most this fraction of the energy, 0.1
+                               (Section 4.1: "until relaxation converges rapidly") */
+  int coarsest_sweeps;      /* GS sweeps solving such a coarsest level, 3 */
+  int dense_max;            /* largest coarsest level solved densely, 8192 */
   lamg_energy_correction ec;
   lamg_precision precision;
   double tol;               /* relative residual target, 1e-8 */

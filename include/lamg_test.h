@@ -20,6 +20,9 @@ extern "C" {
 /* Number of levels of a hierarchy (>= 1). */
 int lamg_t_num_levels(lamg_handle h);
 
+/* 1 when the coarsest level is solved by relaxation sweeps, 0 when densely. */
+int lamg_t_coarsest_relax(lamg_handle h);
+
 /* dims[8] HOST: n, nnz (directed off-diagonal entries), type (0 finest,
  * 1 produced by elimination, 2 produced by aggregation), colours, |F| of the
  * elimination that produced it, test vectors K used when aggregating it,
@@ -42,8 +45,9 @@ lamg_status lamg_t_transfer_export(lamg_handle h, int l, int32_t* out);
 /* Aggregation quantities of level l as the fine side (Sections 3.3-3.4):
  * tv[n*K] relaxed test vectors, aff[nnz] affinities (eq. cuv), ok[nnz]
  * energy-ratio admissibility (eq. qut), weak[nnz], hub[n], state[n] (0
- * undecided, 1 seed, 2 associate, 3 dummy), scal[4] = delta_1, alpha_1,
- * alpha_2, stage.  HOST arrays; any may be NULL. */
+ * undecided, 1 seed, 2 associate, 3 dummy), scal[5] = delta_1, alpha_1,
+ * alpha_2, stage, energy ratio of the last test-vector sweep.  HOST arrays;
+ * any may be NULL. */
 lamg_status lamg_t_agg_export(lamg_handle h, int l, double* tv, double* aff, uint8_t* ok, uint8_t* weak,
                               uint8_t* hub, int32_t* state, double* scal);
 
@@ -51,7 +55,8 @@ lamg_status lamg_t_agg_export(lamg_handle h, int l, double* tv, double* aff, uin
  * DEVICE b_perm[n] (zero-sum) and x_perm[n] (updated in place). */
 lamg_status lamg_t_cycle(lamg_handle h, const double* b_perm, double* x_perm);
 
-/* Coarsest-level solve x = (A_L + (mean diag / n_L) 1 1^T)^-1 b, DEVICE [n_L]. */
+/* Coarsest-level solve x = (A_L + (mean diag / n_L) 1 1^T)^-1 b, DEVICE [n_L]
+ * (dense coarsest levels only). */
 lamg_status lamg_t_coarsest_solve(lamg_handle h, const double* b, double* x);
 
 /* Standalone kernels on a DEVICE CSR whose nodes are already in colour-major
@@ -70,6 +75,15 @@ lamg_status lamg_t_residual(int32_t n, const int32_t* rp, const int32_t* ci, con
  * hash(seed, level, id) asc, id asc) on a DEVICE CSR; DEVICE colour[n] out. */
 lamg_status lamg_t_colour(int32_t n, const int32_t* rp, const int32_t* ci, uint64_t seed, int32_t level,
                           int32_t* colour, void* stream);
+
+/* Instrumentation of the relaxation kernel (Section 3.1.1, eq. gs) and of the
+ * residual kernel.  lamg_t_prof_enable(1) clears the counters and brackets
+ * every later launch with HIP events on the launch's stream; kernel ids:
+ * 0 GS FP64, 1 residual FP64, 2 GS FP32, 3 residual FP32.  lamg_t_prof_read
+ * waits for the recorded events and returns the summed kernel time (ms), the
+ * number of launches and their algorithmic bytes (HOST outputs). */
+void lamg_t_prof_enable(int on);
+lamg_status lamg_t_prof_read(int kernel, double* ms, int64_t* launches, int64_t* bytes);
 
 #ifdef __cplusplus
 }

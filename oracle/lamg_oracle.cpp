@@ -100,10 +100,14 @@ struct Opts {  // mirrors the library options, defaults from Section 4
   uint64_t seed = 0;
   int max_levels = 60;
   double stage1_quantile = 1.0;  // stage-1 affinity threshold: this quantile of best candidate affinities
+  double relax_fast_ratio = 0.1; // stop coarsening when the last test-vector sweep cuts energy at least this much
+  int coarsest_sweeps = 3;       // relaxation sweeps of a coarsest level that relaxation solves
+  int dense_max = 8192;          // largest coarsest level factored densely
 };
 
 struct AggDiag {  // aggregation-level setup quantities, kept for parity tests
   int K = 0;
+  double rate = -1;         // max_k E(x_k after last TV sweep) / E(x_k before it)
   vector<double> tv;        // n x K, after relaxation
   vector<double> aff;       // per directed edge c_us
   vector<uint8_t> ok;       // per directed edge: admissible (energy test)
@@ -132,6 +136,7 @@ struct Level {
 struct Hier {
   Opts o;
   vector<Level> lv;
+  bool coarsest_relax = false;  // coarsest level solved by relaxation sweeps
   vector<i32> perm1;        // level-1 order: perm1[new] = input id
   vector<double> chol;      // dense Cholesky factor of the coarsest system (row-major lower)
   i64 nL = 0;
@@ -407,7 +412,24 @@ Csr schur(const Csr& A, const vector<uint8_t>& inF, vector<i32>& crank) {
 // Section 3.3-3.4: test vectors, affinity (eq. cuv), energy-ratio test
 // (eq. qut, read with the ratio inverted so that it is >= 1), hubs (Section
 // 3.4.1 footnote), weak edges, staged aggregation (Section 3.4.2).
-struct AggResult { vector<i32> agg; i64 nc; };
+struct AggResult { vector<i32> agg; i64 nc; bool fast = false; };
+
+// Energy x^T A x of each of K vectors (n x K row-major), node terms in the
+// fixed row order, nodes summed in order: sum_u sum_v w_uv (x_u - x_v)^2 / 2.
+vector<double> energies(const Csr& A, const vector<double>& X, int K) {
+  vector<double> E(K, 0.0);
+  for (i64 u = 0; u < A.n; ++u) {
+    i64 p0 = A.ptr[u];
+    for (int k = 0; k < K; ++k) {
+      double e = row_reduce<double>(A.deg(u), [&](i64 t) {
+        double d = X[u * K + k] - X[(i64)A.col[p0 + t] * K + k];
+        return A.val[p0 + t] * (d * d);
+      });
+      E[k] += e;
+    }
+  }
+  return E;
+}
 
 AggResult aggregate(const Level& L, const Opts& o, int agg_index, int level, AggDiag& D) {
   const Csr& A = L.A;
@@ -419,8 +441,21 @@ AggResult aggregate(const Level& L, const Opts& o, int agg_index, int level, Agg
   for (i64 u = 0; u < n; ++u)
     for (int k = 0; k < K; ++k)
       X[u * K + k] = unit_pm1(hash5(o.seed, STREAM_TV, (uint64_t)level, (uint64_t)k, (uint64_t)u));
-  for (int s = 0; s < o.tv_sweeps; ++s) gs_sweep<double>(A, A.val.data(), A.diag.data(), nullptr, X.data(), K);
+  for (int s = 0; s + 1 < o.tv_sweeps; ++s) gs_sweep<double>(A, A.val.data(), A.diag.data(), nullptr, X.data(), K);
+  // Section 4.1: stop coarsening when relaxation converges rapidly, judged by
+  // the energy reduction of the last test-vector sweep.
+  vector<double> E0 = energies(A, X, K);
+  if (o.tv_sweeps > 0) gs_sweep<double>(A, A.val.data(), A.diag.data(), nullptr, X.data(), K);
+  vector<double> E1 = energies(A, X, K);
+  D.rate = 0;
+  for (int k = 0; k < K; ++k) D.rate = std::max(D.rate, E0[k] > 0 ? E1[k] / E0[k] : 0.0);
   D.tv = X;
+  if (o.tv_sweeps > 0 && D.rate <= o.relax_fast_ratio) {
+    AggResult R;
+    R.nc = n;
+    R.fast = true;
+    return R;
+  }
   // node quantities
   vector<double> nrm(n), ystar((size_t)n * K), emin((size_t)n * K), sw(n), swd(n), maxw(n, 0.0);
   for (i64 u = 0; u < n; ++u) {
@@ -628,6 +663,7 @@ int setup(Hier& H, i64 n, i64 m, const i32* eu, const i32* ev, const double* w) 
     AggDiag D;
     AggResult R = aggregate(F, H.o, nagg, l, D);
     F.diag = D;
+    if (R.fast) { H.coarsest_relax = true; break; }  // relaxation alone is fast here
     if (R.nc >= F.A.n) break;  // no coarsening possible: this level is the coarsest
     Level C;
     C.A = galerkin(F.A, R.agg, R.nc);
@@ -655,7 +691,9 @@ int setup(Hier& H, i64 n, i64 m, const i32* eu, const i32* ev, const double* w) 
     L.val32.assign(L.A.val.begin(), L.A.val.end());
     L.diag32.assign(L.A.diag.begin(), L.A.diag.end());
   }
-  coarsest_factor(H);
+  if (H.lv.back().A.n > H.o.dense_max) H.coarsest_relax = true;
+  if (!H.coarsest_relax) coarsest_factor(H);
+  else H.nL = H.lv.back().A.n;
   return 0;
 }
 
@@ -732,6 +770,10 @@ void body(const Hier& H, Work<T>& W, int l, int sub) {
   vector<T>& r = W.r[l];
   i64 n = L.A.n;
   if (l == Lc) {
+    if (H.coarsest_relax) {  // relaxation converges rapidly on this level
+      for (int s = 0; s < H.o.coarsest_sweeps; ++s) gs_sweep<T>(L.A, VAL<T>(L), DIAG<T>(L), b.data(), x.data(), 1);
+      return;
+    }
     vector<double> bd(b.begin(), b.end()), xd(n);
     coarsest_solve(H, bd.data(), xd.data());
     for (i64 u = 0; u < n; ++u) x[u] = (T)xd[u];
@@ -909,7 +951,8 @@ typedef struct ora_opts {
   int elim_max_degree, coarsest_max_n;
   double weak_edge_ratio, elim_stop_frac;
   int ec; double tol; int max_cycles; uint64_t seed;
-  double stage1_quantile;
+  double stage1_quantile, relax_fast_ratio;
+  int coarsest_sweeps, dense_max;
 } ora_opts;
 
 void ora_opts_default(ora_opts* o) {
@@ -921,6 +964,9 @@ void ora_opts_default(ora_opts* o) {
   o->weak_edge_ratio = d.weak_edge_ratio; o->elim_stop_frac = d.elim_stop_frac;
   o->ec = d.ec; o->tol = d.tol; o->max_cycles = d.max_cycles; o->seed = d.seed;
   o->stage1_quantile = d.stage1_quantile;
+  o->relax_fast_ratio = d.relax_fast_ratio;
+  o->coarsest_sweeps = d.coarsest_sweeps;
+  o->dense_max = d.dense_max;
 }
 
 static Opts to_opts(const ora_opts* o) {
@@ -933,6 +979,9 @@ static Opts to_opts(const ora_opts* o) {
   d.weak_edge_ratio = o->weak_edge_ratio; d.elim_stop_frac = o->elim_stop_frac;
   d.ec = o->ec; d.tol = o->tol; d.max_cycles = o->max_cycles; d.seed = o->seed;
   d.stage1_quantile = o->stage1_quantile;
+  d.relax_fast_ratio = o->relax_fast_ratio;
+  d.coarsest_sweeps = o->coarsest_sweeps;
+  d.dense_max = o->dense_max;
   return d;
 }
 
@@ -1079,10 +1128,11 @@ void ora_agg_export(void* h, int l, double* tv, double* aff, uint8_t* ok, uint8_
   if (weak) std::copy(D.weak.begin(), D.weak.end(), weak);
   if (hub) std::copy(D.hub.begin(), D.hub.end(), hub);
   if (state) std::copy(D.state.begin(), D.state.end(), state);
-  if (scal) { scal[0] = D.delta1; scal[1] = D.alpha1; scal[2] = D.alpha2; scal[3] = D.stage; }
+  if (scal) { scal[0] = D.delta1; scal[1] = D.alpha1; scal[2] = D.alpha2; scal[3] = D.stage; scal[4] = D.rate; }
 }
 void ora_perm1(void* h, i32* out) { const Hier* H = (Hier*)h; std::copy(H->perm1.begin(), H->perm1.end(), out); }
 i64 ora_coarsest_n(void* h) { return ((Hier*)h)->nL; }
+int ora_coarsest_relax(void* h) { return ((Hier*)h)->coarsest_relax ? 1 : 0; }
 void ora_coarsest_solve(void* h, const double* b, double* x) { coarsest_solve(*(Hier*)h, b, x); }
 
 // info: cycles, rel_residual, acf, removed_mean

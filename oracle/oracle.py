@@ -35,7 +35,8 @@ class Opts(C.Structure):
                 ("elim_max_degree", C.c_int), ("coarsest_max_n", C.c_int),
                 ("weak_edge_ratio", C.c_double), ("elim_stop_frac", C.c_double),
                 ("ec", C.c_int), ("tol", C.c_double), ("max_cycles", C.c_int),
-                ("seed", C.c_uint64), ("stage1_quantile", C.c_double)]
+                ("seed", C.c_uint64), ("stage1_quantile", C.c_double), ("relax_fast_ratio", C.c_double),
+                ("coarsest_sweeps", C.c_int), ("dense_max", C.c_int)]
 
 
 _lib = None
@@ -79,6 +80,7 @@ def lib():
             "ora_agg_export": (None, [vp, C.c_int, dp, dp, u8p, u8p, u8p, i32p, dp]),
             "ora_perm1": (None, [vp, i32p]),
             "ora_coarsest_n": (i64, [vp]),
+            "ora_coarsest_relax": (C.c_int, [vp]),
             "ora_coarsest_solve": (None, [vp, dp, dp]),
             "ora_solve": (C.c_int, [vp, dp, dp, C.c_int, C.c_int, dp, dp]),
             "ora_cycle": (None, [vp, dp, dp]),
@@ -311,16 +313,20 @@ class Hierarchy:
         weak = np.zeros(nnz, np.uint8)
         hub = np.zeros(n, np.uint8)
         state = np.zeros(n, np.int32)
-        scal = np.zeros(4)
+        scal = np.zeros(5)
         lib().ora_agg_export(self.h, l, _p(tv, C.c_double), _p(aff, C.c_double), _p(ok, C.c_uint8),
                              _p(weak, C.c_uint8), _p(hub, C.c_uint8), _p(state, C.c_int32), _p(scal, C.c_double))
         return dict(tv=tv.reshape(n, K), aff=aff, ok=ok, weak=weak, hub=hub, state=state,
-                    delta1=scal[0], alpha1=scal[1], alpha2=scal[2], stage=int(scal[3]), K=K)
+                    delta1=scal[0], alpha1=scal[1], alpha2=scal[2], stage=int(scal[3]), rate=scal[4], K=K)
 
     def perm1(self):
         p = np.zeros(self.n, np.int32)
         lib().ora_perm1(self.h, _p(p, C.c_int32))
         return p
+
+    @property
+    def coarsest_relax(self) -> bool:
+        return bool(lib().ora_coarsest_relax(self.h))
 
     def coarsest_solve(self, b):
         n = int(lib().ora_coarsest_n(self.h))

@@ -89,6 +89,11 @@ void body(Hierarchy* H, int l, int sub, std::vector<int64_t>& count) {
   Level& L = H->lv[l];
   Vecs<T>& v = Prec<T>::v(L);
   if (l == Lc) {
+    if (H->coarsest_relax) {  // relaxation converges rapidly on this level
+      for (int i = 0; i < H->o.coarsest_sweeps; ++i)
+        gs_sweep<T>(s, L, Prec<T>::val(L), Prec<T>::diag(L), v.b, v.x);
+      return;
+    }
     if constexpr (sizeof(T) == 8) coarsest_solve(s, H, (const double*)v.b, (double*)v.x);
     else coarsest_solve32(s, H, (const float*)v.b, (float*)v.x);
     return;
@@ -172,7 +177,8 @@ int64_t cycle_bytes(const Hierarchy* H, int prec) {
     const int64_t n = L.n;
     const int64_t M = (int64_t)L.nnz * (4 + sv) + n * (4 + sv);
     if (l + 1 == nl) {
-      tot += bodies[l] * ((int64_t)H->nL * H->nL * 8 + 2 * n * sx);
+      if (H->coarsest_relax) tot += bodies[l] * H->o.coarsest_sweeps * (M + 3 * n * sx);
+      else tot += bodies[l] * ((int64_t)H->nL * H->nL * 8 + 2 * n * sx);
       continue;
     }
     const Level& C = H->lv[l + 1];
@@ -225,6 +231,9 @@ void lamg_options_default(lamg_options* o) {
   o->weak_edge_ratio = 1e-3;
   o->elim_stop_frac = 0.05;
   o->stage1_quantile = 1.0;
+  o->relax_fast_ratio = 0.1;
+  o->coarsest_sweeps = 3;
+  o->dense_max = 8192;
   o->ec = LAMG_EC_RECOMBINE;
   o->precision = LAMG_FP64;
   o->tol = 1e-8;
@@ -252,7 +261,7 @@ static bool opts_ok(const lamg_options& o) {
   return o.gamma >= 1.0 && o.gamma <= 2.0 && o.nu_pre >= 0 && o.nu_post >= 0 && o.tv_k_min >= 1 &&
          o.tv_k_max >= o.tv_k_min && o.tv_k_max <= 10 && o.tv_sweeps >= 0 && o.q_max > 1.0 && o.coarsest_max_n >= 2 &&
          o.elim_max_degree >= 0 && o.stage1_quantile >= 0.0 && o.stage1_quantile <= 1.0 && o.tol >= 0 &&
-         o.max_cycles >= 0;
+         o.max_cycles >= 0 && o.coarsest_sweeps >= 1 && o.dense_max >= 1 && o.dense_max <= 8192;
 }
 
 lamg_status lamg_setup(int64_t n, int64_t m, const int32_t* eu, const int32_t* ev, const double* w,
@@ -283,10 +292,11 @@ lamg_status lamg_setup(int64_t n, int64_t m, const int32_t* eu, const int32_t* e
     while (H->lv.back().n >= opt.coarsest_max_n && (int)H->lv.size() < 60) {
       const int l = (int)H->lv.size() - 1;
       if (try_eliminate(H, l)) continue;
-      if (!aggregate(H, l, nagg)) break;
+      const int r = aggregate(H, l, nagg);
+      if (r == 2) { H->coarsest_relax = true; break; }
+      if (r == 0) break;
       ++nagg;
     }
-    if (H->lv.back().n > 8192) { lamg_free(h); return LAMG_E_OUT_OF_MEMORY; }
     finish_levels(H);
     H->bsave = H->lv[0].v64.b;
     H->x64 = H->lv[0].v64.x;

@@ -40,6 +40,7 @@ constexpr int LONG_PER_BLOCK = RELAX_THREADS / 64;
 
 // Relaxation work list of one colour class (or of all rows).
 struct Tiles {
+  int64_t rows = 0, nnz = 0;  // rows and entries covered (algorithmic bytes per launch)
   int nstream = 0, nlong_blocks = 0;
   int* stream = nullptr;   // [nstream + 1] row boundaries of stream blocks (device)
   int* longrows = nullptr; // [nlong] long row ids (device)
@@ -70,7 +71,7 @@ struct Level {
   double gamma_next = 1.0;          // cycle index for visits from this level to the next
   // aggregation diagnostics (this level as the fine side), kept for parity tests
   int K = 0, stage = 0;
-  double delta1 = 1, alpha1 = 0, alpha2 = -1;
+  double delta1 = 1, alpha1 = 0, alpha2 = -1, rate = -1;
   double* tv = nullptr;
   double* aff = nullptr;
   uint8_t *ok = nullptr, *weak = nullptr, *hub = nullptr;
@@ -86,6 +87,7 @@ struct Hierarchy {
   int64_t m = 0;
   std::vector<Level> lv;
   double* cinv = nullptr;  // dense inverse of the augmented coarsest matrix (n_L x n_L)
+  bool coarsest_relax = false;  // coarsest level solved by relaxation sweeps
   int nL = 0;
   double* red = nullptr;   // reduction scratch (partials + results)
   double* hred = nullptr;  // pinned host mirror of reduction results
@@ -97,6 +99,13 @@ struct Hierarchy {
   double setup_ms = 0;
   int64_t bytes_per_cycle = 0;
 };
+
+// -------------------------------------------------------- instrumentation
+// When enabled, every relaxation / residual launch is bracketed by HIP events
+// on its stream and its algorithmic bytes are accumulated per kernel:
+// 0 GS FP64, 1 residual FP64, 2 GS FP32, 3 residual FP32.
+void prof_mark(hipStream_t s, int kernel, int64_t bytes, bool begin);
+bool prof_on();
 
 // ------------------------------------------------------------- allocation
 void* dalloc(Hierarchy* H, size_t bytes);
@@ -147,7 +156,8 @@ lamg_status build_finest(Hierarchy* H, int64_t n, int64_t m, const int32_t* eu, 
 void colour_and_order(Hierarchy* H, Level& L, int level, std::vector<int>* inv_host_unused);
 int colour_greedy(hipStream_t s, int n, const int* rp, const int* ci, uint64_t seed, int level, int* col);
 bool try_eliminate(Hierarchy* H, int l);
-bool aggregate(Hierarchy* H, int l, int agg_index);
+// 1: coarse level added; 0: no coarsening possible; 2: relaxation is fast
+int aggregate(Hierarchy* H, int l, int agg_index);
 void finish_levels(Hierarchy* H);
 
 // solve

@@ -473,6 +473,8 @@ void build_tiles(Hierarchy* H, Level& L) {
       a = b;
     }
     Tiles& t = L.tiles[c];
+    t.rows = e - L.cptr[c];
+    t.nnz = rph[e] - rph[L.cptr[c]];
     t.nstream = (int)blocks.size();
     t.nlong = (int)lr.size();
     t.nlong_blocks = (t.nlong + LONG_PER_BLOCK - 1) / LONG_PER_BLOCK;
@@ -486,6 +488,8 @@ void build_tiles(Hierarchy* H, Level& L) {
     all_l.insert(all_l.end(), lr.begin(), lr.end());
   }
   Tiles& t = L.all;
+  t.rows = L.n;
+  t.nnz = rph[L.n];
   t.nstream = (int)all_s.size();
   t.nlong = (int)all_l.size();
   t.nlong_blocks = (t.nlong + LONG_PER_BLOCK - 1) / LONG_PER_BLOCK;
@@ -713,6 +717,48 @@ __global__ void k_edges(int n, int K, const int* __restrict__ rp, const int* __r
     weak[t] = (val[t] < wratio * fmax(mu, o.maxw[s])) ? 1 : 0;
   }
 }
+// Node energies e_uk = sum_v w_uv (x_uk - x_vk)^2 of K vectors (fixed row order).
+__global__ void k_energy_short(int n, int K, const int* __restrict__ rp, const int* __restrict__ ci,
+                               const double* __restrict__ val, const double* __restrict__ X, double* __restrict__ e) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= n) return;
+  const int p0 = rp[u], len = rp[u + 1] - p0;
+  if (len > SHORT_ROW) return;
+  for (int k = 0; k < K; ++k)
+    e[(size_t)u * K + k] = dev::row_sum_seq<double>(len, [&](int t) {
+      const double d = X[(size_t)u * K + k] - X[(size_t)ci[p0 + t] * K + k];
+      return val[p0 + t] * (d * d);
+    });
+}
+__global__ void k_energy_long(const int* __restrict__ rows, int nrows, int K, const int* __restrict__ rp,
+                              const int* __restrict__ ci, const double* __restrict__ val, const double* __restrict__ X,
+                              double* __restrict__ e) {
+  const int idx = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, lane = threadIdx.x & 63;
+  if (idx >= nrows) return;
+  const int u = rows[idx];
+  const int p0 = rp[u], len = rp[u + 1] - p0;
+  for (int k = 0; k < K; ++k) {
+    const double s = dev::row_sum_wave<double>(len, lane, [&](int t) {
+      const double d = X[(size_t)u * K + k] - X[(size_t)ci[p0 + t] * K + k];
+      return val[p0 + t] * (d * d);
+    });
+    if (lane == 0) e[(size_t)u * K + k] = s;
+  }
+}
+// column sums of an n x K array, one block per column, fixed tree order
+__global__ __launch_bounds__(256) void k_colsum(int n, int K, const double* __restrict__ e, double* __restrict__ out) {
+  __shared__ double sh[256];
+  const int k = blockIdx.x;
+  double v = 0;
+  for (int u = threadIdx.x; u < n; u += 256) v += e[(size_t)u * K + k];
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[k] = sh[0];
+}
 // Initial states: hubs (Section 3.4.1 footnote) are seeds; nodes whose every
 // edge is weak go to the dummy aggregate; others are undecided.
 __global__ void k_init_state(int n, const int* __restrict__ rp, const int* __restrict__ deg, NodeOut o,
@@ -823,7 +869,21 @@ __global__ void k_copy_u8(int64_t n, const int* __restrict__ a, uint8_t* __restr
 }
 }  // namespace
 
-bool aggregate(Hierarchy* H, int l, int agg_index) {
+// Energies x_k^T A x_k (up to a factor 2) of the K test vectors.
+static std::vector<double> tv_energies(Hierarchy* H, Tmp& tmp, const Level& F, int K) {
+  hipStream_t s = H->s;
+  double* e = tmp.get<double>((size_t)F.n * K);
+  double* out = tmp.get<double>(K);
+  hipLaunchKernelGGL(k_energy_short, grid1(F.n), dim3(256), 0, s, F.n, K, F.rp, F.ci, F.val, F.tv, e);
+  if (F.all.nlong)
+    hipLaunchKernelGGL(k_energy_long, grid1((int64_t)F.all.nlong * 64), dim3(256), 0, s, F.all.longrows, F.all.nlong,
+                       K, F.rp, F.ci, F.val, F.tv, e);
+  hipLaunchKernelGGL(k_colsum, dim3(K), dim3(256), 0, s, F.n, K, e, out);
+  LAMG_HIP(hipGetLastError());
+  return to_host_vec(s, out, (size_t)K);
+}
+
+int aggregate(Hierarchy* H, int l, int agg_index) {
   hipStream_t s = H->s;
   Tmp tmp;
   Level& F = H->lv[l];
@@ -833,7 +893,18 @@ bool aggregate(Hierarchy* H, int l, int agg_index) {
   // test vectors: U[-1,1) then tv_sweeps GS sweeps on A x = 0 (Section 3.3.1)
   F.tv = dnew<double>(H, (size_t)n * K);
   hipLaunchKernelGGL(k_tv_init, grid1((int64_t)n * K), dim3(256), 0, s, n, K, (uint64_t)H->o.seed, (uint64_t)l, F.tv);
-  for (int sw = 0; sw < H->o.tv_sweeps; ++sw) gs_multi_sweep(s, F, nullptr, F.tv, K);
+  for (int sw = 0; sw + 1 < H->o.tv_sweeps; ++sw) gs_multi_sweep(s, F, nullptr, F.tv, K);
+  // Section 4.1: stop coarsening when relaxation converges rapidly, judged by
+  // the energy reduction of the last test-vector sweep.
+  {
+    const std::vector<double> E0 = tv_energies(H, tmp, F, K);
+    if (H->o.tv_sweeps > 0) gs_multi_sweep(s, F, nullptr, F.tv, K);
+    const std::vector<double> E1 = tv_energies(H, tmp, F, K);
+    double rate = 0;
+    for (int k = 0; k < K; ++k) rate = std::max(rate, E0[k] > 0 ? E1[k] / E0[k] : 0.0);
+    F.rate = rate;
+    if (H->o.tv_sweeps > 0 && rate <= H->o.relax_fast_ratio) return 2;
+  }
   int* deg = tmp.get<int>(n);
   hipLaunchKernelGGL(k_degrees, grid1(n), dim3(256), 0, s, n, F.rp, deg);
   NodeOut o;
@@ -916,7 +987,7 @@ bool aggregate(Hierarchy* H, int l, int agg_index) {
   hipLaunchKernelGGL(k_finalise, grid1(n), dim3(256), 0, s, n, st, dmin, rep);
   excl_scan(s, tmp, rep, id, n);
   const int nc = to_host(s, id + n);
-  if (nc >= n) return false;  // no coarsening possible
+  if (nc >= n) return 0;  // no coarsening possible
   int* aggn = tmp.get<int>(n);
   hipLaunchKernelGGL(k_number, grid1(n), dim3(256), 0, s, n, st, seedof, id, dmin, aggn);
   // Galerkin coarse operator
@@ -947,7 +1018,7 @@ bool aggregate(Hierarchy* H, int l, int agg_index) {
   excl_scan(s, tmp, acnt, C.agg_ptr, nc);
   LAMG_HIP(hipStreamSynchronize(s));
   H->lv.push_back(C);
-  return true;
+  return 1;
 }
 
 // Cycle indices (Section 4.2, eq. cycle_index with gamma^l >= 1), FP32 level
@@ -987,7 +1058,9 @@ void finish_levels(Hierarchy* H) {
     mk64(L.v64);
     mk32(L.v32);
   }
-  coarsest_factor(H, H->lv.back());
+  if (H->lv.back().n > H->o.dense_max) H->coarsest_relax = true;
+  if (!H->coarsest_relax) coarsest_factor(H, H->lv.back());
+  else H->nL = H->lv.back().n;
   H->red = dnew<double>(H, k::RED_BLOCKS * 8 + 16);
   LAMG_HIP(hipHostMalloc((void**)&H->hred, 64 * sizeof(double), hipHostMallocDefault));
   LAMG_HIP(hipStreamSynchronize(s));

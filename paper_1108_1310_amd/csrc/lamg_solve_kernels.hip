@@ -6,6 +6,7 @@
 
 #include "lamg_device.hpp"
 #include "lamg_internal.hpp"
+#include "../../include/lamg_test.h"
 
 namespace lamg {
 
@@ -67,9 +68,50 @@ static void launch_relax(hipStream_t s, const Level& L, const Tiles& t, const T*
                          const T* b, T* x, T* r) {
   const int grid = t.nstream + t.nlong_blocks;
   if (grid == 0) return;
+  const bool prof = prof_on();
+  const int kid = MODE + (sizeof(T) == 4 ? 2 : 0);
+  // matrix stream (column index + value per entry, row pointer + diagonal per
+  // row) and three vector streams per row (b or x read, x read, x or r write)
+  const int64_t bytes = t.nnz * (4 + (int64_t)sizeof(T)) + t.rows * (4 + (int64_t)sizeof(T)) +
+                        3 * t.rows * (int64_t)sizeof(T);
+  if (prof) prof_mark(s, kid, bytes, true);
   hipLaunchKernelGGL((k_relax<T, MODE>), dim3(grid), dim3(RELAX_THREADS), 0, s, L.rp, L.ci, val, diag, b, x, r,
                      (const int2*)t.stream, t.nstream, t.longrows, t.nlong);
+  if (prof) prof_mark(s, kid, bytes, false);
   LAMG_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------- instrumentation
+namespace {
+struct Prof {
+  bool on = false;
+  std::vector<hipEvent_t> ev;  // pairs (begin, end)
+  std::vector<int> kid;
+  size_t used = 0;
+  int64_t bytes[4] = {0, 0, 0, 0}, launches[4] = {0, 0, 0, 0};
+};
+Prof g_prof;
+}  // namespace
+bool prof_on() { return g_prof.on; }
+void prof_mark(hipStream_t s, int kernel, int64_t bytes, bool begin) {
+  Prof& P = g_prof;
+  if (begin) {
+    if (P.used + 2 > P.ev.size()) {
+      for (int i = 0; i < 2; ++i) {
+        hipEvent_t e;
+        LAMG_HIP(hipEventCreate(&e));
+        P.ev.push_back(e);
+      }
+      P.kid.push_back(0);
+    }
+    P.kid[P.used / 2] = kernel;
+    LAMG_HIP(hipEventRecord(P.ev[P.used], s));
+  } else {
+    LAMG_HIP(hipEventRecord(P.ev[P.used + 1], s));
+    P.used += 2;
+    P.bytes[kernel] += bytes;
+    P.launches[kernel] += 1;
+  }
 }
 
 template <class T>
@@ -479,3 +521,28 @@ void coarsest_factor(Hierarchy* H, const Level& L) {
 }
 
 }  // namespace lamg
+
+extern "C" {
+void lamg_t_prof_enable(int on) {
+  lamg::Prof& P = lamg::g_prof;
+  P.on = on != 0;
+  P.used = 0;
+  for (int k = 0; k < 4; ++k) { P.bytes[k] = 0; P.launches[k] = 0; }
+}
+lamg_status lamg_t_prof_read(int kernel, double* ms, int64_t* launches, int64_t* bytes) {
+  lamg::Prof& P = lamg::g_prof;
+  if (kernel < 0 || kernel > 3 || !ms || !launches || !bytes) return LAMG_E_INVALID_ARG;
+  double tot = 0;
+  for (size_t i = 0; i + 1 < P.used + 1 && i < P.used; i += 2) {
+    if (P.kid[i / 2] != kernel) continue;
+    if (hipEventSynchronize(P.ev[i + 1]) != hipSuccess) return LAMG_E_DEVICE;
+    float t = 0;
+    if (hipEventElapsedTime(&t, P.ev[i], P.ev[i + 1]) != hipSuccess) return LAMG_E_DEVICE;
+    tot += t;
+  }
+  *ms = tot;
+  *launches = P.launches[kernel];
+  *bytes = P.bytes[kernel];
+  return LAMG_OK;
+}
+}

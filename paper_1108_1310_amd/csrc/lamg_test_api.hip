@@ -42,6 +42,7 @@ Level borrowed_level(Scratch& S, int n, const int32_t* rp, const int32_t* ci, in
 extern "C" {
 
 int lamg_t_num_levels(lamg_handle h) { return h ? (int)h->H.lv.size() : 0; }
+int lamg_t_coarsest_relax(lamg_handle h) { return h && h->H.coarsest_relax ? 1 : 0; }
 
 lamg_status lamg_t_level_dims(lamg_handle h, int l, int64_t* d) {
   if (guard(h, l) != LAMG_OK || !d) return LAMG_E_INVALID_ARG;
@@ -100,7 +101,7 @@ lamg_status lamg_t_agg_export(lamg_handle h, int l, double* tv, double* aff, uin
     d2h(weak, L.weak, (size_t)L.nnz);
     d2h(hub, L.hub, (size_t)L.n);
     d2h(state, L.state, (size_t)L.n);
-    if (scal) { scal[0] = L.delta1; scal[1] = L.alpha1; scal[2] = L.alpha2; scal[3] = L.stage; }
+    if (scal) { scal[0] = L.delta1; scal[1] = L.alpha1; scal[2] = L.alpha2; scal[3] = L.stage; scal[4] = L.rate; }
   } catch (const DevError&) {
     return LAMG_E_DEVICE;
   }
@@ -125,7 +126,7 @@ lamg_status lamg_t_cycle(lamg_handle h, const double* b, double* x) {
 }
 
 lamg_status lamg_t_coarsest_solve(lamg_handle h, const double* b, double* x) {
-  if (!h || !b || !x) return LAMG_E_INVALID_ARG;
+  if (!h || !b || !x || h->H.coarsest_relax) return LAMG_E_INVALID_ARG;
   try {
     coarsest_solve(h->H.s, &h->H, b, x);
     LAMG_HIP(hipStreamSynchronize(h->H.s));

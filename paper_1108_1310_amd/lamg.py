@@ -27,6 +27,7 @@ class Options(C.Structure):
                 ("q_max", C.c_double), ("mu", C.c_double), ("hub_factor", C.c_double),
                 ("elim_max_degree", C.c_int), ("coarsest_max_n", C.c_int),
                 ("weak_edge_ratio", C.c_double), ("elim_stop_frac", C.c_double), ("stage1_quantile", C.c_double),
+                ("relax_fast_ratio", C.c_double), ("coarsest_sweeps", C.c_int), ("dense_max", C.c_int),
                 ("ec", C.c_int), ("precision", C.c_int), ("tol", C.c_double), ("max_cycles", C.c_int),
                 ("warm_start", C.c_int), ("seed", C.c_uint64), ("stream", C.c_void_p)]
 
@@ -66,6 +67,7 @@ def lib():
             "lamg_free": (None, [vp]),
             "lamg_status_str": (C.c_char_p, [C.c_int]),
             "lamg_t_num_levels": (C.c_int, [vp]),
+            "lamg_t_coarsest_relax": (C.c_int, [vp]),
             "lamg_t_level_dims": (C.c_int, [vp, C.c_int, C.POINTER(i64)]),
             "lamg_t_level_gamma": (d, [vp, C.c_int]),
             "lamg_t_level_export": (C.c_int, [vp, C.c_int, vp, vp, vp, vp, vp, vp]),
@@ -77,6 +79,8 @@ def lib():
             "lamg_t_gs32": (C.c_int, [i32, vp, vp, vp, vp, i32, vp, vp, vp, i32, vp]),
             "lamg_t_residual": (C.c_int, [i32, vp, vp, vp, vp, vp, vp, vp, vp]),
             "lamg_t_colour": (C.c_int, [i32, vp, vp, u64, i32, vp, vp]),
+            "lamg_t_prof_enable": (None, [C.c_int]),
+            "lamg_t_prof_read": (C.c_int, [C.c_int, C.POINTER(d), C.POINTER(i64), C.POINTER(i64)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -172,6 +176,10 @@ class Hierarchy:
     def num_levels(self) -> int:
         return lib().lamg_t_num_levels(self.h)
 
+    @property
+    def coarsest_relax(self) -> bool:
+        return bool(lib().lamg_t_coarsest_relax(self.h))
+
     def dims(self, l: int) -> dict:
         d = (C.c_int64 * 8)()
         _check(lib().lamg_t_level_dims(self.h, l, d), "lamg_t_level_dims")
@@ -206,12 +214,12 @@ class Hierarchy:
         weak = np.zeros(nnz, np.uint8)
         hub = np.zeros(n, np.uint8)
         st = np.zeros(n, np.int32)
-        scal = np.zeros(4)
+        scal = np.zeros(5)
         vp = lambda a: C.c_void_p(a.ctypes.data)
         _check(lib().lamg_t_agg_export(self.h, l, vp(tv), vp(aff), vp(ok), vp(weak), vp(hub), vp(st), vp(scal)),
                "lamg_t_agg_export")
         return dict(tv=tv.reshape(n, K), aff=aff, ok=ok, weak=weak, hub=hub, state=st, delta1=scal[0],
-                    alpha1=scal[1], alpha2=scal[2], stage=int(scal[3]), K=K)
+                    alpha1=scal[1], alpha2=scal[2], stage=int(scal[3]), rate=scal[4], K=K)
 
     def cycle(self, b_perm, x_perm):
         b = _dev(b_perm, torch.float64)
@@ -268,3 +276,17 @@ def colour(rp, ci, n, seed=0, level=0):
     out = torch.empty(n, dtype=torch.int32, device="cuda")
     _check(lib().lamg_t_colour(n, _ptr(rp), _ptr(ci), seed, level, _ptr(out), _stream()), "lamg_t_colour")
     return out
+
+
+KERNELS = {0: "gs_fp64", 1: "residual_fp64", 2: "gs_fp32", 3: "residual_fp32"}
+
+
+def prof_enable(on: bool = True):
+    """Bracket every relaxation / residual launch with HIP events (see lamg_test.h)."""
+    lib().lamg_t_prof_enable(1 if on else 0)
+
+
+def prof_read(kernel: int) -> dict:
+    ms, la, by = C.c_double(), C.c_int64(), C.c_int64()
+    _check(lib().lamg_t_prof_read(kernel, C.byref(ms), C.byref(la), C.byref(by)), "lamg_t_prof_read")
+    return dict(kernel=KERNELS[kernel], ms=ms.value, launches=la.value, bytes=by.value)

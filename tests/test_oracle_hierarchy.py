@@ -7,6 +7,7 @@ import pytest
 from test_oracle_pins import random_graph
 
 SMALL = dict(coarsest_max_n=8)  # force several levels on tiny graphs
+NOFAST = dict(relax_fast_ratio=-1.0)  # keep coarsening even where relaxation is fast
 
 
 def grid(nx, ny):
@@ -27,7 +28,7 @@ def test_aggregation_invariants(ora):
     for seed in range(3):
         n = 400
         eu, ev, w = random_graph(n, 3 * n, seed)
-        H = ora.Hierarchy(n, eu, ev, w, seed=seed, coarsest_max_n=20)
+        H = ora.Hierarchy(n, eu, ev, w, seed=seed, coarsest_max_n=20, **NOFAST)
         assert agg_levels(H)
         for l in agg_levels(H):
             L, C = H.level(l), H.level(l + 1)
@@ -59,7 +60,7 @@ def test_affinity_definition(ora):
     = min_p |p X_u - X_s|^2/|X_s|^2 (brute force over p); 0 <= c <= 1; c symmetric."""
     n = 300
     eu, ev, w = random_graph(n, 3 * n, 4)
-    H = ora.Hierarchy(n, eu, ev, w, coarsest_max_n=20)
+    H = ora.Hierarchy(n, eu, ev, w, coarsest_max_n=20, **NOFAST)
     l = agg_levels(H)[0]
     L = H.level(l)
     D = H.agg_diag(l)
@@ -88,7 +89,7 @@ def test_energy_ratio_test(ora):
     paper's quadratic E_u(x; y) = a/2 y^2 - B y + C evaluated directly."""
     n = 300
     eu, ev, w = random_graph(n, 3 * n, 6)
-    H = ora.Hierarchy(n, eu, ev, w, coarsest_max_n=20)
+    H = ora.Hierarchy(n, eu, ev, w, coarsest_max_n=20, **NOFAST)
     l = agg_levels(H)[0]
     L = H.level(l)
     D = H.agg_diag(l)
@@ -119,7 +120,7 @@ def test_hub_rule_on_star(ora):
     for k in (6, 7, 8, 9, 12):
         eu = np.zeros(k, np.int32)
         ev = np.arange(1, k + 1, dtype=np.int32)
-        H = ora.Hierarchy(k + 1, eu, ev, np.ones(k), coarsest_max_n=2, elim_max_degree=0)
+        H = ora.Hierarchy(k + 1, eu, ev, np.ones(k), coarsest_max_n=2, elim_max_degree=0, **NOFAST)
         D = H.agg_diag(0)
         L = H.level(0)
         centre = int(np.where(L.perm == 0)[0][0])
@@ -133,7 +134,7 @@ def test_colour_parallel_scan_equals_serial(ora):
     for seed in range(3):
         n = 500
         eu, ev, w = random_graph(n, 4 * n, seed)
-        H = ora.Hierarchy(n, eu, ev, w, seed=seed, coarsest_max_n=20)
+        H = ora.Hierarchy(n, eu, ev, w, seed=seed, coarsest_max_n=20, **NOFAST)
         for l in agg_levels(H)[:2]:
             L = H.level(l)
             D = H.agg_diag(l)
@@ -197,7 +198,7 @@ def test_solve_matches_pinv(ora, ec, precision):
     for seed in range(3):
         n = 250
         eu, ev, w = random_graph(n, 2 * n, seed)
-        H = ora.Hierarchy(n, eu, ev, w, ec=ec, **SMALL)
+        H = ora.Hierarchy(n, eu, ev, w, ec=ec, **SMALL, **NOFAST)
         assert H.num_levels >= 3
         rng = np.random.default_rng(seed)
         b = rng.standard_normal(n) + 0.3  # non-zero mean is projected away
@@ -252,7 +253,7 @@ def test_adjoint_matches_dense_gradient(ora):
     dL/dw_uv = -(lam_u - lam_v)(x_u - x_v), against a dense pinv derivative."""
     n = 120
     eu, ev, w = random_graph(n, 3 * n, 9)
-    H = ora.Hierarchy(n, eu, ev, w, tol=1e-13, **SMALL)
+    H = ora.Hierarchy(n, eu, ev, w, tol=1e-13, **SMALL, **NOFAST)
     rng = np.random.default_rng(9)
     b = rng.standard_normal(n)
     hold = rng.choice(n, 10, replace=False)
@@ -275,3 +276,34 @@ def test_adjoint_matches_dense_gradient(ora):
         dx = -Ap @ dA @ xd
         want = g @ dx
         assert abs(gw[e] - want) <= 1e-9 * max(1.0, abs(want))
+
+
+def test_relaxation_fast_stops_coarsening(ora):
+    """Section 4.1: coarsening stops when relaxation converges rapidly.  On a
+    complete graph GS removes almost all energy per sweep (Section 3.1.3 names
+    complete graphs among those GS solves well); on a grid it smooths slowly.
+    The rate is the last test-vector sweep's energy ratio, checked here against
+    plain GS on random vectors."""
+    n = 300
+    iu, iv = np.triu_indices(n, 1)
+    rng = np.random.default_rng(0)
+    w = rng.uniform(0.5, 1.0, iu.shape[0])
+    H = ora.Hierarchy(n, iu.astype(np.int32), iv.astype(np.int32), w)
+    assert H.coarsest_relax and H.num_levels == 1
+    D = H.agg_diag(0)
+    assert 0 <= D["rate"] <= 0.1
+    A = ora.laplacian(n, iu, iv, w)
+    Dm = A.dense()
+    x = rng.uniform(-1, 1, n)
+    x1 = ora.gs(A, None, ora.gs(A, None, x))
+    x2 = ora.gs(A, None, x1)
+    assert (x2 @ Dm @ x2) / (x1 @ Dm @ x1) < 0.1
+    b = rng.standard_normal(n)
+    xs, info, _ = H.solve(b)
+    assert info["status"] == 0
+    assert np.allclose(xs, np.linalg.pinv(Dm) @ (b - b.mean()), atol=1e-7 * np.abs(xs).max())
+    nx, eu, ev = grid(64, 64)
+    G = ora.Hierarchy(nx, eu, ev, np.ones(eu.shape[0]))
+    assert not G.coarsest_relax and G.num_levels > 3
+    for l in agg_levels(G):
+        assert G.agg_diag(l)["rate"] > 0.3
