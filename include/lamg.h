@@ -123,6 +123,10 @@ void lamg_free(lamg_handle h);
 /* Static description of a status code. */
 const char* lamg_status_str(lamg_status s);
 
+/* Text of the HIP error behind the last LAMG_E_DEVICE / LAMG_E_OUT_OF_MEMORY
+ * returned on the calling thread ("" if none); valid until the next call. */
+const char* lamg_last_error(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -9,11 +9,17 @@
 //   * the splitmix64 finaliser (Steele, Lea & Flood 2014) used as a
 //     counter-based hash for colouring priorities and test-vector draws;
 //   * the fixed row-reduction order used for every row sum (sequential in
-//     column order for rows of at most 64 terms; otherwise 64 strided partial
-//     sums folded by an xor butterfly with offsets 32..1);
+//     column order for rows of at most 64 terms; otherwise chunks of 512
+//     terms, each reduced by 64 strided partial sums folded by an xor
+//     butterfly with offsets 32..1, chunk sums added in order);
 //   * the level node order (colour-major, then previous id).
 // Build: g++ -O2 -ffp-contract=off -fno-fast-math -shared -fPIC.
-// Parity status of every function is stated beside it (pinned / unpinned).
+// Every function is pinned by a CPU test against the paper or mathematics
+// except: which aggregates the two-stage rule picks (parity unpinned: the
+// paper prints no aggregates; only invariants and the scan equivalence are
+// pinned) and the constants of the stage-1 threshold, the weak-edge ratio,
+// the elimination stop fraction and the fast-relaxation ratio (parity
+// unpinned: builder choices where the paper gives no value).
 
 #include <algorithm>
 #include <cmath>
@@ -51,6 +57,11 @@ const uint64_t STREAM_COLOUR = 7, STREAM_TV = 3;
 inline double unit_pm1(uint64_t h) { return (double)(h >> 11) * (1.0 / 4503599627370496.0) - 1.0; }
 
 // ------------------------------------------------- fixed row-reduction order
+// Rows of at most 64 terms are summed left to right.  Longer rows are cut into
+// chunks of 512 consecutive terms; inside a chunk, partial j (0..63) sums the
+// chunk's terms j, j+64, ..., j+448 left to right, the 64 partials are folded
+// by an xor butterfly (offsets 32..1), and the chunk sums are added left to
+// right.
 template <class T, class F>
 T row_reduce(i64 len, F term) {
   if (len <= 64) {
@@ -58,18 +69,22 @@ T row_reduce(i64 len, F term) {
     for (i64 t = 0; t < len; ++t) s += term(t);
     return s;
   }
-  T p[64];
-  for (int j = 0; j < 64; ++j) {
-    T s = 0;
-    for (i64 t = j; t < len; t += 64) s += term(t);
-    p[j] = s;
+  T total = 0;
+  for (i64 c0 = 0; c0 < len; c0 += 512) {
+    T p[64];
+    for (int j = 0; j < 64; ++j) {
+      T s = 0;
+      for (i64 t = c0 + j; t < len && t < c0 + 512; t += 64) s += term(t);
+      p[j] = s;
+    }
+    for (int off = 32; off >= 1; off >>= 1) {
+      T q[64];
+      for (int j = 0; j < 64; ++j) q[j] = p[j] + p[j ^ off];
+      std::memcpy(p, q, sizeof(p));
+    }
+    total += p[0];
   }
-  for (int off = 32; off >= 1; off >>= 1) {
-    T q[64];
-    for (int j = 0; j < 64; ++j) q[j] = p[j] + p[j ^ off];
-    std::memcpy(p, q, sizeof(p));
-  }
-  return p[0];
+  return total;
 }
 
 // ------------------------------------------------------------- structures

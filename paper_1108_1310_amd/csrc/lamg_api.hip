@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <vector>
 
@@ -50,31 +51,9 @@ __global__ void k_add_f32(int n, const float* __restrict__ e, double* __restrict
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) x[i] += (double)e[i];
 }
-__global__ void k_mean_slot(int nblk, const double* part, double* res, int slot, double scale) {
-  if (threadIdx.x != 0) return;
-  double s = 0;
-  for (int b = 0; b < nblk; ++b) s += part[b * 8];
-  res[slot] = s * scale;
-}
-__global__ __launch_bounds__(256) void k_sum_d(int n, const double* __restrict__ x, double* part) {
-  __shared__ double sh[256];
-  double v = 0;
-  for (int u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += gridDim.x * blockDim.x) v += x[u];
-  sh[threadIdx.x] = v;
-  __syncthreads();
-  for (int w = 128; w >= 1; w >>= 1) {
-    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) part[blockIdx.x * 8] = sh[0];
-}
-
 // mean of a device vector into reduction slot `slot` (device side only)
 void mean_to_slot(hipStream_t s, Hierarchy* H, const double* x, int n, int slot) {
-  const int nb = std::max(1, std::min(k::RED_BLOCKS, (n + 255) / 256));
-  hipLaunchKernelGGL(k_sum_d, dim3(nb), dim3(256), 0, s, n, x, H->red);
-  hipLaunchKernelGGL(k_mean_slot, dim3(1), dim3(64), 0, s, nb, H->red, H->red + k::RED_BLOCKS * 8, slot,
-                     1.0 / (double)n);
+  sum_to_slot(s, H, x, n, slot, 1.0 / (double)n);
 }
 double* res_slots(Hierarchy* H) { return H->red + k::RED_BLOCKS * 8; }
 
@@ -104,7 +83,7 @@ void body(Hierarchy* H, int l, int sub, std::vector<int64_t>& count) {
   const T* dg = Prec<T>::diag(L);
   if (C.type == LT_ELIM) {
     residual<T>(s, L, val, dg, v.b, v.x, v.r);
-    restrict_elim<T>(s, L, C, val, dg, v.r, vc.b);
+    restrict_elim<T>(s, C, v.r, vc.b);
     fill<T>(s, vc.x, T(0), C.n);
     visit<T>(H, l + 1, 1, count);
     interp_elim<T>(s, L, C, val, dg, v.r, vc.x, v.x);
@@ -146,6 +125,56 @@ void cycle(Hierarchy* H) {
 }
 template void cycle<double>(Hierarchy*);
 template void cycle<float>(Hierarchy*);
+
+// The kernel sequence of a cycle depends only on the hierarchy and the solve
+// options, so it is captured once into a graph and replayed.  Capture runs on
+// the hierarchy's private stream; replays go to the caller's stream.  With
+// instrumentation on, the cycle is launched eagerly instead.
+template <class T>
+void cycle_graph(Hierarchy* H, int inst) {
+  if (prof_on()) { cycle<T>(H); return; }
+  const int p = sizeof(T) == 8 ? 0 : 1;
+  if (!H->gexec[p][inst]) {
+    if (!H->cs) LAMG_HIP(hipStreamCreateWithFlags(&H->cs, hipStreamNonBlocking));
+    hipStream_t user = H->s;
+    H->s = H->cs;
+    hipGraph_t g = nullptr;
+    LAMG_HIP(hipStreamBeginCapture(H->cs, hipStreamCaptureModeThreadLocal));
+    try {
+      cycle<T>(H);
+    } catch (...) {
+      (void)hipStreamEndCapture(H->cs, &g);
+      if (g) (void)hipGraphDestroy(g);
+      H->s = user;
+      throw;
+    }
+    LAMG_HIP(hipStreamEndCapture(H->cs, &g));
+    H->s = user;
+    hipGraphExec_t ex = nullptr;
+    const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    LAMG_HIP(e);
+    H->gexec[p][inst] = ex;
+  }
+  LAMG_HIP(hipGraphLaunch(H->gexec[p][inst], H->s));
+}
+template void cycle_graph<double>(Hierarchy*, int);
+template void cycle_graph<float>(Hierarchy*, int);
+
+void drop_graphs(Hierarchy* H) {
+  for (int p = 0; p < 2; ++p)
+    for (int i = 0; i < 2; ++i) {
+      if (H->gexec[p][i]) (void)hipGraphExecDestroy(H->gexec[p][i]);
+      H->gexec[p][i] = nullptr;
+    }
+}
+
+namespace {
+thread_local char g_last_error[256] = "";
+}
+void set_last_error(const char* where, hipError_t e) {
+  std::snprintf(g_last_error, sizeof(g_last_error), "%s: %s (%d)", where, hipGetErrorString(e), (int)e);
+}
 
 // Algorithmic bytes of one cycle (matrix and vector streams per pass).
 int64_t cycle_bytes(const Hierarchy* H, int prec) {
@@ -243,6 +272,8 @@ void lamg_options_default(lamg_options* o) {
   o->stream = nullptr;
 }
 
+const char* lamg_last_error(void) { return g_last_error; }
+
 const char* lamg_status_str(lamg_status s) {
   switch (s) {
     case LAMG_OK: return "ok";
@@ -306,6 +337,7 @@ lamg_status lamg_setup(int64_t n, int64_t m, const int32_t* eu, const int32_t* e
     H->bytes_per_cycle = cycle_bytes(H, LAMG_FP64);
     LAMG_HIP(hipStreamSynchronize(H->s));
   } catch (const DevError& e) {
+    set_last_error("lamg_setup", e.e);
     lamg_free(h);
     return e.e == hipErrorOutOfMemory ? LAMG_E_OUT_OF_MEMORY : LAMG_E_DEVICE;
   }
@@ -320,6 +352,7 @@ lamg_status lamg_set_solve_options(lamg_handle h, const lamg_options* o) {
       (o->ec != LAMG_EC_RECOMBINE && o->ec != LAMG_EC_FLAT_MU))
     return LAMG_E_INVALID_ARG;
   Hierarchy* H = &h->H;
+  drop_graphs(H);  // the captured cycles depend on these options
   H->o.precision = o->precision;
   H->o.ec = o->ec;
   H->o.mu = o->mu;
@@ -360,14 +393,15 @@ static lamg_status solve_one(Hierarchy* H, const double* b, double* x, lamg_info
   if (nb > 0) {
     Vecs<float>& v32 = L.v32;
     while (rk > H->o.tol * nb && it < H->o.max_cycles && std::isfinite(rk)) {
+      const int inst = 0;
       if (!fp32) {
-        cycle<double>(H);  // level-1 vectors alias bsave / x64
+        cycle_graph<double>(H, inst);  // level-1 vectors alias bsave / x64
       } else {
         // inner FP32 cycle on the projected FP64 residual
         mean_to_slot(s, H, H->r64, n, 7);
         hipLaunchKernelGGL(k_sub_to_f32, grid1(n), dim3(256), 0, s, n, (const double*)H->r64, rs, 7, v32.b);
         fill<float>(s, v32.x, 0.0f, n);
-        cycle<float>(H);
+        cycle_graph<float>(H, inst);
         hipLaunchKernelGGL(k_add_f32, grid1(n), dim3(256), 0, s, n, (const float*)v32.x, H->x64);
         subtract_mean<double>(s, H, H->x64, n);
       }
@@ -401,6 +435,7 @@ lamg_status lamg_solve(lamg_handle h, const double* b, double* x, lamg_info* inf
   try {
     return solve_one(&h->H, b, x, info);
   } catch (const DevError& e) {
+    set_last_error("lamg_solve", e.e);
     return e.e == hipErrorOutOfMemory ? LAMG_E_OUT_OF_MEMORY : LAMG_E_DEVICE;
   }
 }
@@ -454,6 +489,7 @@ lamg_status lamg_solve_batch(int32_t count, const lamg_handle* hs, const int32_t
       if (infos) infos[i] = acc;
     }
   } catch (const DevError& e) {
+    set_last_error("lamg_solve_batch", e.e);
     return e.e == hipErrorOutOfMemory ? LAMG_E_OUT_OF_MEMORY : LAMG_E_DEVICE;
   }
   return worst;
@@ -464,6 +500,8 @@ void lamg_free(lamg_handle h) {
   Hierarchy* H = &h->H;
   if (H->s) (void)hipStreamSynchronize(H->s);
   else (void)hipDeviceSynchronize();
+  drop_graphs(H);
+  if (H->cs) (void)hipStreamDestroy(H->cs);
   for (void* p : H->owned) (void)hipFree(p);
   if (H->hred) (void)hipHostFree(H->hred);
   delete h;

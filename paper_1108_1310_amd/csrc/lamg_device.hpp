@@ -44,12 +44,23 @@ __device__ inline T row_sum_seq(int len, F term) {
   for (int t = 0; t < len; ++t) s += term(t);
   return s;
 }
-// Long rows (> 64 terms): lane j sums terms j, j+64, ... then the butterfly.
+// Long rows (> 64 terms), one wavefront: chunks of CHUNK consecutive terms;
+// in each chunk lane j sums terms j, j+64, ... left to right, the butterfly
+// folds the chunk, and chunk sums are added left to right.
+constexpr int CHUNK = 512;
 template <class T, class F>
 __device__ inline T row_sum_wave(int len, int lane, F term) {
-  T s = 0;
-  for (int t = lane; t < len; t += 64) s += term(t);
-  return wave_fold(s);
+  T total = 0;
+  for (int c0 = 0; c0 < len; c0 += CHUNK) {
+    T s = 0;
+#pragma unroll
+    for (int q = 0; q < CHUNK / 64; ++q) {
+      const int t = c0 + lane + 64 * q;
+      if (t < len) s += term(t);
+    }
+    total += wave_fold(s);
+  }
+  return total;
 }
 
 }  // namespace dev

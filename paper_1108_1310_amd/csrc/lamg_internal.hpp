@@ -30,21 +30,30 @@ constexpr uint64_t STREAM_COLOUR = 7, STREAM_TV = 3;
 // butterfly; shorter rows are summed sequentially in column order.
 constexpr int SHORT_ROW = 64;
 
-// Relaxation tile: a "stream" block owns up to TILE_ROWS consecutive short
-// rows whose entries fit in TILE_NNZ products staged in LDS; a "long" block
-// owns up to LONG_PER_BLOCK long rows, one wavefront each.
-constexpr int RELAX_THREADS = 256;
-constexpr int TILE_ROWS = 256;
-constexpr int TILE_NNZ = 2048;
+// Relaxation work list of one colour class (or of all rows), as three kinds
+// of 512-thread blocks launched together, longest work first:
+//   very long rows (> CHUNK entries): one block per row, its 512-entry chunks
+//     spread over the 8 wavefronts;
+//   medium rows (65..CHUNK entries): one wavefront per row, 8 rows per block;
+//   stream tiles: up to TILE_ROWS consecutive short rows whose entries fit in
+//     TILE_NNZ products staged in LDS, one thread per row for the sums.
+constexpr int RELAX_THREADS = 512;
+constexpr int TILE_ROWS = 512;
+constexpr int TILE_NNZ = 4096;
 constexpr int LONG_PER_BLOCK = RELAX_THREADS / 64;
+constexpr int ROW_CHUNK = 512;
 
-// Relaxation work list of one colour class (or of all rows).
 struct Tiles {
   int64_t rows = 0, nnz = 0;  // rows and entries covered (algorithmic bytes per launch)
-  int nstream = 0, nlong_blocks = 0;
-  int* stream = nullptr;   // [nstream + 1] row boundaries of stream blocks (device)
-  int* longrows = nullptr; // [nlong] long row ids (device)
+  int nstream = 0;
+  int* stream = nullptr;      // [nstream] (first, end) row ranges of stream tiles (device int2)
+  int nvlong = 0;
+  int* vlong = nullptr;       // very long rows, longest first (device)
+  int nmed = 0, nmed_blocks = 0;
+  int* med = nullptr;         // medium rows, longest first (device)
+  int* longrows = nullptr;    // every row longer than SHORT_ROW (device; setup kernels)
   int nlong = 0;
+  int blocks() const { return nvlong + nmed_blocks + nstream; }
 };
 
 template <class T>
@@ -67,6 +76,12 @@ struct Level {
   int *agg_ptr = nullptr, *members = nullptr;  // P^T as CSR (aggregate members ascending)
   int* cidx = nullptr;              // ELIM: fine node -> this level's node or -1
   int* cfine = nullptr;             // ELIM: this level's node -> fine node
+  // ELIM restriction P^T r = r_C + R r_F as a CSR over this level's nodes:
+  // columns are fine F nodes, values w_cf / a_ff (FP64 and FP32)
+  int *er_rp = nullptr, *er_ci = nullptr;
+  double* er_val = nullptr;
+  float* er_val32 = nullptr;
+  Tiles er_tiles;
   int nF = 0;
   double gamma_next = 1.0;          // cycle index for visits from this level to the next
   // aggregation diagnostics (this level as the fine side), kept for parity tests
@@ -96,6 +111,9 @@ struct Hierarchy {
   double* r64 = nullptr;   // level-1 outer residual
   double *colb = nullptr, *colx = nullptr;  // column staging of multi-RHS solves
   std::vector<void*> owned;  // every device allocation, freed with the handle
+  // captured cycles: [precision][2 alternating instances]
+  hipStream_t cs = nullptr;  // capture stream
+  hipGraphExec_t gexec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
   double setup_ms = 0;
   int64_t bytes_per_cycle = 0;
 };
@@ -106,6 +124,11 @@ struct Hierarchy {
 // 0 GS FP64, 1 residual FP64, 2 GS FP32, 3 residual FP32.
 void prof_mark(hipStream_t s, int kernel, int64_t bytes, bool begin);
 bool prof_on();
+// Instrumented cycles run eagerly (not from captured graphs) so that every
+// launch has its own timed event pair; prof_flush reads the pending pairs.
+void prof_flush();
+// Message of the last device error on this thread (lamg_last_error).
+void set_last_error(const char* where, hipError_t e);
 
 // ------------------------------------------------------------- allocation
 void* dalloc(Hierarchy* H, size_t bytes);
@@ -135,7 +158,8 @@ void restrict_agg(hipStream_t s, const Level& C, const T* r, T* bc, T mu);
 template <class T>
 void interp_agg(hipStream_t s, const Level& C, int nfine, const T* e, T* x);
 template <class T>
-void restrict_elim(hipStream_t s, const Level& F, const Level& C, const T* val, const T* diag, const T* r, T* bc);
+void restrict_elim(hipStream_t s, const Level& C, const T* r, T* bc);
+void build_elim_restriction(Hierarchy* H, const Level& F, Level& C);
 template <class T>
 void interp_elim(hipStream_t s, const Level& F, const Level& C, const T* val, const T* diag, const T* r, const T* e, T* x);
 template <class T>
@@ -147,6 +171,8 @@ void recombine(hipStream_t s, Hierarchy* H, const Level& L, Vecs<T>& v, int th);
 template <class T>
 void subtract_mean(hipStream_t s, Hierarchy* H, T* x, int n);
 void norm2_async(hipStream_t s, Hierarchy* H, const double* r, int n, double* dst_host);
+// sum of x times scale into result slot `slot` (device side)
+void sum_to_slot(hipStream_t s, Hierarchy* H, const double* x, int n, int slot, double scale);
 void coarsest_solve(hipStream_t s, Hierarchy* H, const double* b, double* x);
 void coarsest_solve32(hipStream_t s, Hierarchy* H, const float* b, float* x);
 void coarsest_factor(Hierarchy* H, const Level& L);
@@ -164,6 +190,10 @@ void finish_levels(Hierarchy* H);
 int64_t cycle_bytes(const Hierarchy* H, int prec);
 template <class T>
 void cycle(Hierarchy* H);
+// Replay one captured cycle (capturing it on first use); `inst` alternates.
+template <class T>
+void cycle_graph(Hierarchy* H, int inst);
+void drop_graphs(Hierarchy* H);
 
 }  // namespace lamg
 

@@ -448,20 +448,50 @@ static int* colour_order_impl(Hierarchy* H, Tmp& tmp, Level& L, int level) {
 }
 
 // Relaxation tiles per colour: consecutive short rows packed into stream
-// blocks (<= TILE_ROWS rows, <= TILE_NNZ entries), long rows listed apart.
+// tiles (<= TILE_ROWS rows, <= TILE_NNZ entries); medium and very long rows
+// listed apart, longest first, so that their blocks are dispatched first.
+static void upload_tiles(Hierarchy* H, Tiles& t, const std::vector<int2>& blocks, std::vector<int> vl,
+                         std::vector<int> md, const std::vector<int>& rph) {
+  hipStream_t s = H->s;
+  auto longer = [&](int a, int b) {
+    const int da = rph[a + 1] - rph[a], db = rph[b + 1] - rph[b];
+    return da != db ? da > db : a < b;
+  };
+  std::sort(vl.begin(), vl.end(), longer);
+  std::sort(md.begin(), md.end(), longer);
+  std::vector<int> all(vl);
+  all.insert(all.end(), md.begin(), md.end());
+  t.nstream = (int)blocks.size();
+  t.nvlong = (int)vl.size();
+  t.nmed = (int)md.size();
+  t.nmed_blocks = (t.nmed + LONG_PER_BLOCK - 1) / LONG_PER_BLOCK;
+  t.nlong = (int)all.size();
+  t.stream = (int*)dnew<int2>(H, blocks.size());
+  t.vlong = dnew<int>(H, vl.size());
+  t.med = dnew<int>(H, md.size());
+  t.longrows = dnew<int>(H, all.size());
+  if (!blocks.empty())
+    LAMG_HIP(hipMemcpyAsync(t.stream, blocks.data(), blocks.size() * sizeof(int2), hipMemcpyHostToDevice, s));
+  if (!vl.empty()) LAMG_HIP(hipMemcpyAsync(t.vlong, vl.data(), vl.size() * sizeof(int), hipMemcpyHostToDevice, s));
+  if (!md.empty()) LAMG_HIP(hipMemcpyAsync(t.med, md.data(), md.size() * sizeof(int), hipMemcpyHostToDevice, s));
+  if (!all.empty()) LAMG_HIP(hipMemcpyAsync(t.longrows, all.data(), all.size() * sizeof(int), hipMemcpyHostToDevice, s));
+  LAMG_HIP(hipStreamSynchronize(s));
+}
+
 void build_tiles(Hierarchy* H, Level& L) {
   hipStream_t s = H->s;
   std::vector<int> rph = to_host_vec(s, L.rp, (size_t)L.n + 1);
   L.tiles.assign(L.ncol, Tiles());
   std::vector<int2> all_s;
-  std::vector<int> all_l;
+  std::vector<int> all_v, all_m;
   for (int c = 0; c < L.ncol; ++c) {
     std::vector<int2> blocks;
-    std::vector<int> lr;
+    std::vector<int> vl, md;
     int a = L.cptr[c];
     const int e = L.cptr[c + 1];
     while (a < e) {
-      if (rph[a + 1] - rph[a] > SHORT_ROW) { lr.push_back(a); ++a; continue; }
+      const int d0 = rph[a + 1] - rph[a];
+      if (d0 > SHORT_ROW) { (d0 > ROW_CHUNK ? vl : md).push_back(a); ++a; continue; }
       int b = a, nz = 0;
       while (b < e && b - a < TILE_ROWS) {
         const int d = rph[b + 1] - rph[b];
@@ -475,31 +505,14 @@ void build_tiles(Hierarchy* H, Level& L) {
     Tiles& t = L.tiles[c];
     t.rows = e - L.cptr[c];
     t.nnz = rph[e] - rph[L.cptr[c]];
-    t.nstream = (int)blocks.size();
-    t.nlong = (int)lr.size();
-    t.nlong_blocks = (t.nlong + LONG_PER_BLOCK - 1) / LONG_PER_BLOCK;
-    t.stream = (int*)dnew<int2>(H, blocks.size());
-    t.longrows = dnew<int>(H, lr.size());
-    if (!blocks.empty())
-      LAMG_HIP(hipMemcpyAsync(t.stream, blocks.data(), blocks.size() * sizeof(int2), hipMemcpyHostToDevice, s));
-    if (!lr.empty())
-      LAMG_HIP(hipMemcpyAsync(t.longrows, lr.data(), lr.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    upload_tiles(H, t, blocks, vl, md, rph);
     all_s.insert(all_s.end(), blocks.begin(), blocks.end());
-    all_l.insert(all_l.end(), lr.begin(), lr.end());
+    all_v.insert(all_v.end(), vl.begin(), vl.end());
+    all_m.insert(all_m.end(), md.begin(), md.end());
   }
-  Tiles& t = L.all;
-  t.rows = L.n;
-  t.nnz = rph[L.n];
-  t.nstream = (int)all_s.size();
-  t.nlong = (int)all_l.size();
-  t.nlong_blocks = (t.nlong + LONG_PER_BLOCK - 1) / LONG_PER_BLOCK;
-  t.stream = (int*)dnew<int2>(H, all_s.size());
-  t.longrows = dnew<int>(H, all_l.size());
-  if (!all_s.empty())
-    LAMG_HIP(hipMemcpyAsync(t.stream, all_s.data(), all_s.size() * sizeof(int2), hipMemcpyHostToDevice, s));
-  if (!all_l.empty())
-    LAMG_HIP(hipMemcpyAsync(t.longrows, all_l.data(), all_l.size() * sizeof(int), hipMemcpyHostToDevice, s));
-  LAMG_HIP(hipStreamSynchronize(s));
+  L.all.rows = L.n;
+  L.all.nnz = rph[L.n];
+  upload_tiles(H, L.all, all_s, all_v, all_m, rph);
 }
 
 void colour_and_order(Hierarchy* H, Level& L, int level, std::vector<int>*) {
@@ -565,6 +578,34 @@ __global__ void k_schur_emit(int n, uint64_t nc, const int* __restrict__ rp, con
       ++o;
     }
 }
+// C-side restriction stencil: for coarse node c (fine node cfine[c]) the F
+// neighbours f in column order with coefficient w_cf / a_ff.
+__global__ void k_er_counts(int nc, const int* __restrict__ cfine, const int* __restrict__ cidx,
+                            const int* __restrict__ rp, const int* __restrict__ ci, int* __restrict__ cnt) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  const int u = cfine[c];
+  int k = 0;
+  for (int t = rp[u]; t < rp[u + 1]; ++t) k += cidx[ci[t]] < 0;
+  cnt[c] = k;
+}
+__global__ void k_er_fill(int nc, const int* __restrict__ cfine, const int* __restrict__ cidx,
+                          const int* __restrict__ rp, const int* __restrict__ ci, const double* __restrict__ val,
+                          const double* __restrict__ diag, const int* __restrict__ erp, int* __restrict__ eci,
+                          double* __restrict__ ev, float* __restrict__ ev32) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  const int u = cfine[c];
+  int o = erp[c];
+  for (int t = rp[u]; t < rp[u + 1]; ++t) {
+    const int f = ci[t];
+    if (cidx[f] >= 0) continue;
+    eci[o] = f;
+    ev[o] = val[t] / diag[f];
+    ev32[o] = (float)val[t] / (float)diag[f];
+    ++o;
+  }
+}
 __global__ void k_elim_maps(int n, const int* __restrict__ inF, const int* __restrict__ crank,
                             const int* __restrict__ cinv, int* __restrict__ cidx, int* __restrict__ cfine) {
   const int u = blockIdx.x * blockDim.x + threadIdx.x;
@@ -575,6 +616,31 @@ __global__ void k_elim_maps(int n, const int* __restrict__ inF, const int* __res
   cfine[c] = u;
 }
 }  // namespace
+
+void build_elim_restriction(Hierarchy* H, const Level& F, Level& C) {
+  hipStream_t s = H->s;
+  Tmp tmp;
+  const int nc = C.n;
+  int* cnt = tmp.get<int>(nc + 1);
+  hipLaunchKernelGGL(k_er_counts, grid1(nc), dim3(256), 0, s, nc, C.cfine, C.cidx, F.rp, F.ci, cnt);
+  C.er_rp = dnew<int>(H, (size_t)nc + 1);
+  excl_scan(s, tmp, cnt, C.er_rp, nc);
+  const int ne = to_host(s, C.er_rp + nc);
+  C.er_ci = dnew<int>(H, std::max(ne, 1));
+  C.er_val = dnew<double>(H, std::max(ne, 1));
+  C.er_val32 = dnew<float>(H, std::max(ne, 1));
+  hipLaunchKernelGGL(k_er_fill, grid1(nc), dim3(256), 0, s, nc, C.cfine, C.cidx, F.rp, F.ci, F.val, F.diag, C.er_rp,
+                     C.er_ci, C.er_val, C.er_val32);
+  // tiles over the stencil rows (a single class: rows are independent)
+  Level R;
+  R.n = nc;
+  R.rp = C.er_rp;
+  R.ci = C.er_ci;
+  R.ncol = 1;
+  R.cptr = {0, nc};
+  build_tiles(H, R);
+  C.er_tiles = R.all;
+}
 
 bool try_eliminate(Hierarchy* H, int l) {
   hipStream_t s = H->s;
@@ -619,6 +685,7 @@ bool try_eliminate(Hierarchy* H, int l) {
   C.cidx = dnew<int>(H, n);
   C.cfine = dnew<int>(H, nc);
   hipLaunchKernelGGL(k_elim_maps, grid1(n), dim3(256), 0, s, n, inF, crank, cinv, C.cidx, C.cfine);
+  build_elim_restriction(H, F, C);
   LAMG_HIP(hipStreamSynchronize(s));
   H->lv.push_back(C);
   return true;

@@ -20,54 +20,129 @@ namespace lamg {
 // sums with stride 64 and folds with an xor butterfly.  A GS pass only ever
 // covers one colour class, whose rows are pairwise non-adjacent, so the rows
 // it writes are never read in the same launch.
+// MODE 0: GS update; MODE 1: residual; MODE 2: elimination restriction
+// out_u = x_{map(u)} + sum (the gathered vector is the fine residual).
+template <class T, int MODE>
+__device__ inline void relax_store(int u, T s, const T* __restrict__ diag, const T* __restrict__ b, T* x,
+                                   T* __restrict__ r, const int* __restrict__ map) {
+  if (MODE == 2) { r[u] = x[map[u]] + s; return; }
+  const T bu = b ? b[u] : T(0);
+  if (MODE == 0) x[u] = (bu + s) / diag[u];
+  else r[u] = (bu + s) - diag[u] * x[u];
+}
+
+// One 512-entry chunk of a long row, one wavefront: lane j sums the chunk's
+// entries j, j+64, ... left to right (all loads issued before the gathers),
+// then the butterfly folds the 64 partials.
+template <class T>
+__device__ inline T chunk_sum(const int* __restrict__ ci, const T* __restrict__ val, const T* x, int p0, int c0,
+                              int len, int lane) {
+  constexpr int UNR = ROW_CHUNK / 64;
+  int cj[UNR];
+  T wj[UNR], xj[UNR];
+#pragma unroll
+  for (int q = 0; q < UNR; ++q) {
+    const int t = c0 + lane + 64 * q;
+    cj[q] = t < len ? ci[p0 + t] : 0;
+    wj[q] = t < len ? val[p0 + t] : T(0);
+  }
+#pragma unroll
+  for (int q = 0; q < UNR; ++q) xj[q] = x[cj[q]];
+  T s = 0;
+#pragma unroll
+  for (int q = 0; q < UNR; ++q)
+    if (c0 + lane + 64 * q < len) s += wj[q] * xj[q];
+  return dev::wave_fold(s);
+}
+
 template <class T, int MODE>
 __global__ __launch_bounds__(RELAX_THREADS) void k_relax(
     const int* __restrict__ rp, const int* __restrict__ ci, const T* __restrict__ val,
     const T* __restrict__ diag, const T* __restrict__ b, T* x, T* __restrict__ r,
-    const int2* __restrict__ sblk, int nstream, const int* __restrict__ longrows, int nlong) {
+    const int* __restrict__ vlong, int nvlong, const int* __restrict__ med, int nmed, int nmed_blocks,
+    const int2* __restrict__ sblk, int nstream, const int* __restrict__ map) {
+  constexpr int PER = TILE_NNZ / RELAX_THREADS;  // entries per thread in a stream tile
+  constexpr int MAXC = 64;                       // chunk sums staged per pass
   __shared__ T prod[TILE_NNZ];
   __shared__ int srp[TILE_ROWS + 1];
-  const int bid = blockIdx.x;
-  if (bid < nstream) {
-    const int2 rr = sblk[bid];
-    const int nr = rr.y - rr.x;
-    for (int i = threadIdx.x; i <= nr; i += RELAX_THREADS) srp[i] = rp[rr.x + i];
-    __syncthreads();
-    const int base = srp[0];
-    const int cnt = srp[nr] - base;
-    for (int j = threadIdx.x; j < cnt; j += RELAX_THREADS) prod[j] = val[base + j] * x[ci[base + j]];
-    __syncthreads();
-    if (threadIdx.x < nr) {
-      const int u = rr.x + threadIdx.x;
-      const int j1 = srp[threadIdx.x + 1] - base;
-      T s = 0;
-      for (int j = srp[threadIdx.x] - base; j < j1; ++j) s += prod[j];
-      const T bu = b ? b[u] : T(0);
-      if (MODE == 0) x[u] = (bu + s) / diag[u];
-      else r[u] = (bu + s) - diag[u] * x[u];
+  __shared__ T csum[MAXC];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  int bid = blockIdx.x;
+  if (bid < nvlong) {
+    // a very long row: chunks k = wv, wv+4, ... per pass; chunk sums added in order
+    const int u = vlong[bid];
+    const int p0 = rp[u], len = rp[u + 1] - p0;
+    const int nch = (len + ROW_CHUNK - 1) / ROW_CHUNK;
+    T total = 0;
+    for (int pass = 0; pass < nch; pass += MAXC) {
+      const int lim = min(MAXC, nch - pass);
+      for (int k = wv; k < lim; k += LONG_PER_BLOCK) {
+        const T sk = chunk_sum<T>(ci, val, x, p0, (pass + k) * ROW_CHUNK, len, lane);
+        if (lane == 0) csum[k] = sk;
+      }
+      __syncthreads();
+      if (threadIdx.x == 0)
+        for (int k = 0; k < lim; ++k) total += csum[k];
+      __syncthreads();
     }
+    if (threadIdx.x == 0) relax_store<T, MODE>(u, total, diag, b, x, r, map);
     return;
   }
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int idx = (bid - nstream) * LONG_PER_BLOCK + wv;
-  if (idx >= nlong) return;
-  const int u = longrows[idx];
-  const int p0 = rp[u], len = rp[u + 1] - p0;
-  T s = 0;
-  for (int t = lane; t < len; t += 64) s += val[p0 + t] * x[ci[p0 + t]];
-  s = dev::wave_fold(s);
-  if (lane == 0) {
-    const T bu = b ? b[u] : T(0);
-    if (MODE == 0) x[u] = (bu + s) / diag[u];
-    else r[u] = (bu + s) - diag[u] * x[u];
+  bid -= nvlong;
+  if (bid < nmed_blocks) {
+    const int idx = bid * LONG_PER_BLOCK + wv;
+    if (idx >= nmed) return;
+    const int u = med[idx];
+    const int p0 = rp[u], len = rp[u + 1] - p0;
+    const T sk = chunk_sum<T>(ci, val, x, p0, 0, len, lane);
+    T total = 0;
+    total += sk;
+    if (lane == 0) relax_store<T, MODE>(u, total, diag, b, x, r, map);
+    return;
+  }
+  bid -= nmed_blocks;
+  const int2 rr = sblk[bid];
+  const int nr = rr.y - rr.x;
+  for (int i = threadIdx.x; i <= nr; i += RELAX_THREADS) srp[i] = rp[rr.x + i];
+  __syncthreads();
+  const int base = srp[0];
+  const int cnt = srp[nr] - base;
+  // all index and weight loads first, then all gathers: PER loads in flight per thread
+  int cj[PER];
+  T wj[PER], xj[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int j = threadIdx.x + q * RELAX_THREADS;
+    cj[q] = j < cnt ? ci[base + j] : 0;
+    wj[q] = j < cnt ? val[base + j] : T(0);
+  }
+#pragma unroll
+  for (int q = 0; q < PER; ++q) xj[q] = x[cj[q]];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int j = threadIdx.x + q * RELAX_THREADS;
+    if (j < cnt) prod[j] = wj[q] * xj[q];
+  }
+  __syncthreads();
+  if (threadIdx.x < nr) {
+    const int j1 = srp[threadIdx.x + 1] - base;
+    T s = 0;
+    for (int j = srp[threadIdx.x] - base; j < j1; ++j) s += prod[j];
+    relax_store<T, MODE>(rr.x + threadIdx.x, s, diag, b, x, r, map);
   }
 }
 
 template <class T, int MODE>
-static void launch_relax(hipStream_t s, const Level& L, const Tiles& t, const T* val, const T* diag,
-                         const T* b, T* x, T* r) {
-  const int grid = t.nstream + t.nlong_blocks;
+static void launch_relax(hipStream_t s, const int* rp, const int* ci, const Tiles& t, const T* val, const T* diag,
+                         const T* b, T* x, T* r, const int* map = nullptr) {
+  const int grid = t.blocks();
   if (grid == 0) return;
+  if (MODE == 2) {
+    hipLaunchKernelGGL((k_relax<T, MODE>), dim3(grid), dim3(RELAX_THREADS), 0, s, rp, ci, val, diag, b, x, r,
+                       t.vlong, t.nvlong, t.med, t.nmed, t.nmed_blocks, (const int2*)t.stream, t.nstream, map);
+    LAMG_HIP(hipGetLastError());
+    return;
+  }
   const bool prof = prof_on();
   const int kid = MODE + (sizeof(T) == 4 ? 2 : 0);
   // matrix stream (column index + value per entry, row pointer + diagonal per
@@ -75,48 +150,73 @@ static void launch_relax(hipStream_t s, const Level& L, const Tiles& t, const T*
   const int64_t bytes = t.nnz * (4 + (int64_t)sizeof(T)) + t.rows * (4 + (int64_t)sizeof(T)) +
                         3 * t.rows * (int64_t)sizeof(T);
   if (prof) prof_mark(s, kid, bytes, true);
-  hipLaunchKernelGGL((k_relax<T, MODE>), dim3(grid), dim3(RELAX_THREADS), 0, s, L.rp, L.ci, val, diag, b, x, r,
-                     (const int2*)t.stream, t.nstream, t.longrows, t.nlong);
+  hipLaunchKernelGGL((k_relax<T, MODE>), dim3(grid), dim3(RELAX_THREADS), 0, s, rp, ci, val, diag, b, x, r,
+                     t.vlong, t.nvlong, t.med, t.nmed, t.nmed_blocks, (const int2*)t.stream, t.nstream, map);
   if (prof) prof_mark(s, kid, bytes, false);
   LAMG_HIP(hipGetLastError());
 }
 
 // ---------------------------------------------------------- instrumentation
 namespace {
+struct Pair {
+  hipEvent_t a, b;
+  int kid;
+  int64_t bytes;
+};
 struct Prof {
   bool on = false;
-  std::vector<hipEvent_t> ev;  // pairs (begin, end)
-  std::vector<int> kid;
-  size_t used = 0;
+  std::vector<Pair> pend;  // launches whose events are not read yet
+  std::vector<hipEvent_t> pool;
+  double ms[4] = {0, 0, 0, 0};
   int64_t bytes[4] = {0, 0, 0, 0}, launches[4] = {0, 0, 0, 0};
 };
 Prof g_prof;
+hipEvent_t new_event() {
+  Prof& P = g_prof;
+  if (!P.pool.empty()) {
+    hipEvent_t e = P.pool.back();
+    P.pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  LAMG_HIP(hipEventCreate(&e));
+  return e;
+}
 }  // namespace
 bool prof_on() { return g_prof.on; }
 void prof_mark(hipStream_t s, int kernel, int64_t bytes, bool begin) {
   Prof& P = g_prof;
   if (begin) {
-    if (P.used + 2 > P.ev.size()) {
-      for (int i = 0; i < 2; ++i) {
-        hipEvent_t e;
-        LAMG_HIP(hipEventCreate(&e));
-        P.ev.push_back(e);
-      }
-      P.kid.push_back(0);
-    }
-    P.kid[P.used / 2] = kernel;
-    LAMG_HIP(hipEventRecord(P.ev[P.used], s));
+    Pair q;
+    q.a = new_event();
+    q.b = new_event();
+    q.kid = kernel;
+    q.bytes = bytes;
+    LAMG_HIP(hipEventRecord(q.a, s));
+    P.pend.push_back(q);
   } else {
-    LAMG_HIP(hipEventRecord(P.ev[P.used + 1], s));
-    P.used += 2;
-    P.bytes[kernel] += bytes;
-    P.launches[kernel] += 1;
+    LAMG_HIP(hipEventRecord(P.pend.back().b, s));
   }
+}
+// Read every pending event pair (waiting for it) into the per-kernel totals.
+void prof_flush() {
+  Prof& P = g_prof;
+  for (const Pair& q : P.pend) {
+    float t = 0;
+    LAMG_HIP(hipEventSynchronize(q.b));
+    LAMG_HIP(hipEventElapsedTime(&t, q.a, q.b));
+    P.ms[q.kid] += t;
+    P.bytes[q.kid] += q.bytes;
+    P.launches[q.kid] += 1;
+    P.pool.push_back(q.a);
+    P.pool.push_back(q.b);
+  }
+  P.pend.clear();
 }
 
 template <class T>
 void gs_colour(hipStream_t s, const Level& L, int c, const T* val, const T* diag, const T* b, T* x) {
-  launch_relax<T, 0>(s, L, L.tiles[c], val, diag, b, x, (T*)nullptr);
+  launch_relax<T, 0>(s, L.rp, L.ci, L.tiles[c], val, diag, b, x, (T*)nullptr);
 }
 template <class T>
 void gs_sweep(hipStream_t s, const Level& L, const T* val, const T* diag, const T* b, T* x) {
@@ -124,7 +224,7 @@ void gs_sweep(hipStream_t s, const Level& L, const T* val, const T* diag, const 
 }
 template <class T>
 void residual(hipStream_t s, const Level& L, const T* val, const T* diag, const T* b, const T* x, T* r) {
-  launch_relax<T, 1>(s, L, L.all, val, diag, b, (T*)x, r);
+  launch_relax<T, 1>(s, L.rp, L.ci, L.all, val, diag, b, (T*)x, r);
 }
 template void gs_colour<double>(hipStream_t, const Level&, int, const double*, const double*, const double*, double*);
 template void gs_colour<float>(hipStream_t, const Level&, int, const float*, const float*, const float*, float*);
@@ -171,9 +271,7 @@ __global__ __launch_bounds__(256) void k_gs_multi_long(const int* __restrict__ r
   const int u = longrows[idx];
   const int p0 = rp[u], len = rp[u + 1] - p0;
   for (int k = 0; k < K; ++k) {
-    double s = 0;
-    for (int t = lane; t < len; t += 64) s += val[p0 + t] * X[(size_t)ci[p0 + t] * K + k];
-    s = dev::wave_fold(s);
+    const double s = dev::row_sum_wave<double>(len, lane, [&](int t) { return val[p0 + t] * X[(size_t)ci[p0 + t] * K + k]; });
     if (lane == 0) {
       const double bu = B ? B[(size_t)u * K + k] : 0.0;
       X[(size_t)u * K + k] = (bu + s) / diag[u];
@@ -213,22 +311,6 @@ __global__ void k_interp_agg(int n, const int* __restrict__ agg, const T* __rest
   const int u = blockIdx.x * blockDim.x + threadIdx.x;
   if (u < n) x[u] += e[agg[u]];
 }
-// Elimination restriction P^T r (eq. elim): r_c + sum_{f in F, adjacent}
-// (w_cf / a_ff) r_f in column order.
-template <class T>
-__global__ void k_restrict_elim(int nc, const int* __restrict__ cfine, const int* __restrict__ cidx,
-                                const int* __restrict__ rp, const int* __restrict__ ci, const T* __restrict__ val,
-                                const T* __restrict__ diag, const T* __restrict__ r, T* __restrict__ bc) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= nc) return;
-  const int u = cfine[c];
-  T s = r[u];
-  for (int t = rp[u]; t < rp[u + 1]; ++t) {
-    const int f = ci[t];
-    if (cidx[f] < 0) s += (val[t] / diag[f]) * r[f];
-  }
-  bc[c] = s;
-}
 // Exact elimination correction: e_C = e^c, e_F = (r_F + W_FC e^c) / a_FF.
 template <class T>
 __global__ void k_interp_elim(int n, const int* __restrict__ cidx, const int* __restrict__ rp, const int* __restrict__ ci,
@@ -258,9 +340,15 @@ template <class T>
 void interp_agg(hipStream_t s, const Level& C, int nfine, const T* e, T* x) {
   hipLaunchKernelGGL(k_interp_agg<T>, g1(nfine), dim3(256), 0, s, nfine, C.agg, e, x);
 }
+// Elimination restriction on the precomputed C-side stencil, with the
+// relaxation kernel's tiling (hub rows of C nodes have many F neighbours).
 template <class T>
-void restrict_elim(hipStream_t s, const Level& F, const Level& C, const T* val, const T* diag, const T* r, T* bc) {
-  hipLaunchKernelGGL(k_restrict_elim<T>, g1(C.n), dim3(256), 0, s, C.n, C.cfine, C.cidx, F.rp, F.ci, val, diag, r, bc);
+void restrict_elim(hipStream_t s, const Level& C, const T* r, T* bc) {
+  const T* ev;
+  if constexpr (sizeof(T) == 8) ev = (const T*)C.er_val;
+  else ev = (const T*)C.er_val32;
+  launch_relax<T, 2>(s, C.er_rp, C.er_ci, C.er_tiles, ev, (const T*)nullptr, (const T*)nullptr, (T*)r, bc,
+                     C.cfine);
 }
 template <class T>
 void interp_elim(hipStream_t s, const Level& F, const Level& C, const T* val, const T* diag, const T* r, const T* e,
@@ -274,7 +362,7 @@ void fill(hipStream_t s, T* p, T v, int n) {
 #define INST(T)                                                                                         \
   template void restrict_agg<T>(hipStream_t, const Level&, const T*, T*, T);                           \
   template void interp_agg<T>(hipStream_t, const Level&, int, const T*, T*);                           \
-  template void restrict_elim<T>(hipStream_t, const Level&, const Level&, const T*, const T*, const T*, T*); \
+  template void restrict_elim<T>(hipStream_t, const Level&, const T*, T*);                             \
   template void interp_elim<T>(hipStream_t, const Level&, const Level&, const T*, const T*, const T*, const T*, T*); \
   template void fill<T>(hipStream_t, T*, T, int);
 INST(double)
@@ -328,12 +416,26 @@ __global__ __launch_bounds__(k::RED_THREADS) void k_recomb_dots(int n, int th, c
 // Sum the block partials in a fixed order and solve the th x th normal
 // equations of min || r + sum_i alpha_i d_i || (eq. recomb).  A direction is
 // dropped when its Gram entry is negligible or the 2x2 system is singular.
-__global__ void k_recomb_alpha(int nblk, int th, const double* part, double* res) {
+// Sum slot `slot` of nblk block partials with a fixed tree (256 threads).
+__device__ inline double finish_slot(int nblk, const double* part, int slot) {
+  __shared__ double sh[256];
+  double v = 0;
+  for (int b = threadIdx.x; b < nblk; b += 256) v += part[b * NSLOT + slot];
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+__global__ __launch_bounds__(256) void k_recomb_alpha(int nblk, int th, const double* part, double* res) {
   __shared__ double tot[6];
-  if (threadIdx.x < 6) {
-    double s = 0;
-    for (int b = 0; b < nblk; ++b) s += part[b * NSLOT + threadIdx.x];
-    tot[threadIdx.x] = s;
+  for (int q = 0; q < 6; ++q) {
+    const double v = finish_slot(nblk, part, q);
+    if (threadIdx.x == 0) tot[q] = v;
   }
   __syncthreads();
   if (threadIdx.x != 0) return;
@@ -383,7 +485,7 @@ void recombine(hipStream_t s, Hierarchy* H, const Level& L, Vecs<T>& v, int th) 
   const int nb = red_grid(L.n);
   hipLaunchKernelGGL(k_recomb_dots<T>, dim3(nb), dim3(k::RED_THREADS), 0, s, L.n, th, v.r, v.R[0], v.R[1],
                      red_part(H));
-  hipLaunchKernelGGL(k_recomb_alpha, dim3(1), dim3(64), 0, s, nb, th, red_part(H), red_res(H));
+  hipLaunchKernelGGL(k_recomb_alpha, dim3(1), dim3(256), 0, s, nb, th, red_part(H), red_res(H));
   hipLaunchKernelGGL(k_recomb_update<T>, g1(L.n), dim3(256), 0, s, L.n, th, red_res(H), v.X[0], v.X[1], v.x);
   LAMG_HIP(hipGetLastError());
 }
@@ -405,11 +507,9 @@ __global__ __launch_bounds__(k::RED_THREADS) void k_sumsq(int n, const T* __rest
   }
   block_sum_store<1>(v, part + blockIdx.x * NSLOT);
 }
-__global__ void k_finish(int nblk, const double* part, double* res, int slot, double scale) {
-  if (threadIdx.x != 0) return;
-  double s = 0;
-  for (int b = 0; b < nblk; ++b) s += part[b * NSLOT];
-  res[slot] = s * scale;
+__global__ __launch_bounds__(256) void k_finish(int nblk, const double* part, double* res, int slot, double scale) {
+  const double s = finish_slot(nblk, part, 0);
+  if (threadIdx.x == 0) res[slot] = s * scale;
 }
 template <class T>
 __global__ void k_sub_mean(int n, const double* __restrict__ res, int slot, T* __restrict__ x) {
@@ -417,11 +517,17 @@ __global__ void k_sub_mean(int n, const double* __restrict__ res, int slot, T* _
   if (u < n) x[u] = (T)((double)x[u] - res[slot]);
 }
 
+void sum_to_slot(hipStream_t s, Hierarchy* H, const double* x, int n, int slot, double scale) {
+  const int nb = red_grid(n);
+  hipLaunchKernelGGL(k_sum<double>, dim3(nb), dim3(k::RED_THREADS), 0, s, n, x, red_part(H));
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, nb, red_part(H), red_res(H), slot, scale);
+}
+
 template <class T>
 void subtract_mean(hipStream_t s, Hierarchy* H, T* x, int n) {
   const int nb = red_grid(n);
   hipLaunchKernelGGL(k_sum<T>, dim3(nb), dim3(k::RED_THREADS), 0, s, n, x, red_part(H));
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, s, nb, red_part(H), red_res(H), 4, 1.0 / (double)n);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, nb, red_part(H), red_res(H), 4, 1.0 / (double)n);
   hipLaunchKernelGGL(k_sub_mean<T>, g1(n), dim3(256), 0, s, n, red_res(H), 4, x);
   LAMG_HIP(hipGetLastError());
 }
@@ -432,7 +538,7 @@ template void subtract_mean<float>(hipStream_t, Hierarchy*, float*, int);
 void norm2_async(hipStream_t s, Hierarchy* H, const double* r, int n, double* dst_host) {
   const int nb = red_grid(n);
   hipLaunchKernelGGL(k_sumsq<double>, dim3(nb), dim3(k::RED_THREADS), 0, s, n, r, red_part(H));
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, s, nb, red_part(H), red_res(H), 5, 1.0);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, nb, red_part(H), red_res(H), 5, 1.0);
   LAMG_HIP(hipMemcpyAsync(dst_host, red_res(H) + 5, sizeof(double), hipMemcpyDeviceToHost, s));
 }
 
@@ -525,22 +631,22 @@ void coarsest_factor(Hierarchy* H, const Level& L) {
 extern "C" {
 void lamg_t_prof_enable(int on) {
   lamg::Prof& P = lamg::g_prof;
+  try {
+    lamg::prof_flush();
+  } catch (const lamg::DevError&) {
+  }
   P.on = on != 0;
-  P.used = 0;
-  for (int k = 0; k < 4; ++k) { P.bytes[k] = 0; P.launches[k] = 0; }
+  for (int k = 0; k < 4; ++k) { P.ms[k] = 0; P.bytes[k] = 0; P.launches[k] = 0; }
 }
 lamg_status lamg_t_prof_read(int kernel, double* ms, int64_t* launches, int64_t* bytes) {
   lamg::Prof& P = lamg::g_prof;
   if (kernel < 0 || kernel > 3 || !ms || !launches || !bytes) return LAMG_E_INVALID_ARG;
-  double tot = 0;
-  for (size_t i = 0; i + 1 < P.used + 1 && i < P.used; i += 2) {
-    if (P.kid[i / 2] != kernel) continue;
-    if (hipEventSynchronize(P.ev[i + 1]) != hipSuccess) return LAMG_E_DEVICE;
-    float t = 0;
-    if (hipEventElapsedTime(&t, P.ev[i], P.ev[i + 1]) != hipSuccess) return LAMG_E_DEVICE;
-    tot += t;
+  try {
+    lamg::prof_flush();
+  } catch (const lamg::DevError&) {
+    return LAMG_E_DEVICE;
   }
-  *ms = tot;
+  *ms = P.ms[kernel];
   *launches = P.launches[kernel];
   *bytes = P.bytes[kernel];
   return LAMG_OK;

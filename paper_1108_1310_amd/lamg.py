@@ -44,7 +44,8 @@ class Info(C.Structure):
 class LamgError(RuntimeError):
     def __init__(self, status: int, where: str):
         self.status = status
-        super().__init__(f"{where}: {lib().lamg_status_str(status).decode()} (status {status})")
+        detail = lib().lamg_last_error().decode() if status in (E_DEVICE, E_OUT_OF_MEMORY) else ""
+        super().__init__(f"{where}: {lib().lamg_status_str(status).decode()} (status {status}) {detail}".rstrip())
 
 
 _lib = None
@@ -66,6 +67,7 @@ def lib():
             "lamg_set_solve_options": (C.c_int, [vp, C.POINTER(Options)]),
             "lamg_free": (None, [vp]),
             "lamg_status_str": (C.c_char_p, [C.c_int]),
+            "lamg_last_error": (C.c_char_p, []),
             "lamg_t_num_levels": (C.c_int, [vp]),
             "lamg_t_coarsest_relax": (C.c_int, [vp]),
             "lamg_t_level_dims": (C.c_int, [vp, C.c_int, C.POINTER(i64)]),
