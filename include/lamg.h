@@ -62,6 +62,9 @@ typedef struct lamg_options {
                                (Section 4.1: "until relaxation converges rapidly") */
   int coarsest_sweeps;      /* GS sweeps solving such a coarsest level, 3 */
   int dense_max;            /* largest coarsest level solved densely, 8192 */
+  int tail_max_n;           /* coarse levels with at most this many nodes (and all
+                               coarser ones) run inside one workgroup per entry, 4096;
+                               0 = every level launches its own kernels */
   lamg_energy_correction ec;
   lamg_precision precision;
   double tol;               /* relative residual target, 1e-8 */
@@ -112,6 +115,16 @@ lamg_status lamg_solve(lamg_handle h, const double* b, double* x, lamg_info* inf
  * on the current device. */
 lamg_status lamg_solve_batch(int32_t count, const lamg_handle* hs, const int32_t* nrhs,
                              const double* const* B, double* const* X, lamg_info* infos);
+
+/* Adjoint edge gradient of a solve x = A^+ b (spec differentiable form):
+ * for a loss L with dL/dx = g, the caller solves A lam = g (lamg_solve on the
+ * same hierarchy, since A is symmetric) and this kernel forms
+ *   grad_w[e] = -(lam[eu[e]] - lam[ev[e]]) (x[eu[e]] - x[ev[e]])
+ * for every input edge e.  eu, ev DEVICE int32[m] (indices are not checked
+ * here: pass the arrays given to lamg_setup); x, lam DEVICE double[n];
+ * grad_w DEVICE double[m] out.  stream: hipStream_t (NULL = null stream). */
+lamg_status lamg_edge_gradient(int64_t m, const int32_t* eu, const int32_t* ev, const double* x,
+                               const double* lam, double* grad_w, void* stream);
 
 /* Change solve-phase options of an existing hierarchy (precision, ec, tol,
  * max_cycles, warm_start, stream); setup-phase fields are ignored. */

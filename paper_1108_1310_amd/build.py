@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpaper_lamg.so")
-SOURCES = ["lamg_solve_kernels.hip", "lamg_setup.hip", "lamg_api.hip", "lamg_test_api.hip"]
+SOURCES = ["lamg_solve_kernels.hip", "lamg_setup.hip", "lamg_tail.hip", "lamg_api.hip", "lamg_test_api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -33,7 +33,7 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(jobs: int = 4) -> str:
+def build(jobs: int = 5) -> str:
     os.makedirs(BUILD, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(_compile, SOURCES))

@@ -108,6 +108,7 @@ void body(Hierarchy* H, int l, int sub, std::vector<int64_t>& count) {
 template <class T>
 void visit(Hierarchy* H, int l, int th, std::vector<int64_t>& count) {
   const int Lc = (int)H->lv.size() - 1;
+  if (l == H->tail_lc) { tail_run_next<T>(H); return; }  // this entry's program segment
   if (l == Lc) { body<T>(H, l, 0, count); return; }
   for (int i = 0; i < th; ++i) body<T>(H, l, i, count);
   if (H->o.ec == LAMG_EC_RECOMBINE && H->lv[l + 1].type == LT_AGG)
@@ -117,10 +118,12 @@ void visit(Hierarchy* H, int l, int th, std::vector<int64_t>& count) {
 
 template <class T>
 void cycle(Hierarchy* H) {
+  tail_prepare(H);
+  H->tail_cursor = 0;
   std::vector<int64_t> count(H->lv.size(), 0);
   visit<T>(H, 0, 1, count);
   Level& L = H->lv[0];
-  subtract_mean<T>(H->s, H, Prec<T>::v(L).x, L.n);
+  if (H->tail_lc != 0) subtract_mean<T>(H->s, H, Prec<T>::v(L).x, L.n);  // else in the tail program
   LAMG_HIP(hipGetLastError());
 }
 template void cycle<double>(Hierarchy*);
@@ -134,6 +137,7 @@ template <class T>
 void cycle_graph(Hierarchy* H, int inst) {
   if (prof_on()) { cycle<T>(H); return; }
   const int p = sizeof(T) == 8 ? 0 : 1;
+  tail_prepare(H);  // uploads with synchronous copies: before any capture
   if (!H->gexec[p][inst]) {
     if (!H->cs) LAMG_HIP(hipStreamCreateWithFlags(&H->cs, hipStreamNonBlocking));
     hipStream_t user = H->s;
@@ -263,6 +267,7 @@ void lamg_options_default(lamg_options* o) {
   o->relax_fast_ratio = 0.1;
   o->coarsest_sweeps = 3;
   o->dense_max = 8192;
+  o->tail_max_n = 4096;
   o->ec = LAMG_EC_RECOMBINE;
   o->precision = LAMG_FP64;
   o->tol = 1e-8;
@@ -292,7 +297,7 @@ static bool opts_ok(const lamg_options& o) {
   return o.gamma >= 1.0 && o.gamma <= 2.0 && o.nu_pre >= 0 && o.nu_post >= 0 && o.tv_k_min >= 1 &&
          o.tv_k_max >= o.tv_k_min && o.tv_k_max <= 10 && o.tv_sweeps >= 0 && o.q_max > 1.0 && o.coarsest_max_n >= 2 &&
          o.elim_max_degree >= 0 && o.stage1_quantile >= 0.0 && o.stage1_quantile <= 1.0 && o.tol >= 0 &&
-         o.max_cycles >= 0 && o.coarsest_sweeps >= 1 && o.dense_max >= 1 && o.dense_max <= 8192;
+         o.max_cycles >= 0 && o.coarsest_sweeps >= 1 && o.dense_max >= 1 && o.dense_max <= 8192 && o.tail_max_n >= 0;
 }
 
 lamg_status lamg_setup(int64_t n, int64_t m, const int32_t* eu, const int32_t* ev, const double* w,
@@ -352,7 +357,12 @@ lamg_status lamg_set_solve_options(lamg_handle h, const lamg_options* o) {
       (o->ec != LAMG_EC_RECOMBINE && o->ec != LAMG_EC_FLAT_MU))
     return LAMG_E_INVALID_ARG;
   Hierarchy* H = &h->H;
-  drop_graphs(H);  // the captured cycles depend on these options
+  // the captured cycles and the tail program depend on these options
+  if (o->ec != H->o.ec || o->mu != H->o.mu || o->nu_pre != H->o.nu_pre || o->nu_post != H->o.nu_post) {
+    drop_graphs(H);
+    H->tail_lc = -1;
+  }
+  if (o->nu_pre < 0 || o->nu_post < 0) return LAMG_E_INVALID_ARG;
   H->o.precision = o->precision;
   H->o.ec = o->ec;
   H->o.mu = o->mu;
@@ -493,6 +503,31 @@ lamg_status lamg_solve_batch(int32_t count, const lamg_handle* hs, const int32_t
     return e.e == hipErrorOutOfMemory ? LAMG_E_OUT_OF_MEMORY : LAMG_E_DEVICE;
   }
   return worst;
+}
+
+namespace {
+__global__ void k_edge_grad(int64_t m, const int32_t* __restrict__ eu, const int32_t* __restrict__ ev,
+                            const double* __restrict__ x, const double* __restrict__ lam, double* __restrict__ g) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m) return;
+  const int u = eu[e], v = ev[e];
+  g[e] = -(lam[u] - lam[v]) * (x[u] - x[v]);
+}
+}  // namespace
+
+lamg_status lamg_edge_gradient(int64_t m, const int32_t* eu, const int32_t* ev, const double* x, const double* lam,
+                               double* grad_w, void* stream) {
+  if (m < 0 || (m > 0 && (!eu || !ev || !x || !lam || !grad_w))) return LAMG_E_INVALID_ARG;
+  if (m == 0) return LAMG_OK;
+  try {
+    hipLaunchKernelGGL(k_edge_grad, grid1(m), dim3(256), 0, (hipStream_t)stream, m, eu, ev, x, lam, grad_w);
+    LAMG_HIP(hipGetLastError());
+    LAMG_HIP(hipStreamSynchronize((hipStream_t)stream));
+  } catch (const DevError& e) {
+    set_last_error("lamg_edge_gradient", e.e);
+    return LAMG_E_DEVICE;
+  }
+  return LAMG_OK;
 }
 
 void lamg_free(lamg_handle h) {

@@ -71,6 +71,7 @@ struct Level {
   int* perm = nullptr;              // node order: perm[new] = natural id
   std::vector<Tiles> tiles;         // per colour
   Tiles all;                        // every row (residual)
+  std::vector<int> long_ptr, long_rows;  // host: rows > SHORT_ROW grouped by colour
   // transfer from the previous level into this one
   int* agg = nullptr;               // AGG: fine node -> this level's node
   int *agg_ptr = nullptr, *members = nullptr;  // P^T as CSR (aggregate members ascending)
@@ -116,6 +117,12 @@ struct Hierarchy {
   hipGraphExec_t gexec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
   double setup_ms = 0;
   int64_t bytes_per_cycle = 0;
+  // single-workgroup tail: levels >= tail_lc run from an op program
+  int tail_lc = -1;               // -1: not prepared; == lv.size(): no tail
+  void* tail_levels = nullptr;    // device array of level descriptors
+  int4* tail_prog = nullptr;      // device op program of one finest cycle
+  std::vector<int2> tail_segs;    // (offset, length) per entry into the tail
+  int tail_cursor = 0;
 };
 
 // -------------------------------------------------------- instrumentation
@@ -194,6 +201,11 @@ void cycle(Hierarchy* H);
 template <class T>
 void cycle_graph(Hierarchy* H, int inst);
 void drop_graphs(Hierarchy* H);
+// Tail: prepare the descriptors and the op program (idempotent), and run the
+// next program segment (one entry into level tail_lc) on the stream.
+void tail_prepare(Hierarchy* H);
+template <class T>
+void tail_run_next(Hierarchy* H);
 
 }  // namespace lamg
 

@@ -482,6 +482,8 @@ void build_tiles(Hierarchy* H, Level& L) {
   hipStream_t s = H->s;
   std::vector<int> rph = to_host_vec(s, L.rp, (size_t)L.n + 1);
   L.tiles.assign(L.ncol, Tiles());
+  L.long_ptr.assign(1, 0);
+  L.long_rows.clear();
   std::vector<int2> all_s;
   std::vector<int> all_v, all_m;
   for (int c = 0; c < L.ncol; ++c) {
@@ -506,6 +508,9 @@ void build_tiles(Hierarchy* H, Level& L) {
     t.rows = e - L.cptr[c];
     t.nnz = rph[e] - rph[L.cptr[c]];
     upload_tiles(H, t, blocks, vl, md, rph);
+    L.long_rows.insert(L.long_rows.end(), vl.begin(), vl.end());
+    L.long_rows.insert(L.long_rows.end(), md.begin(), md.end());
+    L.long_ptr.push_back((int)L.long_rows.size());
     all_s.insert(all_s.end(), blocks.begin(), blocks.end());
     all_v.insert(all_v.end(), vl.begin(), vl.end());
     all_m.insert(all_m.end(), md.begin(), md.end());

@@ -1,0 +1,584 @@
+// Single-workgroup tail of the cycle (Section 4.2 cycles on the small coarse
+// levels).  The coarse levels are visited many times per finest cycle
+// (fractional cycle index, eq. cycle_index) but hold few nodes, so one launch
+// per colour pass would be dominated by launch latency.  Instead, every entry
+// into level tail_lc runs one 1024-thread workgroup that executes a
+// precomputed op program (the same relaxations, transfers, recombinations and
+// coarsest solves the multi-launch path performs, in the same order), with a
+// workgroup barrier between ops.  Sums keep the fixed order of the other
+// kernels: short rows left to right by one thread, long rows (> 64 entries)
+// by one wavefront in 512-entry chunks.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "lamg_device.hpp"
+#include "lamg_internal.hpp"
+
+namespace lamg {
+
+namespace {
+
+constexpr int TAIL_THREADS = 1024;
+constexpr int TAIL_WAVES = TAIL_THREADS / 64;
+
+enum TailOp {
+  OP_GS = 1,      // one multicolour sweep of level l
+  OP_RES = 2,     // residual of level l into a = 0: r, 1: R0, 2: R1
+  OP_SAVEX = 3,   // X[a] = x
+  OP_RAGG = 4,    // b_{l+1} = mu^(b) * P^T src(a)
+  OP_ZERO = 5,    // x_l = 0
+  OP_IAGG = 6,    // x_l += P x_{l+1}
+  OP_RELIM = 7,   // b_{l+1} = elimination restriction of r_l
+  OP_IELIM = 8,   // x_l += exact elimination correction from x_{l+1}
+  OP_RECOMB = 9,  // iterate recombination over a = theta sub-cycles
+  OP_COARSE = 10, // coarsest solve of level l
+  OP_MEAN = 11,   // x_l -= mean(x_l)
+  OP_RRAGG = 12,  // fused: residual into src(a), X[sub] = x when a > 0, b_{l+1} = mu^(b) P^T src, x_{l+1} = 0
+};
+
+struct TailLevel {
+  int n, nnz, ncol, nc;  // nc: nodes of level l+1 (0 for the coarsest)
+  const int *rp, *ci;
+  const double *val64, *diag64;
+  const float *val32, *diag32;
+  const int *cptr, *lptr, *lrows;
+  const int *agg, *agg_ptr, *members;                 // into level l+1 (aggregation)
+  const int *cidx, *cfine, *er_rp, *er_ci;            // into level l+1 (elimination)
+  const double* er64;
+  const float* er32;
+  double *x64, *b64, *r64, *X64[2], *R64[2];
+  float *x32, *b32, *r32, *X32[2], *R32[2];
+};
+
+struct TailParams {
+  const TailLevel* L;
+  int lc;
+  const double* Minv;
+  int nL, crelax, csweeps;
+  double mu;
+};
+
+template <class T> struct TV;
+template <> struct TV<double> {
+  __device__ static const double* val(const TailLevel& L) { return L.val64; }
+  __device__ static const double* diag(const TailLevel& L) { return L.diag64; }
+  __device__ static const double* er(const TailLevel& L) { return L.er64; }
+  __device__ static double* x(const TailLevel& L) { return L.x64; }
+  __device__ static double* b(const TailLevel& L) { return L.b64; }
+  __device__ static double* r(const TailLevel& L) { return L.r64; }
+  __device__ static double* X(const TailLevel& L, int i) { return L.X64[i]; }
+  __device__ static double* R(const TailLevel& L, int i) { return L.R64[i]; }
+};
+template <> struct TV<float> {
+  __device__ static const float* val(const TailLevel& L) { return L.val32; }
+  __device__ static const float* diag(const TailLevel& L) { return L.diag32; }
+  __device__ static const float* er(const TailLevel& L) { return L.er32; }
+  __device__ static float* x(const TailLevel& L) { return L.x32; }
+  __device__ static float* b(const TailLevel& L) { return L.b32; }
+  __device__ static float* r(const TailLevel& L) { return L.r32; }
+  __device__ static float* X(const TailLevel& L, int i) { return L.X32[i]; }
+  __device__ static float* R(const TailLevel& L, int i) { return L.R32[i]; }
+};
+
+// Sum of a row against vector v, left to right; the index and weight loads of
+// 8 entries are issued before their 8 gathers (arrays in global memory or LDS).
+template <class T>
+__device__ __attribute__((always_inline)) inline T row_seq_p(const T* val, const int* ci, int p0, int len, const T* v) {
+  T s = 0;
+  for (int t0 = 0; t0 < len; t0 += 8) {
+    int cj[8];
+    T wj[8], xj[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int t = t0 + q;
+      cj[q] = t < len ? ci[p0 + t] : 0;
+      wj[q] = t < len ? val[p0 + t] : T(0);
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) xj[q] = v[cj[q]];
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (t0 + q < len) s += wj[q] * xj[q];
+  }
+  return s;
+}
+template <class T>
+__device__ __attribute__((always_inline)) inline T row_seq(const TailLevel& L, int p0, int len, const T* v) {
+  const T* val = TV<T>::val(L);
+  T s = 0;
+  for (int t0 = 0; t0 < len; t0 += 8) {
+    int cj[8];
+    T wj[8], xj[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int t = t0 + q;
+      cj[q] = t < len ? L.ci[p0 + t] : 0;
+      wj[q] = t < len ? val[p0 + t] : T(0);
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) xj[q] = v[cj[q]];
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (t0 + q < len) s += wj[q] * xj[q];
+  }
+  return s;
+}
+template <class T>
+__device__ __attribute__((always_inline)) inline T row_short(const TailLevel& L, int u, const T* v) {
+  const int p0 = L.rp[u];
+  return row_seq<T>(L, p0, L.rp[u + 1] - p0, v);
+}
+template <class T>
+__device__ __attribute__((always_inline)) inline T row_long(const TailLevel& L, int u, const T* v, int lane) {
+  const int p0 = L.rp[u], len = L.rp[u + 1] - p0;
+  const T* val = TV<T>::val(L);
+  return dev::row_sum_wave<T>(len, lane, [&](int t) { return val[p0 + t] * v[L.ci[p0 + t]]; });
+}
+
+// One multicolour GS sweep: short rows one per thread, long rows one per
+// wavefront, a barrier after each colour class.
+template <class T>
+__device__ __attribute__((always_inline)) inline void tail_gs(const TailLevel& L) {
+  T* x = TV<T>::x(L);
+  const T* b = TV<T>::b(L);
+  const T* dg = TV<T>::diag(L);
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+  for (int c = 0; c < L.ncol; ++c) {
+    for (int u = L.cptr[c] + tid; u < L.cptr[c + 1]; u += TAIL_THREADS)
+      if (L.rp[u + 1] - L.rp[u] <= SHORT_ROW) x[u] = (b[u] + row_short<T>(L, u, x)) / dg[u];
+    for (int k = L.lptr[c] + wv; k < L.lptr[c + 1]; k += TAIL_WAVES) {
+      const int u = L.lrows[k];
+      const T s = row_long<T>(L, u, x, lane);
+      if (lane == 0) x[u] = (b[u] + s) / dg[u];
+    }
+    __syncthreads();
+  }
+}
+// The same sweep with the level staged in LDS for its whole duration: x, b,
+// diagonal, row pointers and colour bounds always; column indices and weights
+// too when they fit.  One bulk load and one write-back replace the global
+// round trips of every colour phase.  Same sums in the same order.
+constexpr int TAIL_LDS = 128 * 1024;
+template <class T>
+__device__ inline size_t tail_vec_bytes(const TailLevel& L) {
+  return (size_t)L.n * (3 * sizeof(T) + sizeof(int)) + 2 * sizeof(int) + (size_t)(2 * L.ncol + 2) * sizeof(int);
+}
+template <class T>
+__device__ inline bool tail_fits(const TailLevel& L) {
+  return tail_vec_bytes<T>(L) <= (size_t)TAIL_LDS;
+}
+template <class T>
+__device__ inline bool tail_fits_all(const TailLevel& L) {
+  return tail_vec_bytes<T>(L) + (size_t)L.nnz * (sizeof(T) + sizeof(int)) + 16 <= (size_t)TAIL_LDS;
+}
+template <class T>
+__device__ __attribute__((always_inline)) inline void tail_gs_lds(const TailLevel& L, char* lds, int sweeps) {
+  T* x = TV<T>::x(L);
+  const T* b = TV<T>::b(L);
+  const T* dg = TV<T>::diag(L);
+  const int n = L.n, nc = L.ncol;
+  T* sx = (T*)lds;
+  T* sbv = sx + n;
+  T* sd = sbv + n;
+  int* srp = (int*)(sd + n);
+  int* scp = srp + n + 1;
+  int* slp = scp + nc + 1;
+  const bool all = tail_fits_all<T>(L);
+  // 16-byte aligned start for the matrix entries
+  char* mend = (char*)(slp + nc + 1);
+  T* sval = (T*)(((size_t)mend + 15) & ~(size_t)15);
+  int* sci = (int*)(sval + (all ? L.nnz : 0));
+  const T* val = all ? (const T*)sval : TV<T>::val(L);
+  const int* ci = all ? (const int*)sci : L.ci;
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+  for (int i = tid; i < n; i += TAIL_THREADS) { sx[i] = x[i]; sbv[i] = b[i]; sd[i] = dg[i]; srp[i] = L.rp[i]; }
+  for (int i = tid; i <= nc; i += TAIL_THREADS) { scp[i] = L.cptr[i]; slp[i] = L.lptr[i]; }
+  if (tid == 0) srp[n] = L.rp[n];
+  if (all) {
+    const T* gv = TV<T>::val(L);
+    for (int i = tid; i < L.nnz; i += TAIL_THREADS) { sval[i] = gv[i]; sci[i] = L.ci[i]; }
+  }
+  __syncthreads();
+  for (int sw = 0; sw < sweeps; ++sw)
+    for (int c = 0; c < nc; ++c) {
+      const int c1 = scp[c + 1];
+      for (int u = scp[c] + tid; u < c1; u += TAIL_THREADS) {
+        const int p0 = srp[u], len = srp[u + 1] - p0;
+        if (len > SHORT_ROW) continue;
+        sx[u] = (sbv[u] + row_seq_p<T>(val, ci, p0, len, sx)) / sd[u];
+      }
+      for (int k = slp[c] + wv; k < slp[c + 1]; k += TAIL_WAVES) {
+        const int u = L.lrows[k];
+        const int p0 = srp[u], len = srp[u + 1] - p0;
+        const T s = dev::row_sum_wave<T>(len, lane, [&](int t) { return val[p0 + t] * sx[ci[p0 + t]]; });
+        if (lane == 0) sx[u] = (sbv[u] + s) / sd[u];
+      }
+      __syncthreads();
+    }
+  for (int i = tid; i < n; i += TAIL_THREADS) x[i] = sx[i];
+}
+template <class T>
+__device__ __attribute__((always_inline)) inline void tail_sweeps(const TailLevel& L, char* lds, int sweeps) {
+  if (tail_fits<T>(L)) {
+    tail_gs_lds<T>(L, lds, sweeps);
+  } else {
+    for (int sw = 0; sw < sweeps; ++sw) tail_gs<T>(L);
+  }
+}
+
+template <class T>
+__device__ __attribute__((always_inline)) inline void tail_res(const TailLevel& L, T* out) {
+  const T* x = TV<T>::x(L);
+  const T* b = TV<T>::b(L);
+  const T* dg = TV<T>::diag(L);
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+  for (int u = tid; u < L.n; u += TAIL_THREADS)
+    if (L.rp[u + 1] - L.rp[u] <= SHORT_ROW) out[u] = (b[u] + row_short<T>(L, u, x)) - dg[u] * x[u];
+  for (int k = wv; k < L.lptr[L.ncol]; k += TAIL_WAVES) {
+    const int u = L.lrows[k];
+    const T s = row_long<T>(L, u, x, lane);
+    if (lane == 0) out[u] = (b[u] + s) - dg[u] * x[u];
+  }
+}
+
+// Fixed-order sum of NV values per thread over the workgroup: a butterfly
+// inside each wavefront, then the 16 wavefront sums left to right.
+template <int NV>
+__device__ inline void block_sums(double (&v)[NV], double (*sh)[TAIL_WAVES]) {
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    const double t = dev::wave_fold(v[i]);
+    if (lane == 0) sh[i][wv] = t;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    double t = 0;
+    for (int w = 0; w < TAIL_WAVES; ++w) t += sh[i][w];
+    v[i] = t;
+  }
+  __syncthreads();
+}
+
+template <class T>
+__global__ __launch_bounds__(TAIL_THREADS) void k_tail(TailParams P, const int4* __restrict__ prog, int nops) {
+  __shared__ double sh[6][TAIL_WAVES];
+  extern __shared__ double lds_d[];  // staging: GS sweeps, coarsest right-hand side
+  char* lds = (char*)lds_d;
+  double* sb = lds_d;
+  const int tid = threadIdx.x;
+  for (int i = 0; i < nops; ++i) {
+    const int4 op = prog[i];
+    const TailLevel& L = P.L[op.y - P.lc];
+    switch (op.x) {
+      case OP_GS:
+        tail_sweeps<T>(L, lds, 1);
+        break;
+      case OP_RES:
+        tail_res<T>(L, op.z == 0 ? TV<T>::r(L) : TV<T>::R(L, op.z - 1));
+        break;
+      case OP_SAVEX: {
+        const T* x = TV<T>::x(L);
+        T* X = TV<T>::X(L, op.z);
+        for (int u = tid; u < L.n; u += TAIL_THREADS) X[u] = x[u];
+        break;
+      }
+      case OP_RAGG: {
+        const TailLevel& C = P.L[op.y + 1 - P.lc];
+        const T* src = op.z == 0 ? TV<T>::r(L) : TV<T>::R(L, op.z - 1);
+        T* bc = TV<T>::b(C);
+        const T mu = op.w ? (T)P.mu : T(1);
+        for (int U = tid; U < L.nc; U += TAIL_THREADS) {
+          T s = 0;
+          for (int j = L.agg_ptr[U]; j < L.agg_ptr[U + 1]; ++j) s += src[L.members[j]];
+          bc[U] = mu * s;
+        }
+        break;
+      }
+      case OP_RRAGG: {
+        // one thread per aggregate: residuals of its members (rows summed left
+        // to right), saved iterate, restricted sum, zeroed coarse iterate
+        const TailLevel& C = P.L[op.y + 1 - P.lc];
+        T* dst = op.z == 0 ? TV<T>::r(L) : TV<T>::R(L, op.z - 1);
+        T* Xs = op.z == 0 ? nullptr : TV<T>::X(L, op.z - 1);
+        const T* x = TV<T>::x(L);
+        const T* b = TV<T>::b(L);
+        const T* dg = TV<T>::diag(L);
+        T* bc = TV<T>::b(C);
+        T* xc = TV<T>::x(C);
+        const T mu = op.w ? (T)P.mu : T(1);
+        for (int U = tid; U < L.nc; U += TAIL_THREADS) {
+          T s = 0;
+          for (int j = L.agg_ptr[U]; j < L.agg_ptr[U + 1]; ++j) {
+            const int m = L.members[j];
+            const int p0 = L.rp[m];
+            const T xm = x[m];
+            const T rm = (b[m] + row_seq<T>(L, p0, L.rp[m + 1] - p0, x)) - dg[m] * xm;
+            dst[m] = rm;
+            if (Xs) Xs[m] = xm;
+            s += rm;
+          }
+          bc[U] = mu * s;
+          xc[U] = T(0);
+        }
+        break;
+      }
+      case OP_ZERO: {
+        T* x = TV<T>::x(L);
+        for (int u = tid; u < L.n; u += TAIL_THREADS) x[u] = T(0);
+        break;
+      }
+      case OP_IAGG: {
+        const TailLevel& C = P.L[op.y + 1 - P.lc];
+        const T* e = TV<T>::x(C);
+        T* x = TV<T>::x(L);
+        for (int u = tid; u < L.n; u += TAIL_THREADS) x[u] += e[L.agg[u]];
+        break;
+      }
+      case OP_RELIM: {
+        const TailLevel& C = P.L[op.y + 1 - P.lc];
+        const T* r = TV<T>::r(L);
+        const T* er = TV<T>::er(L);
+        T* bc = TV<T>::b(C);
+        for (int c = tid; c < L.nc; c += TAIL_THREADS) {
+          T s = 0;
+          for (int j = L.er_rp[c]; j < L.er_rp[c + 1]; ++j) s += er[j] * r[L.er_ci[j]];
+          bc[c] = r[L.cfine[c]] + s;
+        }
+        break;
+      }
+      case OP_IELIM: {
+        const TailLevel& C = P.L[op.y + 1 - P.lc];
+        const T* e = TV<T>::x(C);
+        const T* r = TV<T>::r(L);
+        const T* val = TV<T>::val(L);
+        const T* dg = TV<T>::diag(L);
+        T* x = TV<T>::x(L);
+        for (int u = tid; u < L.n; u += TAIL_THREADS) {
+          const int c = L.cidx[u];
+          if (c >= 0) { x[u] += e[c]; continue; }
+          T s = r[u];
+          for (int t = L.rp[u]; t < L.rp[u + 1]; ++t) s += val[t] * e[L.cidx[L.ci[t]]];
+          x[u] += s / dg[u];
+        }
+        break;
+      }
+      case OP_RECOMB: {
+        const int th = op.z;
+        T* r = TV<T>::r(L);
+        tail_res<T>(L, r);
+        __syncthreads();
+        const T* R0 = TV<T>::R(L, 0);
+        const T* R1 = TV<T>::R(L, 1);
+        double v[6] = {0, 0, 0, 0, 0, 0};
+        for (int u = tid; u < L.n; u += TAIL_THREADS) {
+          const double ru = (double)r[u];
+          const double d0 = (double)(R0[u] - r[u]);
+          const double d1 = th > 1 ? (double)(R1[u] - r[u]) : 0.0;
+          v[0] += d0 * d0; v[1] += d0 * d1; v[2] += d1 * d1; v[3] += d0 * ru; v[4] += d1 * ru; v[5] += ru * ru;
+        }
+        block_sums<6>(v, sh);
+        const double G00 = v[0], G01 = v[1], G11 = v[2], g0 = v[3], g1 = v[4], rr = v[5];
+        const double tiny = 1e-28 * rr;
+        double a0 = 0, a1 = 0;
+        if (th == 1) {
+          if (G00 > tiny) a0 = -g0 / G00;
+        } else {
+          const double det = G00 * G11 - G01 * G01;
+          if (G00 > tiny && G11 > tiny && det > 1e-12 * G00 * G11) {
+            a0 = (-g0 * G11 + g1 * G01) / det;
+            a1 = (-g1 * G00 + g0 * G01) / det;
+          } else if (G00 >= G11) {
+            if (G00 > tiny) a0 = -g0 / G00;
+          } else {
+            if (G11 > tiny) a1 = -g1 / G11;
+          }
+        }
+        T* x = TV<T>::x(L);
+        const T* X0 = TV<T>::X(L, 0);
+        const T* X1 = TV<T>::X(L, 1);
+        for (int u = tid; u < L.n; u += TAIL_THREADS) {
+          const double xu = (double)x[u];
+          double y = xu;
+          y += a0 * ((double)X0[u] - xu);
+          if (th > 1) y += a1 * ((double)X1[u] - xu);
+          x[u] = (T)y;
+        }
+        break;
+      }
+      case OP_COARSE: {
+        if (P.crelax) {
+          tail_sweeps<T>(L, lds, P.csweeps);
+          break;
+        }
+        // x = M^-1 b: one wavefront per row, coalesced row loads
+        const T* b = TV<T>::b(L);
+        T* x = TV<T>::x(L);
+        for (int j = tid; j < P.nL; j += TAIL_THREADS) sb[j] = (double)b[j];
+        __syncthreads();
+        const int wv = tid >> 6, lane = tid & 63;
+        for (int r = wv; r < P.nL; r += TAIL_WAVES) {
+          const double* row = P.Minv + (size_t)r * P.nL;
+          double s = 0;
+          for (int j = lane; j < P.nL; j += 64) s += row[j] * sb[j];
+          s = dev::wave_fold(s);
+          if (lane == 0) x[r] = (T)s;
+        }
+        break;
+      }
+      case OP_MEAN: {
+        T* x = TV<T>::x(L);
+        double v[1] = {0};
+        for (int u = tid; u < L.n; u += TAIL_THREADS) v[0] += (double)x[u];
+        block_sums<1>(v, sh);
+        const double mean = v[0] / (double)L.n;
+        for (int u = tid; u < L.n; u += TAIL_THREADS) x[u] = (T)((double)x[u] - mean);
+        break;
+      }
+      default:
+        break;
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------ program generation
+// Mirrors the host cycle (visit / body) from level lc down, emitting ops.
+struct Gen {
+  const Hierarchy* H;
+  std::vector<int4> prog;
+  std::vector<int64_t> count;
+  void op(int code, int l, int a = 0, int b = 0) { prog.push_back(make_int4(code, l, a, b)); }
+  void visit(int l, int th) {
+    const int Lc = (int)H->lv.size() - 1;
+    if (l == Lc) { op(OP_COARSE, l); return; }
+    for (int i = 0; i < th; ++i) body(l, i);
+    if (H->o.ec == LAMG_EC_RECOMBINE && H->lv[l + 1].type == LT_AGG) op(OP_RECOMB, l, th);
+  }
+  void body(int l, int sub) {
+    const int Lc = (int)H->lv.size() - 1;
+    if (l == Lc) { op(OP_COARSE, l); return; }
+    if (H->lv[l + 1].type == LT_ELIM) {
+      op(OP_RES, l, 0);
+      op(OP_RELIM, l);
+      op(OP_ZERO, l + 1);
+      visit(l + 1, 1);
+      op(OP_IELIM, l);
+      return;
+    }
+    const bool rec = H->o.ec == LAMG_EC_RECOMBINE;
+    for (int i = 0; i < H->o.nu_pre; ++i) op(OP_GS, l);
+    const int src = rec ? 1 + sub : 0;
+    op(OP_RRAGG, l, src, rec ? 0 : 1);
+    const int64_t c = count[l]++;
+    const double gl = H->lv[l].gamma_next;
+    const int th = (int)(std::ceil((double)(c + 1) * gl) - std::ceil((double)c * gl));
+    visit(l + 1, th);
+    op(OP_IAGG, l);
+    for (int i = 0; i < H->o.nu_post; ++i) op(OP_GS, l);
+  }
+};
+
+// Replays the host part of the schedule (levels < lc) to find every entry
+// into level lc and its theta, in launch order.
+void host_walk(const Hierarchy* H, int l, int th, std::vector<int64_t>& count, int lc, Gen& g,
+               std::vector<int2>& segs) {
+  const int Lc = (int)H->lv.size() - 1;
+  if (l == lc) {
+    const int off = (int)g.prog.size();
+    g.visit(l, th);
+    if (lc == 0) g.op(OP_MEAN, 0);
+    segs.push_back(make_int2(off, (int)g.prog.size() - off));
+    return;
+  }
+  if (l == Lc) return;
+  for (int i = 0; i < th; ++i) {
+    if (H->lv[l + 1].type == LT_ELIM) { host_walk(H, l + 1, 1, count, lc, g, segs); continue; }
+    const int64_t c = count[l]++;
+    const double gl = H->lv[l].gamma_next;
+    host_walk(H, l + 1, (int)(std::ceil((double)(c + 1) * gl) - std::ceil((double)c * gl)), count, lc, g, segs);
+  }
+}
+
+}  // namespace
+
+void tail_prepare(Hierarchy* H) {
+  if (H->tail_lc >= 0) return;
+  const int nl = (int)H->lv.size();
+  const int tmax = H->o.tail_max_n;
+  int lc = nl;
+  if (tmax > 0)
+    for (int l = nl - 1; l >= 0 && H->lv[l].n <= tmax; --l) lc = l;
+  if (lc >= nl) { H->tail_lc = lc; return; }
+  // descriptors of levels lc .. nl-1
+  std::vector<TailLevel> d(nl - lc);
+  for (int l = lc; l < nl; ++l) {
+    const Level& L = H->lv[l];
+    TailLevel& t = d[l - lc];
+    std::memset(&t, 0, sizeof(t));
+    t.n = L.n; t.nnz = L.nnz; t.ncol = L.ncol; t.nc = l + 1 < nl ? H->lv[l + 1].n : 0;
+    t.rp = L.rp; t.ci = L.ci; t.val64 = L.val; t.diag64 = L.diag; t.val32 = L.val32; t.diag32 = L.diag32;
+    int* cp = dnew<int>(H, L.cptr.size());
+    int* lp = dnew<int>(H, L.long_ptr.size());
+    int* lr = dnew<int>(H, std::max<size_t>(L.long_rows.size(), 1));
+    LAMG_HIP(hipMemcpy(cp, L.cptr.data(), L.cptr.size() * sizeof(int), hipMemcpyHostToDevice));
+    LAMG_HIP(hipMemcpy(lp, L.long_ptr.data(), L.long_ptr.size() * sizeof(int), hipMemcpyHostToDevice));
+    if (!L.long_rows.empty())
+      LAMG_HIP(hipMemcpy(lr, L.long_rows.data(), L.long_rows.size() * sizeof(int), hipMemcpyHostToDevice));
+    t.cptr = cp; t.lptr = lp; t.lrows = lr;
+    if (l + 1 < nl) {
+      const Level& C = H->lv[l + 1];
+      t.agg = C.agg; t.agg_ptr = C.agg_ptr; t.members = C.members;
+      t.cidx = C.cidx; t.cfine = C.cfine; t.er_rp = C.er_rp; t.er_ci = C.er_ci; t.er64 = C.er_val; t.er32 = C.er_val32;
+    }
+    t.x64 = L.v64.x; t.b64 = L.v64.b; t.r64 = L.v64.r;
+    t.x32 = L.v32.x; t.b32 = L.v32.b; t.r32 = L.v32.r;
+    for (int i = 0; i < 2; ++i) {
+      t.X64[i] = L.v64.X[i]; t.R64[i] = L.v64.R[i]; t.X32[i] = L.v32.X[i]; t.R32[i] = L.v32.R[i];
+    }
+  }
+  TailLevel* dd = dnew<TailLevel>(H, d.size());
+  LAMG_HIP(hipMemcpy(dd, d.data(), d.size() * sizeof(TailLevel), hipMemcpyHostToDevice));
+  H->tail_levels = dd;
+  // the op program of one finest cycle
+  Gen g;
+  g.H = H;
+  g.count.assign(nl, 0);
+  std::vector<int64_t> hc(nl, 0);
+  H->tail_segs.clear();
+  H->tail_lc = lc;  // host_walk reads the hierarchy only
+  host_walk(H, 0, 1, hc, lc, g, H->tail_segs);
+  H->tail_lc = -1;
+  H->tail_prog = dnew<int4>(H, std::max<size_t>(g.prog.size(), 1));
+  LAMG_HIP(hipMemcpy(H->tail_prog, g.prog.data(), g.prog.size() * sizeof(int4), hipMemcpyHostToDevice));
+  H->tail_lc = lc;  // ready
+}
+
+template <class T>
+void tail_run_next(Hierarchy* H) {
+  const int2 seg = H->tail_segs[H->tail_cursor++];
+  TailParams P;
+  P.L = (const TailLevel*)H->tail_levels;
+  P.lc = H->tail_lc;
+  P.Minv = H->cinv;
+  P.nL = H->nL;
+  P.crelax = H->coarsest_relax ? 1 : 0;
+  P.csweeps = H->o.coarsest_sweeps;
+  P.mu = H->o.mu;
+  const size_t lds = std::max<size_t>(TAIL_LDS, H->coarsest_relax ? 0 : (size_t)H->nL * sizeof(double));
+  static bool attr_set = false;
+  if (!attr_set) {
+    LAMG_HIP(hipFuncSetAttribute((const void*)k_tail<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    LAMG_HIP(hipFuncSetAttribute((const void*)k_tail<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(k_tail<T>, dim3(1), dim3(TAIL_THREADS), lds, H->s, P, (const int4*)(H->tail_prog + seg.x), seg.y);
+  LAMG_HIP(hipGetLastError());
+}
+template void tail_run_next<double>(Hierarchy*);
+template void tail_run_next<float>(Hierarchy*);
+
+}  // namespace lamg

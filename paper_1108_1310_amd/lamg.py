@@ -28,6 +28,7 @@ class Options(C.Structure):
                 ("elim_max_degree", C.c_int), ("coarsest_max_n", C.c_int),
                 ("weak_edge_ratio", C.c_double), ("elim_stop_frac", C.c_double), ("stage1_quantile", C.c_double),
                 ("relax_fast_ratio", C.c_double), ("coarsest_sweeps", C.c_int), ("dense_max", C.c_int),
+                ("tail_max_n", C.c_int),
                 ("ec", C.c_int), ("precision", C.c_int), ("tol", C.c_double), ("max_cycles", C.c_int),
                 ("warm_start", C.c_int), ("seed", C.c_uint64), ("stream", C.c_void_p)]
 
@@ -65,6 +66,7 @@ def lib():
             "lamg_solve_batch": (C.c_int, [i32, C.POINTER(vp), C.POINTER(i32), C.POINTER(vp), C.POINTER(vp),
                                            C.POINTER(Info)]),
             "lamg_set_solve_options": (C.c_int, [vp, C.POINTER(Options)]),
+            "lamg_edge_gradient": (C.c_int, [i64, vp, vp, vp, vp, vp, vp]),
             "lamg_free": (None, [vp]),
             "lamg_status_str": (C.c_char_p, [C.c_int]),
             "lamg_last_error": (C.c_char_p, []),
@@ -234,6 +236,49 @@ class Hierarchy:
         x = torch.zeros_like(b)
         _check(lib().lamg_t_coarsest_solve(self.h, _ptr(b), _ptr(x)), "lamg_t_coarsest_solve")
         return x
+
+
+def edge_gradient(eu, ev, x, lam):
+    """grad_w[e] = -(lam_u - lam_v)(x_u - x_v) for every edge (HIP kernel)."""
+    eu, ev = _dev(eu, torch.int32), _dev(ev, torch.int32)
+    g = torch.empty(eu.numel(), dtype=torch.float64, device="cuda")
+    _check(lib().lamg_edge_gradient(eu.numel(), _ptr(eu), _ptr(ev), _ptr(x.contiguous()), _ptr(lam.contiguous()),
+                                    _ptr(g), _stream()), "lamg_edge_gradient")
+    return g
+
+
+class LaplacianSolve(torch.autograd.Function):
+    """x = A(w)^+ (b - mean b) for the Laplacian of the graph (eu, ev, w).
+
+    Backward (the adjoint reuses the hierarchy because A is symmetric):
+    lam = A^+ (g - mean g); dL/db = lam; dL/dw_e = -(lam_u - lam_v)(x_u - x_v).
+    The hierarchy is built in forward and kept on the context.
+    """
+
+    @staticmethod
+    def forward(ctx, b, w, eu, ev, n, opts=None):
+        H = Hierarchy(int(n), eu, ev, w.detach(), **(opts or {}))
+        x, info = H.solve(b.detach())
+        if info["status"] != OK:
+            raise LamgError(info["status"], "LaplacianSolve.forward")
+        ctx.H = H
+        ctx.save_for_backward(x, eu, ev)
+        return x
+
+    @staticmethod
+    def backward(ctx, g):
+        x, eu, ev = ctx.saved_tensors
+        lam, info = ctx.H.solve(g.detach().to(torch.float64))
+        if info["status"] != OK:
+            raise LamgError(info["status"], "LaplacianSolve.backward")
+        gw = edge_gradient(eu, ev, x, lam) if ctx.needs_input_grad[1] else None
+        gb = lam if ctx.needs_input_grad[0] else None
+        return gb, gw, None, None, None, None
+
+
+def laplacian_solve(b, w, eu, ev, n, **opts):
+    """Differentiable solve (see LaplacianSolve)."""
+    return LaplacianSolve.apply(b, w, eu, ev, n, opts or None)
 
 
 def solve_batch(hs: list[Hierarchy], Bs: list, Xs: list | None = None):

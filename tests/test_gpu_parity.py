@@ -218,3 +218,26 @@ def test_multi_rhs_equals_single(ora, lg):
     for j in range(4):
         xj, ij = Hg.solve(torch.tensor(B[:, j].copy(), device="cuda"))
         assert np.linalg.norm(X[:, j] - xj.cpu().numpy()) <= 1e-12 * np.linalg.norm(X[:, j])
+
+
+@pytest.mark.parametrize("name", ["grid64", "rgg16k", "grid3d16"])
+def test_tail_matches_multilaunch(ora, lg, name):
+    """The single-workgroup tail program gives the cycle of the per-kernel
+    launches (same operations; only a few row sums are ordered differently)."""
+    _print_case(f"tail {name}")
+    n, eu, ev, w = graphs()[name]
+    Ht = lg.Hierarchy(n, eu, ev, w)                 # default: coarse levels in the tail
+    Hm = lg.Hierarchy(n, eu, ev, w, tail_max_n=0)   # every level launches its kernels
+    rng = np.random.default_rng(9)
+    b = rng.standard_normal(n)
+    b -= b.mean()
+    xt = Ht.cycle(b, np.zeros(n)).cpu().numpy()
+    xm = Hm.cycle(b, np.zeros(n)).cpu().numpy()
+    # recombination Gram sums are reduced in another tree order
+    assert np.linalg.norm(xt - xm) <= 1e-10 * np.linalg.norm(xm)
+    for prec in (0, 1):
+        xt, it = Ht.solve(torch.tensor(b, device="cuda"), precision=prec)
+        xm, im = Hm.solve(torch.tensor(b, device="cuda"), precision=prec)
+        assert it["status"] == 0 and im["status"] == 0
+        assert abs(it["cycles"] - im["cycles"]) <= 1
+        assert torch.linalg.norm(xt - xm) <= 1e-7 * torch.linalg.norm(xm)
