@@ -32,7 +32,8 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=1)
-    p.add_argument("--workload", default="chung_lu_2p20", choices=["chung_lu_2p20", "grid2d_64", "rgg_2p20"])
+    p.add_argument("--workload", default="chung_lu_2p20",
+                   choices=["chung_lu_2p20", "grid2d_64", "rgg_2p20", "grid3d_128_k32"])
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU reference baseline")
     p.add_argument("--no-fp32", action="store_true")
     return p.parse_args()
@@ -72,6 +73,97 @@ def timed_solves(H, b, precision, steps, warmup, lamg, instrument=False):
     return dict(seconds=dt, cycles=cycles, bytes=byts, rel_residual=worst, prof=prof, x=x)
 
 
+def timed_multi(H, B, precision, steps, warmup, lamg, instrument=False):
+    """Time `steps` multi-vector solves of all columns of B (one hierarchy)."""
+    import torch
+    H.set_solve_options(precision=precision)
+    for _ in range(warmup):
+        H.solve_multi(B)
+    torch.cuda.synchronize()
+    kid = 4 if precision == lamg.FP64 else 6
+    lamg.prof_enable(instrument)
+    cycles, col_cycles, byts, worst = 0, 0, 0, 0.0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        X, info, cols, rc = H.solve_multi(B)
+        if rc != 0:
+            raise RuntimeError(f"multi-vector solve status {rc}")
+        cycles += info["cycles"]
+        col_cycles += int(cols["cycles"].sum())
+        byts += info["bytes_moved"]
+        worst = max(worst, info["rel_residual"])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = lamg.prof_read(kid)
+    lamg.prof_enable(False)
+    return dict(seconds=dt, cycles=cycles, col_cycles=col_cycles, bytes=byts, rel_residual=worst, prof=prof, x=X)
+
+
+def main_multi(a, g, B):
+    """Multi-vector workload: k right-hand sides as one n x k batch on one
+    hierarchy.  FP32 cycles with FP64 refinement are the headline for this
+    configuration; plain FP64 multi-vector solves are timed beside them."""
+    import torch
+    from paper_1108_1310_amd import lamg
+    k = B.shape[1]
+    Bd = torch.tensor(B, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    H = lamg.Hierarchy(g.n, g.eu, g.ev, g.w)
+    torch.cuda.synchronize()
+    setup_ms = (time.perf_counter() - t0) * 1e3
+    print(f"[bench] setup {setup_ms:.1f} ms, {H.num_levels} levels", file=sys.stderr, flush=True)
+    r32 = timed_multi(H, Bd, lamg.FP32_REFINE, a.steps, a.warmup, lamg)
+    print(f"[bench] mv fp32+refine {r32['seconds']:.3f}s cycles={r32['cycles']}", file=sys.stderr, flush=True)
+    i32 = timed_multi(H, Bd, lamg.FP32_REFINE, a.steps, 0, lamg, instrument=True)
+    print(f"[bench] mv fp32+refine instrumented {i32['seconds']:.3f}s", file=sys.stderr, flush=True)
+    r64 = timed_multi(H, Bd, lamg.FP64, a.steps, a.warmup, lamg)
+    print(f"[bench] mv fp64 {r64['seconds']:.3f}s cycles={r64['cycles']}", file=sys.stderr, flush=True)
+    x64 = r64["x"]
+    err = float(torch.linalg.norm(r32["x"] - x64) / torch.linalg.norm(x64))
+    p = i32["prof"]
+    achieved = p["bytes"] / (p["ms"] * 1e6) if p["ms"] > 0 else 0.0
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "kernel": "k_relax_mv<float,0,4> (multi-vector multicolour GS, FP32)",
+                "avg_launch_us": 1e3 * p["ms"] / max(1, p["launches"]), "launches": p["launches"],
+                "bytes_per_launch": p["bytes"] / max(1, p["launches"]),
+                "kernel_share_of_step": p["ms"] / (i32["seconds"] * 1e3),
+                "instrumented_ms_per_step": i32["seconds"] * 1e3 / a.steps}
+    cpu = None
+    if not a.no_cpu:
+        print("[bench] cpu baseline", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(a.workload)
+    value = g.m * k * r32["cycles"] / r32["seconds"]
+    rec = {
+        "metric": "edges*cycles/s to 1e-8 rel. residual (multi-vector: edges x columns x cycles; FP32+refine, FP64 beside)",
+        "value": value,
+        "unit": "edges*cycles/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": r32["seconds"] * 1e3 / a.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": a.workload, "n": g.n, "m": g.m, "k": k, "precision": "fp32+fp64-refine",
+                   "tol": 1e-8, "levels": H.num_levels, "setup_ms": setup_ms},
+        "gbps": r32["bytes"] / r32["seconds"] / 1e9,
+        "cycles_per_solve": r32["cycles"] / a.steps,
+        "column_cycles_per_solve": r32["col_cycles"] / a.steps,
+        "rel_residual": r32["rel_residual"],
+        "err_vs_fp64": err,
+        "fp64": {"value": g.m * k * r64["cycles"] / r64["seconds"], "ms_per_step": r64["seconds"] * 1e3 / a.steps,
+                 "cycles_per_solve": r64["cycles"] / a.steps, "gbps": r64["bytes"] / r64["seconds"] / 1e9,
+                 "rel_residual": r64["rel_residual"]},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(rec), flush=True)
+
+
 def cpu_baseline(name):
     """The CPU reference (serial C++) on a bounded sample of the same workload recipe."""
     from oracle import oracle as O
@@ -84,6 +176,19 @@ def cpu_baseline(name):
         g = W.rgg(1 << 17)
         b = W.rhs_normal(g.n, 1, W.SEEDS["rgg"])
         sample = "RGG recipe at 2^17 points, FP64 solve to 1e-8, 1 thread"
+    elif name == "grid3d_128_k32":
+        g = W.grid3d_aniso(64)
+        B = W.rhs_normal(g.n, 2, W.SEEDS["grid3d_aniso"])
+        sample = "anisotropic 3D grid recipe at 64^3, 2 right-hand sides solved one after the other, FP64 to 1e-8, 1 thread"
+        H = O.Hierarchy(g.n, g.eu, g.ev, g.w)
+        t0 = time.perf_counter()
+        cyc = 0
+        for j in range(B.shape[1]):
+            x, info, _ = H.solve(B[:, j])
+            cyc += info["cycles"]
+        dt = time.perf_counter() - t0
+        return {"value": g.m * cyc / dt, "unit": "edges*cycles/s", "cores": 1, "kind": "oracle", "sample": sample,
+                "cycles": cyc, "solve_s": dt, "edges": g.m}
     else:
         g, b = W.config(name)
         sample = "full workload, FP64 solve to 1e-8, 1 thread"
@@ -106,6 +211,10 @@ def main():
     torch.cuda.set_device(0)
     print(f"[bench] generating {a.workload}", file=sys.stderr, flush=True)
     g, b = workload(a.workload)
+    if b.ndim == 2 and b.shape[1] > 1:
+        print(f"[bench] n={g.n} m={g.m} k={b.shape[1]}", file=sys.stderr, flush=True)
+        return main_multi(a, g, b)
+    b = b.reshape(-1)
     bd = torch.tensor(b, device="cuda")
     print(f"[bench] setup n={g.n} m={g.m}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()

@@ -107,12 +107,22 @@ lamg_status lamg_setup(int64_t n, int64_t m, const int32_t* eu, const int32_t* e
  * LAMG_E_NOT_CONVERGED still writes the last iterate and fills info. */
 lamg_status lamg_solve(lamg_handle h, const double* b, double* x, lamg_info* info);
 
-/* Batched solves.  For each i < count: handle hs[i] solves nrhs[i] right-hand
+/* Batched solves (re-solving for many b is cheap once the setup is done,
+ * Section 1).  For each i < count: handle hs[i] solves nrhs[i] right-hand
  * sides stored DEVICE B[i] (n_i x nrhs[i], row-major, RHS index fastest) into
- * DEVICE X[i] of the same shape.  count = 1 with nrhs = k is the multi-vector
- * cycle on one hierarchy; count > 1 solves many graphs.  infos: HOST[count],
- * may be NULL (multi-RHS: the worst column is reported).  All handles must live
- * on the current device. */
+ * DEVICE X[i] of the same shape.
+ *   nrhs[i] == 1: the single-vector solve of lamg_solve.
+ *   nrhs[i] == k > 1: the multi-vector cycle.  Every level works on n_l x k
+ *     blocks; each column has its own recombination coefficients, mean and
+ *     convergence test, and stops updating once it meets tol (its mask is
+ *     cleared).  The outer loop is R = B - A X in FP64, one cycle from zero on
+ *     R - mean(R) (FP64, or FP32 under LAMG_FP32_REFINE), X += correction.  The
+ *     handle keeps an n_l x k workspace (reallocated when k changes; requires
+ *     n * k < 2^31).
+ * infos: HOST[count], may be NULL; for k > 1 it reports the worst column
+ * (largest residual, cycles = cycles of the batch).  Statuses as lamg_solve;
+ * the first failing entry's status is returned.  All handles must live on the
+ * current device. */
 lamg_status lamg_solve_batch(int32_t count, const lamg_handle* hs, const int32_t* nrhs,
                              const double* const* B, double* const* X, lamg_info* infos);
 

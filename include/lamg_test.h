@@ -55,6 +55,19 @@ lamg_status lamg_t_agg_export(lamg_handle h, int l, double* tv, double* aff, uin
  * DEVICE b_perm[n] (zero-sum) and x_perm[n] (updated in place). */
 lamg_status lamg_t_cycle(lamg_handle h, const double* b_perm, double* x_perm);
 
+/* One FP64 multi-vector cycle (Section 4.2, every column with its own
+ * recombination coefficients and mean) on the finest level in colour-major
+ * order: DEVICE b_perm[n x k] and x_perm[n x k] row-major (right-hand side
+ * index fastest; x updated in place).  Allocates the k-column workspace on
+ * first use. */
+lamg_status lamg_t_mv_cycle(lamg_handle h, int32_t k, const double* b_perm, double* x_perm);
+
+/* Per-column results of the last multi-vector solve on h with k columns
+ * (HOST outputs [k]): cycles the column iterated, final relative residual,
+ * removed mean of its right-hand side.  LAMG_E_INVALID_ARG if the last
+ * multi-vector solve had another k. */
+lamg_status lamg_t_mv_columns(lamg_handle h, int32_t k, int32_t* cycles, double* rel, double* removed_mean);
+
 /* Coarsest-level solve x = (A_L + (mean diag / n_L) 1 1^T)^-1 b, DEVICE [n_L]
  * (dense coarsest levels only). */
 lamg_status lamg_t_coarsest_solve(lamg_handle h, const double* b, double* x);
@@ -79,7 +92,8 @@ lamg_status lamg_t_colour(int32_t n, const int32_t* rp, const int32_t* ci, uint6
 /* Instrumentation of the relaxation kernel (Section 3.1.1, eq. gs) and of the
  * residual kernel.  lamg_t_prof_enable(1) clears the counters and brackets
  * every later launch with HIP events on the launch's stream; kernel ids:
- * 0 GS FP64, 1 residual FP64, 2 GS FP32, 3 residual FP32.  lamg_t_prof_read
+ * 0 GS FP64, 1 residual FP64, 2 GS FP32, 3 residual FP32, and 4..7 the same
+ * four for the multi-vector kernels.  lamg_t_prof_read
  * waits for the recorded events and returns the summed kernel time (ms), the
  * number of launches and their algorithmic bytes (HOST outputs). */
 void lamg_t_prof_enable(int on);

@@ -180,9 +180,10 @@ void set_last_error(const char* where, hipError_t e) {
   std::snprintf(g_last_error, sizeof(g_last_error), "%s: %s (%d)", where, hipGetErrorString(e), (int)e);
 }
 
-// Algorithmic bytes of one cycle (matrix and vector streams per pass).
-int64_t cycle_bytes(const Hierarchy* H, int prec) {
-  const int sv = prec == LAMG_FP64 ? 8 : 4, sx = sv;
+// Algorithmic bytes of one cycle on k right-hand sides: the matrix streams of
+// every pass once, its vector streams k times.
+int64_t cycle_bytes_k(const Hierarchy* H, int prec, int k) {
+  const int64_t sv = prec == LAMG_FP64 ? 8 : 4, sx = sv * k;
   const size_t nl = H->lv.size();
   std::vector<int64_t> bodies(nl, 0), ctr(nl, 0), visits(nl, 0);
   std::vector<int> ths;
@@ -237,6 +238,7 @@ int64_t cycle_bytes(const Hierarchy* H, int prec) {
   tot += 2 * (int64_t)H->lv[0].n * sx;  // mean removal
   return tot;
 }
+int64_t cycle_bytes(const Hierarchy* H, int prec) { return cycle_bytes_k(H, prec, 1); }
 
 }  // namespace lamg
 
@@ -360,6 +362,7 @@ lamg_status lamg_set_solve_options(lamg_handle h, const lamg_options* o) {
   // the captured cycles and the tail program depend on these options
   if (o->ec != H->o.ec || o->mu != H->o.mu || o->nu_pre != H->o.nu_pre || o->nu_post != H->o.nu_post) {
     drop_graphs(H);
+    mv_drop_graphs(H);
     H->tail_lc = -1;
   }
   if (o->nu_pre < 0 || o->nu_post < 0) return LAMG_E_INVALID_ARG;
@@ -450,17 +453,6 @@ lamg_status lamg_solve(lamg_handle h, const double* b, double* x, lamg_info* inf
   }
 }
 
-namespace {
-__global__ void k_col_get(int n, int k, int j, const double* __restrict__ B, double* __restrict__ b) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) b[i] = B[(size_t)i * k + j];
-}
-__global__ void k_col_put(int n, int k, int j, const double* __restrict__ x, double* __restrict__ X) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) X[(size_t)i * k + j] = x[i];
-}
-}  // namespace
-
 lamg_status lamg_solve_batch(int32_t count, const lamg_handle* hs, const int32_t* nrhs, const double* const* B,
                              double* const* X, lamg_info* infos) {
   if (count < 0 || (count > 0 && (!hs || !nrhs || !B || !X))) return LAMG_E_INVALID_ARG;
@@ -471,31 +463,10 @@ lamg_status lamg_solve_batch(int32_t count, const lamg_handle* hs, const int32_t
   try {
     for (int i = 0; i < count; ++i) {
       Hierarchy* H = &hs[i]->H;
-      const int n = H->lv[0].n, k = nrhs[i];
       lamg_info acc{};
-      if (k == 1) {
-        lamg_status st = solve_one(H, B[i], X[i], &acc);
-        if (st != LAMG_OK && worst == LAMG_OK) worst = st;
-      } else {
-        double* b1 = H->colb;
-        double* x1 = H->colx;
-        for (int j = 0; j < k; ++j) {
-          hipLaunchKernelGGL(k_col_get, grid1(n), dim3(256), 0, H->s, n, k, j, B[i], b1);
-          if (H->o.warm_start) hipLaunchKernelGGL(k_col_get, grid1(n), dim3(256), 0, H->s, n, k, j, (const double*)X[i], x1);
-          lamg_info ci{};
-          lamg_status st = solve_one(H, b1, x1, &ci);
-          if (st != LAMG_OK && worst == LAMG_OK) worst = st;
-          hipLaunchKernelGGL(k_col_put, grid1(n), dim3(256), 0, H->s, n, k, j, (const double*)x1, X[i]);
-          acc.cycles = std::max(acc.cycles, ci.cycles);
-          acc.rel_residual = std::max(acc.rel_residual, ci.rel_residual);
-          acc.acf = std::max(acc.acf, ci.acf);
-          acc.solve_ms += ci.solve_ms;
-          acc.bytes_moved += ci.bytes_moved;
-          acc.levels = ci.levels;
-          acc.setup_ms = ci.setup_ms;
-        }
-        LAMG_HIP(hipStreamSynchronize(H->s));
-      }
+      const lamg_status st = nrhs[i] == 1 ? solve_one(H, B[i], X[i], &acc) : solve_multi(H, nrhs[i], B[i], X[i], &acc);
+      if (st != LAMG_OK && worst == LAMG_OK) worst = st;
+      if (st == LAMG_E_INVALID_ARG) return st;
       if (infos) infos[i] = acc;
     }
   } catch (const DevError& e) {
@@ -536,6 +507,7 @@ void lamg_free(lamg_handle h) {
   if (H->s) (void)hipStreamSynchronize(H->s);
   else (void)hipDeviceSynchronize();
   drop_graphs(H);
+  mv_release(H);
   if (H->cs) (void)hipStreamDestroy(H->cs);
   for (void* p : H->owned) (void)hipFree(p);
   if (H->hred) (void)hipHostFree(H->hred);

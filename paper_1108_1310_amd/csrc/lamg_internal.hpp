@@ -96,6 +96,44 @@ struct Level {
   Vecs<float> v32;
 };
 
+// Device descriptor of one level for the single-workgroup tail program.
+struct TailLevel {
+  int n, nnz, ncol, nc;  // nc: nodes of level l+1 (0 for the coarsest)
+  const int *rp, *ci;
+  const double *val64, *diag64;
+  const float *val32, *diag32;
+  const int *cptr, *lptr, *lrows;
+  const int *agg, *agg_ptr, *members;                 // into level l+1 (aggregation)
+  const int *cidx, *cfine, *er_rp, *er_ci;            // into level l+1 (elimination)
+  const double* er64;
+  const float* er32;
+  double *x64, *b64, *r64, *X64[2], *R64[2];
+  float *x32, *b32, *r32, *X32[2], *R32[2];
+};
+
+// Multi-vector workspace: every level's work vectors as n_l x k row-major
+// blocks (right-hand side index fastest), the FP64 outer vectors of level 0,
+// per-column reduction scratch and convergence mask, and the captured
+// multi-vector cycles.  Reallocated when k changes.
+struct MVWork {
+  int k = 0;
+  std::vector<Vecs<double>> v64;
+  std::vector<Vecs<float>> v32;
+  double *B = nullptr, *X = nullptr, *R = nullptr;  // level 0, colour order
+  int rows = 0;                // rows per pass of the column reductions
+  double* part = nullptr;      // column reduction partials [6][k * rows]
+  double* res = nullptr;       // per-column results [8][k]
+  double* hres = nullptr;      // pinned host mirror of res
+  int* mask = nullptr;         // per-column: 1 while the column still iterates
+  int* hmask = nullptr;        // pinned host mirror
+  TailLevel* tail = nullptr;   // tail descriptors pointing at this workspace
+  const void* tail_src = nullptr;  // the single-vector descriptors they were built from
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  std::vector<void*> owned;    // device allocations of this workspace
+  std::vector<int> cycles;     // last solve, per column
+  std::vector<double> rel, removed;
+};
+
 struct Hierarchy {
   lamg_options o;
   hipStream_t s = nullptr;
@@ -123,12 +161,15 @@ struct Hierarchy {
   int4* tail_prog = nullptr;      // device op program of one finest cycle
   std::vector<int2> tail_segs;    // (offset, length) per entry into the tail
   int tail_cursor = 0;
+  std::vector<TailLevel> tail_host;  // host copy of the descriptors
+  MVWork mv;
 };
 
 // -------------------------------------------------------- instrumentation
 // When enabled, every relaxation / residual launch is bracketed by HIP events
 // on its stream and its algorithmic bytes are accumulated per kernel:
-// 0 GS FP64, 1 residual FP64, 2 GS FP32, 3 residual FP32.
+// 0 GS FP64, 1 residual FP64, 2 GS FP32, 3 residual FP32, and 4..7 the same
+// four for the multi-vector kernels.
 void prof_mark(hipStream_t s, int kernel, int64_t bytes, bool begin);
 bool prof_on();
 // Instrumented cycles run eagerly (not from captured graphs) so that every
@@ -195,6 +236,7 @@ void finish_levels(Hierarchy* H);
 
 // solve
 int64_t cycle_bytes(const Hierarchy* H, int prec);
+int64_t cycle_bytes_k(const Hierarchy* H, int prec, int k);
 template <class T>
 void cycle(Hierarchy* H);
 // Replay one captured cycle (capturing it on first use); `inst` alternates.
@@ -206,6 +248,15 @@ void drop_graphs(Hierarchy* H);
 void tail_prepare(Hierarchy* H);
 template <class T>
 void tail_run_next(Hierarchy* H);
+// Multi-vector tail: one workgroup per column of the workspace blocks.
+void tail_prepare_mv(Hierarchy* H);
+template <class T>
+void tail_run_next_mv(Hierarchy* H);
+
+// multi-vector cycle and solve
+void mv_release(Hierarchy* H);
+void mv_drop_graphs(Hierarchy* H);
+lamg_status solve_multi(Hierarchy* H, int k, const double* B, double* X, lamg_info* info);
 
 }  // namespace lamg
 

@@ -167,8 +167,8 @@ struct Prof {
   bool on = false;
   std::vector<Pair> pend;  // launches whose events are not read yet
   std::vector<hipEvent_t> pool;
-  double ms[4] = {0, 0, 0, 0};
-  int64_t bytes[4] = {0, 0, 0, 0}, launches[4] = {0, 0, 0, 0};
+  double ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int64_t bytes[8] = {0, 0, 0, 0, 0, 0, 0, 0}, launches[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 };
 Prof g_prof;
 hipEvent_t new_event() {
@@ -636,11 +636,11 @@ void lamg_t_prof_enable(int on) {
   } catch (const lamg::DevError&) {
   }
   P.on = on != 0;
-  for (int k = 0; k < 4; ++k) { P.ms[k] = 0; P.bytes[k] = 0; P.launches[k] = 0; }
+  for (int k = 0; k < 8; ++k) { P.ms[k] = 0; P.bytes[k] = 0; P.launches[k] = 0; }
 }
 lamg_status lamg_t_prof_read(int kernel, double* ms, int64_t* launches, int64_t* bytes) {
   lamg::Prof& P = lamg::g_prof;
-  if (kernel < 0 || kernel > 3 || !ms || !launches || !bytes) return LAMG_E_INVALID_ARG;
+  if (kernel < 0 || kernel > 7 || !ms || !launches || !bytes) return LAMG_E_INVALID_ARG;
   try {
     lamg::prof_flush();
   } catch (const lamg::DevError&) {

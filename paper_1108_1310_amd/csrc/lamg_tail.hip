@@ -38,26 +38,13 @@ enum TailOp {
   OP_RRAGG = 12,  // fused: residual into src(a), X[sub] = x when a > 0, b_{l+1} = mu^(b) P^T src, x_{l+1} = 0
 };
 
-struct TailLevel {
-  int n, nnz, ncol, nc;  // nc: nodes of level l+1 (0 for the coarsest)
-  const int *rp, *ci;
-  const double *val64, *diag64;
-  const float *val32, *diag32;
-  const int *cptr, *lptr, *lrows;
-  const int *agg, *agg_ptr, *members;                 // into level l+1 (aggregation)
-  const int *cidx, *cfine, *er_rp, *er_ci;            // into level l+1 (elimination)
-  const double* er64;
-  const float* er32;
-  double *x64, *b64, *r64, *X64[2], *R64[2];
-  float *x32, *b32, *r32, *X32[2], *R32[2];
-};
-
 struct TailParams {
   const TailLevel* L;
   int lc;
   const double* Minv;
   int nL, crelax, csweeps;
   double mu;
+  int kc;  // columns of the vector blocks (multi-vector form; 1 otherwise)
 };
 
 template <class T> struct TV;
@@ -82,10 +69,30 @@ template <> struct TV<float> {
   __device__ static float* R(const TailLevel& L, int i) { return L.R32[i]; }
 };
 
+// One column of an n x k row-major block: element i at p[i * k].  With
+// MV = false the stride is the compile-time constant 1 (a plain vector).
+template <class T, bool MV>
+struct Col {
+  T* p;
+  int k;
+  __device__ __attribute__((always_inline)) T& operator[](int i) const {
+    if constexpr (MV) return p[i * k];
+    else return p[i];
+  }
+};
+template <bool MV>
+struct ColOf {
+  int j, k;  // column index and stride
+  template <class T>
+  __device__ __attribute__((always_inline)) Col<T, MV> operator()(T* p) const {
+    return Col<T, MV>{MV ? p + j : p, k};
+  }
+};
+
 // Sum of a row against vector v, left to right; the index and weight loads of
 // 8 entries are issued before their 8 gathers (arrays in global memory or LDS).
-template <class T>
-__device__ __attribute__((always_inline)) inline T row_seq_p(const T* val, const int* ci, int p0, int len, const T* v) {
+template <class T, class V>
+__device__ __attribute__((always_inline)) inline T row_seq_p(const T* val, const int* ci, int p0, int len, V v) {
   T s = 0;
   for (int t0 = 0; t0 < len; t0 += 8) {
     int cj[8];
@@ -104,34 +111,17 @@ __device__ __attribute__((always_inline)) inline T row_seq_p(const T* val, const
   }
   return s;
 }
-template <class T>
-__device__ __attribute__((always_inline)) inline T row_seq(const TailLevel& L, int p0, int len, const T* v) {
-  const T* val = TV<T>::val(L);
-  T s = 0;
-  for (int t0 = 0; t0 < len; t0 += 8) {
-    int cj[8];
-    T wj[8], xj[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int t = t0 + q;
-      cj[q] = t < len ? L.ci[p0 + t] : 0;
-      wj[q] = t < len ? val[p0 + t] : T(0);
-    }
-#pragma unroll
-    for (int q = 0; q < 8; ++q) xj[q] = v[cj[q]];
-#pragma unroll
-    for (int q = 0; q < 8; ++q)
-      if (t0 + q < len) s += wj[q] * xj[q];
-  }
-  return s;
+template <class T, class V>
+__device__ __attribute__((always_inline)) inline T row_seq(const TailLevel& L, int p0, int len, V v) {
+  return row_seq_p<T>(TV<T>::val(L), L.ci, p0, len, v);
 }
-template <class T>
-__device__ __attribute__((always_inline)) inline T row_short(const TailLevel& L, int u, const T* v) {
+template <class T, class V>
+__device__ __attribute__((always_inline)) inline T row_short(const TailLevel& L, int u, V v) {
   const int p0 = L.rp[u];
   return row_seq<T>(L, p0, L.rp[u + 1] - p0, v);
 }
-template <class T>
-__device__ __attribute__((always_inline)) inline T row_long(const TailLevel& L, int u, const T* v, int lane) {
+template <class T, class V>
+__device__ __attribute__((always_inline)) inline T row_long(const TailLevel& L, int u, V v, int lane) {
   const int p0 = L.rp[u], len = L.rp[u + 1] - p0;
   const T* val = TV<T>::val(L);
   return dev::row_sum_wave<T>(len, lane, [&](int t) { return val[p0 + t] * v[L.ci[p0 + t]]; });
@@ -139,10 +129,10 @@ __device__ __attribute__((always_inline)) inline T row_long(const TailLevel& L, 
 
 // One multicolour GS sweep: short rows one per thread, long rows one per
 // wavefront, a barrier after each colour class.
-template <class T>
-__device__ __attribute__((always_inline)) inline void tail_gs(const TailLevel& L) {
-  T* x = TV<T>::x(L);
-  const T* b = TV<T>::b(L);
+template <class T, bool MV>
+__device__ __attribute__((always_inline)) inline void tail_gs(const TailLevel& L, ColOf<MV> C) {
+  auto x = C(TV<T>::x(L));
+  auto b = C(TV<T>::b(L));
   const T* dg = TV<T>::diag(L);
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
   for (int c = 0; c < L.ncol; ++c) {
@@ -173,10 +163,11 @@ template <class T>
 __device__ inline bool tail_fits_all(const TailLevel& L) {
   return tail_vec_bytes<T>(L) + (size_t)L.nnz * (sizeof(T) + sizeof(int)) + 16 <= (size_t)TAIL_LDS;
 }
-template <class T>
-__device__ __attribute__((always_inline)) inline void tail_gs_lds(const TailLevel& L, char* lds, int sweeps) {
-  T* x = TV<T>::x(L);
-  const T* b = TV<T>::b(L);
+template <class T, bool MV>
+__device__ __attribute__((always_inline)) inline void tail_gs_lds(const TailLevel& L, ColOf<MV> C, char* lds,
+                                                                  int sweeps) {
+  auto x = C(TV<T>::x(L));
+  auto b = C(TV<T>::b(L));
   const T* dg = TV<T>::diag(L);
   const int n = L.n, nc = L.ncol;
   T* sx = (T*)lds;
@@ -207,7 +198,7 @@ __device__ __attribute__((always_inline)) inline void tail_gs_lds(const TailLeve
       for (int u = scp[c] + tid; u < c1; u += TAIL_THREADS) {
         const int p0 = srp[u], len = srp[u + 1] - p0;
         if (len > SHORT_ROW) continue;
-        sx[u] = (sbv[u] + row_seq_p<T>(val, ci, p0, len, sx)) / sd[u];
+        sx[u] = (sbv[u] + row_seq_p<T>(val, ci, p0, len, (const T*)sx)) / sd[u];
       }
       for (int k = slp[c] + wv; k < slp[c + 1]; k += TAIL_WAVES) {
         const int u = L.lrows[k];
@@ -219,19 +210,20 @@ __device__ __attribute__((always_inline)) inline void tail_gs_lds(const TailLeve
     }
   for (int i = tid; i < n; i += TAIL_THREADS) x[i] = sx[i];
 }
-template <class T>
-__device__ __attribute__((always_inline)) inline void tail_sweeps(const TailLevel& L, char* lds, int sweeps) {
+template <class T, bool MV>
+__device__ __attribute__((always_inline)) inline void tail_sweeps(const TailLevel& L, ColOf<MV> C, char* lds,
+                                                                  int sweeps) {
   if (tail_fits<T>(L)) {
-    tail_gs_lds<T>(L, lds, sweeps);
+    tail_gs_lds<T, MV>(L, C, lds, sweeps);
   } else {
-    for (int sw = 0; sw < sweeps; ++sw) tail_gs<T>(L);
+    for (int sw = 0; sw < sweeps; ++sw) tail_gs<T, MV>(L, C);
   }
 }
 
-template <class T>
-__device__ __attribute__((always_inline)) inline void tail_res(const TailLevel& L, T* out) {
-  const T* x = TV<T>::x(L);
-  const T* b = TV<T>::b(L);
+template <class T, bool MV>
+__device__ __attribute__((always_inline)) inline void tail_res(const TailLevel& L, ColOf<MV> C, Col<T, MV> out) {
+  auto x = C(TV<T>::x(L));
+  auto b = C(TV<T>::b(L));
   const T* dg = TV<T>::diag(L);
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
   for (int u = tid; u < L.n; u += TAIL_THREADS)
@@ -263,33 +255,37 @@ __device__ inline void block_sums(double (&v)[NV], double (*sh)[TAIL_WAVES]) {
   __syncthreads();
 }
 
-template <class T>
+// The op interpreter.  Multi-vector form: workgroup j runs the program on
+// column j of every block (stride P.kc); each column's recombination
+// coefficients and means are its own.
+template <class T, bool MV>
 __global__ __launch_bounds__(TAIL_THREADS) void k_tail(TailParams P, const int4* __restrict__ prog, int nops) {
   __shared__ double sh[6][TAIL_WAVES];
   extern __shared__ double lds_d[];  // staging: GS sweeps, coarsest right-hand side
   char* lds = (char*)lds_d;
   double* sb = lds_d;
   const int tid = threadIdx.x;
+  const ColOf<MV> C{MV ? (int)blockIdx.x : 0, MV ? P.kc : 1};
   for (int i = 0; i < nops; ++i) {
     const int4 op = prog[i];
     const TailLevel& L = P.L[op.y - P.lc];
     switch (op.x) {
       case OP_GS:
-        tail_sweeps<T>(L, lds, 1);
+        tail_sweeps<T, MV>(L, C, lds, 1);
         break;
       case OP_RES:
-        tail_res<T>(L, op.z == 0 ? TV<T>::r(L) : TV<T>::R(L, op.z - 1));
+        tail_res<T, MV>(L, C, C(op.z == 0 ? TV<T>::r(L) : TV<T>::R(L, op.z - 1)));
         break;
       case OP_SAVEX: {
-        const T* x = TV<T>::x(L);
-        T* X = TV<T>::X(L, op.z);
+        auto x = C(TV<T>::x(L));
+        auto X = C(TV<T>::X(L, op.z));
         for (int u = tid; u < L.n; u += TAIL_THREADS) X[u] = x[u];
         break;
       }
       case OP_RAGG: {
-        const TailLevel& C = P.L[op.y + 1 - P.lc];
-        const T* src = op.z == 0 ? TV<T>::r(L) : TV<T>::R(L, op.z - 1);
-        T* bc = TV<T>::b(C);
+        const TailLevel& Lc = P.L[op.y + 1 - P.lc];
+        auto src = C(op.z == 0 ? TV<T>::r(L) : TV<T>::R(L, op.z - 1));
+        auto bc = C(TV<T>::b(Lc));
         const T mu = op.w ? (T)P.mu : T(1);
         for (int U = tid; U < L.nc; U += TAIL_THREADS) {
           T s = 0;
@@ -301,14 +297,15 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(TailParams P, const int4*
       case OP_RRAGG: {
         // one thread per aggregate: residuals of its members (rows summed left
         // to right), saved iterate, restricted sum, zeroed coarse iterate
-        const TailLevel& C = P.L[op.y + 1 - P.lc];
-        T* dst = op.z == 0 ? TV<T>::r(L) : TV<T>::R(L, op.z - 1);
-        T* Xs = op.z == 0 ? nullptr : TV<T>::X(L, op.z - 1);
-        const T* x = TV<T>::x(L);
-        const T* b = TV<T>::b(L);
+        const TailLevel& Lc = P.L[op.y + 1 - P.lc];
+        auto dst = C(op.z == 0 ? TV<T>::r(L) : TV<T>::R(L, op.z - 1));
+        const bool save = op.z != 0;
+        auto Xs = C(save ? TV<T>::X(L, op.z - 1) : TV<T>::x(L));
+        auto x = C(TV<T>::x(L));
+        auto b = C(TV<T>::b(L));
         const T* dg = TV<T>::diag(L);
-        T* bc = TV<T>::b(C);
-        T* xc = TV<T>::x(C);
+        auto bc = C(TV<T>::b(Lc));
+        auto xc = C(TV<T>::x(Lc));
         const T mu = op.w ? (T)P.mu : T(1);
         for (int U = tid; U < L.nc; U += TAIL_THREADS) {
           T s = 0;
@@ -318,7 +315,7 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(TailParams P, const int4*
             const T xm = x[m];
             const T rm = (b[m] + row_seq<T>(L, p0, L.rp[m + 1] - p0, x)) - dg[m] * xm;
             dst[m] = rm;
-            if (Xs) Xs[m] = xm;
+            if (save) Xs[m] = xm;
             s += rm;
           }
           bc[U] = mu * s;
@@ -327,22 +324,22 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(TailParams P, const int4*
         break;
       }
       case OP_ZERO: {
-        T* x = TV<T>::x(L);
+        auto x = C(TV<T>::x(L));
         for (int u = tid; u < L.n; u += TAIL_THREADS) x[u] = T(0);
         break;
       }
       case OP_IAGG: {
-        const TailLevel& C = P.L[op.y + 1 - P.lc];
-        const T* e = TV<T>::x(C);
-        T* x = TV<T>::x(L);
+        const TailLevel& Lc = P.L[op.y + 1 - P.lc];
+        auto e = C(TV<T>::x(Lc));
+        auto x = C(TV<T>::x(L));
         for (int u = tid; u < L.n; u += TAIL_THREADS) x[u] += e[L.agg[u]];
         break;
       }
       case OP_RELIM: {
-        const TailLevel& C = P.L[op.y + 1 - P.lc];
-        const T* r = TV<T>::r(L);
+        const TailLevel& Lc = P.L[op.y + 1 - P.lc];
+        auto r = C(TV<T>::r(L));
         const T* er = TV<T>::er(L);
-        T* bc = TV<T>::b(C);
+        auto bc = C(TV<T>::b(Lc));
         for (int c = tid; c < L.nc; c += TAIL_THREADS) {
           T s = 0;
           for (int j = L.er_rp[c]; j < L.er_rp[c + 1]; ++j) s += er[j] * r[L.er_ci[j]];
@@ -351,12 +348,12 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(TailParams P, const int4*
         break;
       }
       case OP_IELIM: {
-        const TailLevel& C = P.L[op.y + 1 - P.lc];
-        const T* e = TV<T>::x(C);
-        const T* r = TV<T>::r(L);
+        const TailLevel& Lc = P.L[op.y + 1 - P.lc];
+        auto e = C(TV<T>::x(Lc));
+        auto r = C(TV<T>::r(L));
         const T* val = TV<T>::val(L);
         const T* dg = TV<T>::diag(L);
-        T* x = TV<T>::x(L);
+        auto x = C(TV<T>::x(L));
         for (int u = tid; u < L.n; u += TAIL_THREADS) {
           const int c = L.cidx[u];
           if (c >= 0) { x[u] += e[c]; continue; }
@@ -368,11 +365,11 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(TailParams P, const int4*
       }
       case OP_RECOMB: {
         const int th = op.z;
-        T* r = TV<T>::r(L);
-        tail_res<T>(L, r);
+        auto r = C(TV<T>::r(L));
+        tail_res<T, MV>(L, C, r);
         __syncthreads();
-        const T* R0 = TV<T>::R(L, 0);
-        const T* R1 = TV<T>::R(L, 1);
+        auto R0 = C(TV<T>::R(L, 0));
+        auto R1 = C(TV<T>::R(L, 1));
         double v[6] = {0, 0, 0, 0, 0, 0};
         for (int u = tid; u < L.n; u += TAIL_THREADS) {
           const double ru = (double)r[u];
@@ -397,9 +394,9 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(TailParams P, const int4*
             if (G11 > tiny) a1 = -g1 / G11;
           }
         }
-        T* x = TV<T>::x(L);
-        const T* X0 = TV<T>::X(L, 0);
-        const T* X1 = TV<T>::X(L, 1);
+        auto x = C(TV<T>::x(L));
+        auto X0 = C(TV<T>::X(L, 0));
+        auto X1 = C(TV<T>::X(L, 1));
         for (int u = tid; u < L.n; u += TAIL_THREADS) {
           const double xu = (double)x[u];
           double y = xu;
@@ -411,12 +408,12 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(TailParams P, const int4*
       }
       case OP_COARSE: {
         if (P.crelax) {
-          tail_sweeps<T>(L, lds, P.csweeps);
+          tail_sweeps<T, MV>(L, C, lds, P.csweeps);
           break;
         }
         // x = M^-1 b: one wavefront per row, coalesced row loads
-        const T* b = TV<T>::b(L);
-        T* x = TV<T>::x(L);
+        auto b = C(TV<T>::b(L));
+        auto x = C(TV<T>::x(L));
         for (int j = tid; j < P.nL; j += TAIL_THREADS) sb[j] = (double)b[j];
         __syncthreads();
         const int wv = tid >> 6, lane = tid & 63;
@@ -430,7 +427,7 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(TailParams P, const int4*
         break;
       }
       case OP_MEAN: {
-        T* x = TV<T>::x(L);
+        auto x = C(TV<T>::x(L));
         double v[1] = {0};
         for (int u = tid; u < L.n; u += TAIL_THREADS) v[0] += (double)x[u];
         block_sums<1>(v, sh);
@@ -543,6 +540,7 @@ void tail_prepare(Hierarchy* H) {
   TailLevel* dd = dnew<TailLevel>(H, d.size());
   LAMG_HIP(hipMemcpy(dd, d.data(), d.size() * sizeof(TailLevel), hipMemcpyHostToDevice));
   H->tail_levels = dd;
+  H->tail_host = d;
   // the op program of one finest cycle
   Gen g;
   g.H = H;
@@ -557,28 +555,69 @@ void tail_prepare(Hierarchy* H) {
   H->tail_lc = lc;  // ready
 }
 
-template <class T>
-void tail_run_next(Hierarchy* H) {
+namespace {
+template <class T, bool MV>
+void launch_tail(Hierarchy* H, const void* levels, int kc) {
   const int2 seg = H->tail_segs[H->tail_cursor++];
   TailParams P;
-  P.L = (const TailLevel*)H->tail_levels;
+  P.L = (const TailLevel*)levels;
   P.lc = H->tail_lc;
   P.Minv = H->cinv;
   P.nL = H->nL;
   P.crelax = H->coarsest_relax ? 1 : 0;
   P.csweeps = H->o.coarsest_sweeps;
   P.mu = H->o.mu;
-  const size_t lds = std::max<size_t>(TAIL_LDS, H->coarsest_relax ? 0 : (size_t)H->nL * sizeof(double));
+  P.kc = kc;
+  // TAIL_LDS covers the coarsest right-hand side too: n_L <= 8192 doubles
+  const size_t lds = TAIL_LDS;
   static bool attr_set = false;
   if (!attr_set) {
-    LAMG_HIP(hipFuncSetAttribute((const void*)k_tail<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    LAMG_HIP(hipFuncSetAttribute((const void*)k_tail<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    LAMG_HIP(hipFuncSetAttribute((const void*)k_tail<T, MV>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     attr_set = true;
   }
-  hipLaunchKernelGGL(k_tail<T>, dim3(1), dim3(TAIL_THREADS), lds, H->s, P, (const int4*)(H->tail_prog + seg.x), seg.y);
+  hipLaunchKernelGGL((k_tail<T, MV>), dim3(MV ? kc : 1), dim3(TAIL_THREADS), lds, H->s, P,
+                     (const int4*)(H->tail_prog + seg.x), seg.y);
   LAMG_HIP(hipGetLastError());
+}
+}  // namespace
+
+template <class T>
+void tail_run_next(Hierarchy* H) {
+  launch_tail<T, false>(H, H->tail_levels, 1);
 }
 template void tail_run_next<double>(Hierarchy*);
 template void tail_run_next<float>(Hierarchy*);
+
+// Descriptors of the tail levels that point at the multi-vector workspace
+// (rebuilt whenever the workspace or the single-vector descriptors change).
+void tail_prepare_mv(Hierarchy* H) {
+  tail_prepare(H);
+  MVWork& W = H->mv;
+  const int nl = (int)H->lv.size();
+  const int lc = H->tail_lc;
+  if (lc >= nl || W.tail_src == H->tail_levels) return;
+  std::vector<TailLevel> d = H->tail_host;
+  for (int l = lc; l < nl; ++l) {
+    TailLevel& t = d[l - lc];
+    const Vecs<double>& a = W.v64[l];
+    const Vecs<float>& f = W.v32[l];
+    t.x64 = a.x; t.b64 = a.b; t.r64 = a.r;
+    t.x32 = f.x; t.b32 = f.b; t.r32 = f.r;
+    for (int i = 0; i < 2; ++i) { t.X64[i] = a.X[i]; t.R64[i] = a.R[i]; t.X32[i] = f.X[i]; t.R32[i] = f.R[i]; }
+  }
+  void* p = nullptr;
+  LAMG_HIP(hipMalloc(&p, d.size() * sizeof(TailLevel)));
+  W.owned.push_back(p);
+  LAMG_HIP(hipMemcpy(p, d.data(), d.size() * sizeof(TailLevel), hipMemcpyHostToDevice));
+  W.tail = (TailLevel*)p;
+  W.tail_src = H->tail_levels;
+}
+
+template <class T>
+void tail_run_next_mv(Hierarchy* H) {
+  launch_tail<T, true>(H, H->mv.tail, H->mv.k);
+}
+template void tail_run_next_mv<double>(Hierarchy*);
+template void tail_run_next_mv<float>(Hierarchy*);
 
 }  // namespace lamg

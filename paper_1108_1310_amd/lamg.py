@@ -78,6 +78,8 @@ def lib():
             "lamg_t_transfer_export": (C.c_int, [vp, C.c_int, vp]),
             "lamg_t_agg_export": (C.c_int, [vp, C.c_int, vp, vp, vp, vp, vp, vp, vp]),
             "lamg_t_cycle": (C.c_int, [vp, vp, vp]),
+            "lamg_t_mv_cycle": (C.c_int, [vp, i32, vp, vp]),
+            "lamg_t_mv_columns": (C.c_int, [vp, i32, vp, vp, vp]),
             "lamg_t_coarsest_solve": (C.c_int, [vp, vp, vp]),
             "lamg_t_gs": (C.c_int, [i32, vp, vp, vp, vp, i32, vp, vp, vp, i32, vp]),
             "lamg_t_gs32": (C.c_int, [i32, vp, vp, vp, vp, i32, vp, vp, vp, i32, vp]),
@@ -150,7 +152,12 @@ class Hierarchy:
             lib().lamg_free(self.h)
             self.h = None
 
-    __del__ = close
+    def __del__(self):
+        # at interpreter exit the module globals may already be gone; the
+        # process teardown releases device memory then
+        if _lib is not None and getattr(self, "h", None):
+            _lib.lamg_free(self.h)
+            self.h = None
 
     def set_solve_options(self, **kw):
         for k, v in kw.items():
@@ -230,6 +237,30 @@ class Hierarchy:
         x = _dev(x_perm, torch.float64).clone()
         _check(lib().lamg_t_cycle(self.h, _ptr(b), _ptr(x)), "lamg_t_cycle")
         return x
+
+    def mv_cycle(self, B_perm, X_perm):
+        """One FP64 multi-vector cycle on [n, k] colour-ordered blocks."""
+        b = _dev(B_perm, torch.float64).contiguous()
+        x = _dev(X_perm, torch.float64).clone().contiguous()
+        _check(lib().lamg_t_mv_cycle(self.h, b.shape[1], _ptr(b), _ptr(x)), "lamg_t_mv_cycle")
+        return x
+
+    def solve_multi(self, B, X=None, **kw):
+        """Solve A X[:, j] = B[:, j] - mean for every column of B [n, k] with
+        the multi-vector cycle.  Returns (X, info of the worst column, per-column
+        dict with cycles / rel_residual / removed_mean arrays, status)."""
+        if kw:
+            self.set_solve_options(**kw)
+        B = _dev(B, torch.float64).contiguous()
+        k = B.shape[1]
+        Xs, infos, rc = solve_batch([self], [B], None if X is None else [X])
+        cyc = np.zeros(k, np.int32)
+        rel = np.zeros(k)
+        rm = np.zeros(k)
+        if k > 1:
+            _check(lib().lamg_t_mv_columns(self.h, k, C.c_void_p(cyc.ctypes.data), C.c_void_p(rel.ctypes.data),
+                                           C.c_void_p(rm.ctypes.data)), "lamg_t_mv_columns")
+        return Xs[0], infos[0], dict(cycles=cyc, rel_residual=rel, removed_mean=rm), rc
 
     def coarsest_solve(self, b):
         b = _dev(b, torch.float64)
