@@ -33,7 +33,7 @@ def parse():
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--workload", default="chung_lu_2p20",
-                   choices=["chung_lu_2p20", "grid2d_64", "rgg_2p20", "grid3d_128_k32"])
+                   choices=["chung_lu_2p20", "grid2d_64", "rgg_2p20", "grid3d_128_k32", "graph_batch_256"])
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU reference baseline")
     p.add_argument("--no-fp32", action="store_true")
     return p.parse_args()
@@ -164,6 +164,99 @@ def main_multi(a, g, B):
     print(json.dumps(rec), flush=True)
 
 
+def main_batch(a):
+    """Many-graph workload: 256 independent uneven graphs, one right-hand side
+    each, solved in one persistent launch per step (FP64 and FP32+refine);
+    the same graphs solved one after another with the multi-launch cycle are
+    timed once beside it."""
+    import torch
+    from paper_1108_1310_amd import lamg, workloads as W
+    gs = W.graph_batch()
+    bs = [torch.tensor(W.rhs_normal(g.n, 1, 1000 + i), device="cuda") for i, g in enumerate(gs)]
+    m_tot = sum(g.m for g in gs)
+    n_tot = sum(g.n for g in gs)
+    print(f"[bench] batch of {len(gs)} graphs: n={n_tot} m={m_tot}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hs = [lamg.Hierarchy(g.n, g.eu, g.ev, g.w) for g in gs]
+    torch.cuda.synchronize()
+    setup_ms = (time.perf_counter() - t0) * 1e3
+    print(f"[bench] setup {setup_ms:.1f} ms", file=sys.stderr, flush=True)
+    res = {}
+    for prec in (lamg.FP64, lamg.FP32_REFINE):
+        for h in hs:
+            h.set_solve_options(precision=prec)
+        for _ in range(a.warmup):
+            lamg.solve_batch(hs, bs)  # the first call also autotunes the launch
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        edge_cycles, byts, worst, cyc = 0, 0, 0.0, 0
+        t0 = time.perf_counter()
+        ev0.record()
+        for _ in range(a.steps):
+            X, infos, rc = lamg.solve_batch(hs, bs)
+            if rc != 0:
+                raise RuntimeError(f"batch status {rc}")
+            edge_cycles += sum(g.m * i["cycles"] for g, i in zip(gs, infos))
+            byts += sum(i["bytes_moved"] for i in infos)
+            worst = max(worst, max(i["rel_residual"] for i in infos))
+            cyc += sum(i["cycles"] for i in infos)
+        ev1.record()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        res[prec] = dict(seconds=dt, event_ms=ev0.elapsed_time(ev1), edge_cycles=edge_cycles, bytes=byts, worst=worst,
+                         cycles=cyc, X=X)
+        print(f"[bench] batch precision={prec} {dt:.3f}s", file=sys.stderr, flush=True)
+    # the same graphs one after another (multi-launch single solves), FP64
+    for h in hs:
+        h.set_solve_options(precision=lamg.FP64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    seq_ec = 0
+    for g, h, b in zip(gs, hs, bs):
+        x, i = h.solve(b)
+        seq_ec += g.m * i["cycles"]
+    torch.cuda.synchronize()
+    seq = time.perf_counter() - t0
+    print(f"[bench] sequential fp64 {seq:.3f}s", file=sys.stderr, flush=True)
+    r64, r32 = res[lamg.FP64], res[lamg.FP32_REFINE]
+    achieved = r64["bytes"] / (r64["event_ms"] * 1e6)
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "kernel": "k_batch (persistent many-graph solve, FP64)",
+                "avg_launch_us": 1e3 * r64["event_ms"] / a.steps, "launches": a.steps,
+                "bytes_per_launch": r64["bytes"] / a.steps}
+    cpu = None
+    if not a.no_cpu:
+        print("[bench] cpu baseline", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(a.workload)
+    rec = {
+        "metric": "edges*cycles/s to 1e-8 rel. residual (sum over the batch's graphs; FP64, FP32+refine beside)",
+        "value": r64["edge_cycles"] / r64["seconds"],
+        "unit": "edges*cycles/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": r64["seconds"] * 1e3 / a.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": a.workload, "graphs": len(gs), "n": n_tot, "m": m_tot, "precision": "fp64",
+                   "tol": 1e-8, "setup_ms": setup_ms},
+        "gbps": r64["bytes"] / r64["seconds"] / 1e9,
+        "cycles_per_graph": r64["cycles"] / (a.steps * len(gs)),
+        "rel_residual": r64["worst"],
+        "fp32_refine": {"value": r32["edge_cycles"] / r32["seconds"], "ms_per_step": r32["seconds"] * 1e3 / a.steps,
+                        "gbps": r32["bytes"] / r32["seconds"] / 1e9, "rel_residual": r32["worst"]},
+        "sequential_fp64": {"value": seq_ec / seq, "ms": seq * 1e3},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(rec), flush=True)
+
+
 def cpu_baseline(name):
     """The CPU reference (serial C++) on a bounded sample of the same workload recipe."""
     from oracle import oracle as O
@@ -189,6 +282,18 @@ def cpu_baseline(name):
         dt = time.perf_counter() - t0
         return {"value": g.m * cyc / dt, "unit": "edges*cycles/s", "cores": 1, "kind": "oracle", "sample": sample,
                 "cycles": cyc, "solve_s": dt, "edges": g.m}
+    elif name == "graph_batch_256":
+        gs = W.graph_batch()[:24]
+        sample = "the first 24 graphs of the batch, FP64 solves to 1e-8 one after another, 1 thread (setup not timed)"
+        dt, ec = 0.0, 0
+        for i, g in enumerate(gs):
+            H = O.Hierarchy(g.n, g.eu, g.ev, g.w)
+            t0 = time.perf_counter()
+            x, info, _ = H.solve(W.rhs_normal(g.n, 1, 1000 + i))
+            dt += time.perf_counter() - t0
+            ec += g.m * info["cycles"]
+        return {"value": ec / dt, "unit": "edges*cycles/s", "cores": 1, "kind": "oracle", "sample": sample,
+                "solve_s": dt}
     else:
         g, b = W.config(name)
         sample = "full workload, FP64 solve to 1e-8, 1 thread"
@@ -210,6 +315,8 @@ def main():
     from paper_1108_1310_amd import lamg
     torch.cuda.set_device(0)
     print(f"[bench] generating {a.workload}", file=sys.stderr, flush=True)
+    if a.workload == "graph_batch_256":
+        return main_batch(a)
     g, b = workload(a.workload)
     if b.ndim == 2 and b.shape[1] > 1:
         print(f"[bench] n={g.n} m={g.m} k={b.shape[1]}", file=sys.stderr, flush=True)

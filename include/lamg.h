@@ -110,8 +110,17 @@ lamg_status lamg_solve(lamg_handle h, const double* b, double* x, lamg_info* inf
 /* Batched solves (re-solving for many b is cheap once the setup is done,
  * Section 1).  For each i < count: handle hs[i] solves nrhs[i] right-hand
  * sides stored DEVICE B[i] (n_i x nrhs[i], row-major, RHS index fastest) into
- * DEVICE X[i] of the same shape.
- *   nrhs[i] == 1: the single-vector solve of lamg_solve.
+ * DEVICE X[i] of the same shape.  A handle may appear only once.
+ *   nrhs[i] == 1, count == 1 (or n_i > 2^18): the single-vector solve of
+ *     lamg_solve.
+ *   nrhs[i] == 1, count > 1, n_i <= 2^18: all such entries are solved in ONE
+ *     persistent launch on hs[0]'s stream: each workgroup takes the next graph
+ *     from a queue (largest estimated work first) and runs its whole solve
+ *     (the same cycle as lamg_solve, each graph with its own precision, tol,
+ *     max_cycles and warm start).  The launch configuration is autotuned: the
+ *     first batch of a given shape is solved once per candidate configuration
+ *     and the fastest is kept for the process (no tuning when a warm start is
+ *     requested); results do not depend on the configuration.
  *   nrhs[i] == k > 1: the multi-vector cycle.  Every level works on n_l x k
  *     blocks; each column has its own recombination coefficients, mean and
  *     convergence test, and stops updating once it meets tol (its mask is

@@ -68,6 +68,14 @@ lamg_status lamg_t_mv_cycle(lamg_handle h, int32_t k, const double* b_perm, doub
  * multi-vector solve had another k. */
 lamg_status lamg_t_mv_columns(lamg_handle h, int32_t k, int32_t* cycles, double* rel, double* removed_mean);
 
+/* Launch configuration of the persistent many-graph solve (lamg_solve_batch
+ * with count > 1): config in [0, 4) forces that configuration (LDS staging
+ * budget 128/64 KB, 1 or 2 workgroups per compute unit, largest-work-first or
+ * input queue order); -1 restores the autotuner, which times every
+ * configuration on the first batch of each shape and keeps the fastest.
+ * Process-wide; not thread-safe.  LAMG_E_INVALID_ARG outside [-1, 4). */
+lamg_status lamg_t_batch_config(int32_t config);
+
 /* Coarsest-level solve x = (A_L + (mean diag / n_L) 1 1^T)^-1 b, DEVICE [n_L]
  * (dense coarsest levels only). */
 lamg_status lamg_t_coarsest_solve(lamg_handle h, const double* b, double* x);

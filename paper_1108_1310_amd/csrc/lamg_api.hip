@@ -363,7 +363,7 @@ lamg_status lamg_set_solve_options(lamg_handle h, const lamg_options* o) {
   if (o->ec != H->o.ec || o->mu != H->o.mu || o->nu_pre != H->o.nu_pre || o->nu_post != H->o.nu_post) {
     drop_graphs(H);
     mv_drop_graphs(H);
-    H->tail_lc = -1;
+    invalidate_programs(H);
   }
   if (o->nu_pre < 0 || o->nu_post < 0) return LAMG_E_INVALID_ARG;
   H->o.precision = o->precision;
@@ -453,21 +453,46 @@ lamg_status lamg_solve(lamg_handle h, const double* b, double* x, lamg_info* inf
   }
 }
 
+// Graphs up to this size join the persistent launch of a many-graph batch;
+// larger ones are solved one after another with the multi-launch cycle.
+constexpr int BATCH_MAX_N = 1 << 18;
+
 lamg_status lamg_solve_batch(int32_t count, const lamg_handle* hs, const int32_t* nrhs, const double* const* B,
                              double* const* X, lamg_info* infos) {
   if (count < 0 || (count > 0 && (!hs || !nrhs || !B || !X))) return LAMG_E_INVALID_ARG;
   lamg_status worst = LAMG_OK;
   for (int i = 0; i < count; ++i) {
     if (!hs[i] || nrhs[i] < 1 || !B[i] || !X[i]) return LAMG_E_INVALID_ARG;
+    for (int j = 0; j < i; ++j)
+      if (hs[j] == hs[i]) return LAMG_E_INVALID_ARG;  // one handle, one solve at a time
   }
   try {
+    std::vector<int> many;  // single right-hand sides of small graphs: one persistent launch
     for (int i = 0; i < count; ++i) {
       Hierarchy* H = &hs[i]->H;
       lamg_info acc{};
-      const lamg_status st = nrhs[i] == 1 ? solve_one(H, B[i], X[i], &acc) : solve_multi(H, nrhs[i], B[i], X[i], &acc);
-      if (st != LAMG_OK && worst == LAMG_OK) worst = st;
+      lamg_status st = LAMG_OK;
+      if (nrhs[i] > 1) st = solve_multi(H, nrhs[i], B[i], X[i], &acc);
+      else if (count > 1 && H->lv[0].n <= BATCH_MAX_N) { many.push_back(i); continue; }
+      else st = solve_one(H, B[i], X[i], &acc);
       if (st == LAMG_E_INVALID_ARG) return st;
+      if (st != LAMG_OK && worst == LAMG_OK) worst = st;
       if (infos) infos[i] = acc;
+    }
+    if (!many.empty()) {
+      std::vector<Hierarchy*> H(many.size());
+      std::vector<const double*> b(many.size());
+      std::vector<double*> x(many.size());
+      std::vector<lamg_info> inf(many.size());
+      for (size_t j = 0; j < many.size(); ++j) {
+        H[j] = &hs[many[j]]->H;
+        b[j] = B[many[j]];
+        x[j] = X[many[j]];
+      }
+      const lamg_status st = solve_graphs((int)many.size(), H.data(), b.data(), x.data(), inf.data());
+      if (st != LAMG_OK && worst == LAMG_OK) worst = st;
+      if (infos)
+        for (size_t j = 0; j < many.size(); ++j) infos[many[j]] = inf[j];
     }
   } catch (const DevError& e) {
     set_last_error("lamg_solve_batch", e.e);

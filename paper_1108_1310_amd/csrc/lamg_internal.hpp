@@ -72,6 +72,7 @@ struct Level {
   std::vector<Tiles> tiles;         // per colour
   Tiles all;                        // every row (residual)
   std::vector<int> long_ptr, long_rows;  // host: rows > SHORT_ROW grouped by colour
+  int *d_cptr = nullptr, *d_lptr = nullptr, *d_lrows = nullptr;  // device copies (op programs)
   // transfer from the previous level into this one
   int* agg = nullptr;               // AGG: fine node -> this level's node
   int *agg_ptr = nullptr, *members = nullptr;  // P^T as CSR (aggregate members ascending)
@@ -163,6 +164,11 @@ struct Hierarchy {
   int tail_cursor = 0;
   std::vector<TailLevel> tail_host;  // host copy of the descriptors
   MVWork mv;
+  // whole-hierarchy op program (every level, from level 0) for the
+  // persistent many-graph solve
+  void* full_levels = nullptr;
+  int4* full_prog = nullptr;
+  int full_nops = 0;
 };
 
 // -------------------------------------------------------- instrumentation
@@ -248,6 +254,11 @@ void drop_graphs(Hierarchy* H);
 void tail_prepare(Hierarchy* H);
 template <class T>
 void tail_run_next(Hierarchy* H);
+// Drop the op programs (they depend on nu, ec and mu).
+void invalidate_programs(Hierarchy* H);
+// Persistent many-graph solve: every graph's whole solve in one workgroup.
+lamg_status solve_graphs(int count, Hierarchy* const* hs, const double* const* B, double* const* X,
+                         lamg_info* infos);
 // Multi-vector tail: one workgroup per column of the workspace blocks.
 void tail_prepare_mv(Hierarchy* H);
 template <class T>

@@ -80,6 +80,7 @@ def lib():
             "lamg_t_cycle": (C.c_int, [vp, vp, vp]),
             "lamg_t_mv_cycle": (C.c_int, [vp, i32, vp, vp]),
             "lamg_t_mv_columns": (C.c_int, [vp, i32, vp, vp, vp]),
+            "lamg_t_batch_config": (C.c_int, [i32]),
             "lamg_t_coarsest_solve": (C.c_int, [vp, vp, vp]),
             "lamg_t_gs": (C.c_int, [i32, vp, vp, vp, vp, i32, vp, vp, vp, i32, vp]),
             "lamg_t_gs32": (C.c_int, [i32, vp, vp, vp, vp, i32, vp, vp, vp, i32, vp]),

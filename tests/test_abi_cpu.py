@@ -50,3 +50,6 @@ def test_host_only_entry_points():
     assert L.lamg_setup(4, 3, None, None, None, None, ctypes.byref(h)) == lamg.E_INVALID_ARG
     assert h.value is None
     L.lamg_free(None)  # no-op
+    # batch launch configuration: only -1 (autotune) and 0..3
+    assert L.lamg_t_batch_config(4) == lamg.E_INVALID_ARG and L.lamg_t_batch_config(-2) == lamg.E_INVALID_ARG
+    assert L.lamg_t_batch_config(-1) == 0
