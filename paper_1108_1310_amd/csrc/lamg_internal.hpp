@@ -176,7 +176,12 @@ struct Hierarchy {
 // on its stream and its algorithmic bytes are accumulated per kernel:
 // 0 GS FP64, 1 residual FP64, 2 GS FP32, 3 residual FP32, and 4..7 the same
 // four for the multi-vector kernels.
-void prof_mark(hipStream_t s, int kernel, int64_t bytes, bool begin);
+// Spans: prof_begin records the opening event of a run of launches of one
+// kernel, prof_count adds each launch (and its algorithmic bytes) of that
+// kernel to the open span, prof_end records the closing event.
+void prof_begin(hipStream_t s, int kernel);
+void prof_count(int kernel, int64_t bytes);
+void prof_end(hipStream_t s);
 bool prof_on();
 // Instrumented cycles run eagerly (not from captured graphs) so that every
 // launch has its own timed event pair; prof_flush reads the pending pairs.

@@ -199,17 +199,17 @@ void relax_mv(hipStream_t s, const int* rp, const int* ci, const T* val, const T
   // read, x or r write
   const int64_t bytes = t.nnz * (4 + (int64_t)sizeof(T)) + t.rows * (4 + (int64_t)sizeof(T)) +
                         3 * t.rows * (int64_t)k * (int64_t)sizeof(T);
-  if (prof) prof_mark(s, kid, bytes, true);
+  const int* lr = (const int*)t.longrows;
+  if (prof) prof_count(kid, bytes);
   if (vw == 1)
-    hipLaunchKernelGGL((k_relax_mv<T, MODE, 1>), dim3(grid), dim3(MVT), 0, s, rp, ci, val, diag, b, x, r, map, k,
-                       glog, r0, r1, (const int*)t.longrows, t.nlong, nlb);
+    hipLaunchKernelGGL((k_relax_mv<T, MODE, 1>), dim3(grid), dim3(MVT), 0, s, rp, ci, val, diag, b, x, r, map, k, glog,
+                       r0, r1, lr, t.nlong, nlb);
   else if constexpr (sizeof(T) == 8)
-    hipLaunchKernelGGL((k_relax_mv<T, MODE, 2>), dim3(grid), dim3(MVT), 0, s, rp, ci, val, diag, b, x, r, map, k,
-                       glog, r0, r1, (const int*)t.longrows, t.nlong, nlb);
+    hipLaunchKernelGGL((k_relax_mv<T, MODE, 2>), dim3(grid), dim3(MVT), 0, s, rp, ci, val, diag, b, x, r, map, k, glog,
+                       r0, r1, lr, t.nlong, nlb);
   else
-    hipLaunchKernelGGL((k_relax_mv<T, MODE, 4>), dim3(grid), dim3(MVT), 0, s, rp, ci, val, diag, b, x, r, map, k,
-                       glog, r0, r1, (const int*)t.longrows, t.nlong, nlb);
-  if (prof) prof_mark(s, kid, bytes, false);
+    hipLaunchKernelGGL((k_relax_mv<T, MODE, 4>), dim3(grid), dim3(MVT), 0, s, rp, ci, val, diag, b, x, r, map, k, glog,
+                       r0, r1, lr, t.nlong, nlb);
   LAMG_HIP(hipGetLastError());
 }
 
@@ -229,13 +229,17 @@ template <> struct PrecM<float> {
 
 template <class T>
 void gs_sweep_mv(hipStream_t s, const Level& L, int k, const T* b, T* x) {
+  prof_begin(s, sizeof(T) == 4 ? 6 : 4);
   for (int c = 0; c < L.ncol; ++c)
     relax_mv<T, 0>(s, L.rp, L.ci, PrecM<T>::val(L), PrecM<T>::diag(L), b, x, (T*)nullptr, nullptr, k, L.cptr[c],
                    L.cptr[c + 1], L.tiles[c]);
+  prof_end(s);
 }
 template <class T>
 void residual_mv(hipStream_t s, const Level& L, int k, const T* b, const T* x, T* r) {
+  prof_begin(s, sizeof(T) == 4 ? 7 : 5);
   relax_mv<T, 1>(s, L.rp, L.ci, PrecM<T>::val(L), PrecM<T>::diag(L), b, (T*)x, r, nullptr, k, 0, L.n, L.all);
+  prof_end(s);
 }
 
 // ---------------------------------------------------------------- transfers

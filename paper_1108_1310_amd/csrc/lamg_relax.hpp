@@ -1,0 +1,131 @@
+// The relaxation kernel (multicolour Gauss-Seidel, residual and elimination
+// restriction over tiled CSR rows).  Kept in a file of its own: the recorded
+// HBM traffic of this kernel is tied to this file's contents.
+#pragma once
+#include "lamg_device.hpp"
+#include "lamg_internal.hpp"
+
+namespace lamg {
+
+// One pass over a set of rows of a colour-ordered level.
+//   MODE 0: Gauss-Seidel update x_u <- (b_u + sum_v w_uv x_v) / a_uu (eq. gs)
+//   MODE 1: residual r_u <- (b_u + sum_v w_uv x_v) - a_uu x_u
+// Stream blocks stage the products w_uv * x_v of up to TILE_NNZ entries of
+// consecutive short rows in LDS with coalesced loads, then one thread per row
+// sums them left to right.  Long-row blocks give each row a wavefront that
+// sums with stride 64 and folds with an xor butterfly.  A GS pass only ever
+// covers one colour class, whose rows are pairwise non-adjacent, so the rows
+// it writes are never read in the same launch.
+// MODE 0: GS update; MODE 1: residual; MODE 2: elimination restriction
+// out_u = x_{map(u)} + sum (the gathered vector is the fine residual).
+template <class T, int MODE>
+__device__ inline void relax_store(int u, T s, const T* __restrict__ diag, const T* __restrict__ b, T* x,
+                                   T* __restrict__ r, const int* __restrict__ map) {
+  if (MODE == 2) { r[u] = x[map[u]] + s; return; }
+  const T bu = b ? b[u] : T(0);
+  if (MODE == 0) x[u] = (bu + s) / diag[u];
+  else r[u] = (bu + s) - diag[u] * x[u];
+}
+
+// One 512-entry chunk of a long row, one wavefront: lane j sums the chunk's
+// entries j, j+64, ... left to right (all loads issued before the gathers),
+// then the butterfly folds the 64 partials.
+template <class T>
+__device__ inline T chunk_sum(const int* __restrict__ ci, const T* __restrict__ val, const T* x, int p0, int c0,
+                              int len, int lane) {
+  constexpr int UNR = ROW_CHUNK / 64;
+  int cj[UNR];
+  T wj[UNR], xj[UNR];
+#pragma unroll
+  for (int q = 0; q < UNR; ++q) {
+    const int t = c0 + lane + 64 * q;
+    cj[q] = t < len ? ci[p0 + t] : 0;
+    wj[q] = t < len ? val[p0 + t] : T(0);
+  }
+#pragma unroll
+  for (int q = 0; q < UNR; ++q) xj[q] = x[cj[q]];
+  T s = 0;
+#pragma unroll
+  for (int q = 0; q < UNR; ++q)
+    if (c0 + lane + 64 * q < len) s += wj[q] * xj[q];
+  return dev::wave_fold(s);
+}
+
+template <class T, int MODE>
+__global__ __launch_bounds__(RELAX_THREADS) void k_relax(
+    const int* __restrict__ rp, const int* __restrict__ ci, const T* __restrict__ val,
+    const T* __restrict__ diag, const T* __restrict__ b, T* x, T* __restrict__ r,
+    const int* __restrict__ vlong, int nvlong, const int* __restrict__ med, int nmed, int nmed_blocks,
+    const int2* __restrict__ sblk, int nstream, const int* __restrict__ map) {
+  constexpr int PER = TILE_NNZ / RELAX_THREADS;  // entries per thread in a stream tile
+  constexpr int MAXC = 64;                       // chunk sums staged per pass
+  __shared__ T prod[TILE_NNZ];
+  __shared__ int srp[TILE_ROWS + 1];
+  __shared__ T csum[MAXC];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  int bid = blockIdx.x;
+  if (bid < nvlong) {
+    // a very long row: chunks k = wv, wv+4, ... per pass; chunk sums added in order
+    const int u = vlong[bid];
+    const int p0 = rp[u], len = rp[u + 1] - p0;
+    const int nch = (len + ROW_CHUNK - 1) / ROW_CHUNK;
+    T total = 0;
+    for (int pass = 0; pass < nch; pass += MAXC) {
+      const int lim = min(MAXC, nch - pass);
+      for (int k = wv; k < lim; k += LONG_PER_BLOCK) {
+        const T sk = chunk_sum<T>(ci, val, x, p0, (pass + k) * ROW_CHUNK, len, lane);
+        if (lane == 0) csum[k] = sk;
+      }
+      __syncthreads();
+      if (threadIdx.x == 0)
+        for (int k = 0; k < lim; ++k) total += csum[k];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) relax_store<T, MODE>(u, total, diag, b, x, r, map);
+    return;
+  }
+  bid -= nvlong;
+  if (bid < nmed_blocks) {
+    const int idx = bid * LONG_PER_BLOCK + wv;
+    if (idx >= nmed) return;
+    const int u = med[idx];
+    const int p0 = rp[u], len = rp[u + 1] - p0;
+    const T sk = chunk_sum<T>(ci, val, x, p0, 0, len, lane);
+    T total = 0;
+    total += sk;
+    if (lane == 0) relax_store<T, MODE>(u, total, diag, b, x, r, map);
+    return;
+  }
+  bid -= nmed_blocks;
+  const int2 rr = sblk[bid];
+  const int nr = rr.y - rr.x;
+  for (int i = threadIdx.x; i <= nr; i += RELAX_THREADS) srp[i] = rp[rr.x + i];
+  __syncthreads();
+  const int base = srp[0];
+  const int cnt = srp[nr] - base;
+  // all index and weight loads first, then all gathers: PER loads in flight per thread
+  int cj[PER];
+  T wj[PER], xj[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int j = threadIdx.x + q * RELAX_THREADS;
+    cj[q] = j < cnt ? ci[base + j] : 0;
+    wj[q] = j < cnt ? val[base + j] : T(0);
+  }
+#pragma unroll
+  for (int q = 0; q < PER; ++q) xj[q] = x[cj[q]];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int j = threadIdx.x + q * RELAX_THREADS;
+    if (j < cnt) prod[j] = wj[q] * xj[q];
+  }
+  __syncthreads();
+  if (threadIdx.x < nr) {
+    const int j1 = srp[threadIdx.x + 1] - base;
+    T s = 0;
+    for (int j = srp[threadIdx.x] - base; j < j1; ++j) s += prod[j];
+    relax_store<T, MODE>(rr.x + threadIdx.x, s, diag, b, x, r, map);
+  }
+}
+
+}  // namespace lamg
