@@ -100,6 +100,10 @@ struct Level {
 // Device descriptor of one level for the single-workgroup tail program.
 struct TailLevel {
   int n, nnz, ncol, nc;  // nc: nodes of level l+1 (0 for the coarsest)
+  int nlong;             // rows longer than 64 entries
+  int nner;              // entries of the elimination stencil into level l+1
+  int vres;              // set on the device: this level's arrays sit in LDS
+  int pad_;
   const int *rp, *ci;
   const double *val64, *diag64;
   const float *val32, *diag32;

@@ -25,7 +25,7 @@ constexpr int TAIL_THREADS = 1024;
 constexpr int TAIL_WAVES = TAIL_THREADS / 64;
 
 enum TailOp {
-  OP_GS = 1,      // one multicolour sweep of level l
+  OP_GS = 1,      // a = multicolour sweeps of level l (one staging for all)
   OP_RES = 2,     // residual of level l into a = 0: r, 1: R0, 2: R1
   OP_SAVEX = 3,   // X[a] = x
   OP_RAGG = 4,    // b_{l+1} = mu^(b) * P^T src(a)
@@ -46,7 +46,9 @@ struct TailParams {
   int nL, crelax, csweeps;
   double mu;
   int kc;         // columns of the vector blocks (multi-vector form; 1 otherwise)
-  int lds_bytes;  // dynamic LDS of the launch: staging budget of the sweeps
+  int lds_bytes;  // dynamic LDS of the launch
+  int res_bytes;  // of which at most this much holds LDS-resident levels
+  int nlev;       // levels lc .. lc + nlev - 1 in the program
 };
 
 template <class T> struct TV;
@@ -85,16 +87,23 @@ struct Col {
 template <bool MV>
 struct ColOf {
   int j, k;  // column index and stride
+  // column j of level L's vector p: strided in global memory, or (for a
+  // level whose arrays sit in LDS) this workgroup's contiguous copy
   template <class T>
-  __device__ __attribute__((always_inline)) Col<T, MV> operator()(T* p) const {
-    return Col<T, MV>{MV ? p + j : p, k};
+  __device__ __attribute__((always_inline)) Col<T, MV> v(const TailLevel& L, T* p) const {
+    if constexpr (MV) return L.vres ? Col<T, MV>{p, 1} : Col<T, MV>{p + j, k};
+    else return Col<T, MV>{p, 1};
   }
 };
 
+// Pointer into LDS (address space 3): loads through it are ds_read.
+template <class T>
+using LP = __attribute__((address_space(3))) T*;
+
 // Sum of a row against vector v, left to right; the index and weight loads of
 // 8 entries are issued before their 8 gathers (arrays in global memory or LDS).
-template <class T, class V>
-__device__ __attribute__((always_inline)) inline T row_seq_p(const T* val, const int* ci, int p0, int len, V v) {
+template <class T, class VP, class IP, class V>
+__device__ __attribute__((always_inline)) inline T row_seq_p(VP val, IP ci, int p0, int len, V v) {
   T s = 0;
   for (int t0 = 0; t0 < len; t0 += 8) {
     int cj[8];
@@ -133,8 +142,8 @@ __device__ __attribute__((always_inline)) inline T row_long(const TailLevel& L, 
 // wavefront, a barrier after each colour class.
 template <class T, bool MV>
 __device__ __attribute__((always_inline)) inline void tail_gs(const TailLevel& L, ColOf<MV> C) {
-  auto x = C(TV<T>::x(L));
-  auto b = C(TV<T>::b(L));
+  auto x = C.v(L, TV<T>::x(L));
+  auto b = C.v(L, TV<T>::b(L));
   const T* dg = TV<T>::diag(L);
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
   for (int c = 0; c < L.ncol; ++c) {
@@ -152,7 +161,8 @@ __device__ __attribute__((always_inline)) inline void tail_gs(const TailLevel& L
 // diagonal, row pointers and colour bounds always; column indices and weights
 // too when they fit.  One bulk load and one write-back replace the global
 // round trips of every colour phase.  Same sums in the same order.
-constexpr int TAIL_LDS = 128 * 1024;
+constexpr int TAIL_LDS = 152 * 1024;  // dynamic LDS of a tail workgroup (of 160 KB per CU)
+constexpr int TAIL_RES = 96 * 1024;   // of which at most this much holds resident levels
 template <class T>
 __device__ inline size_t tail_vec_bytes(const TailLevel& L) {
   return (size_t)L.n * (3 * sizeof(T) + sizeof(int)) + 2 * sizeof(int) + (size_t)(2 * L.ncol + 2) * sizeof(int);
@@ -165,42 +175,21 @@ template <class T>
 __device__ inline bool tail_fits_all(const TailLevel& L, int budget) {
   return tail_vec_bytes<T>(L) + (size_t)L.nnz * (sizeof(T) + sizeof(int)) + 16 <= (size_t)budget;
 }
-template <class T, bool MV>
-__device__ __attribute__((always_inline)) inline void tail_gs_lds(const TailLevel& L, ColOf<MV> C, char* lds,
-                                                                  int budget, int sweeps) {
-  auto x = C(TV<T>::x(L));
-  auto b = C(TV<T>::b(L));
-  const T* dg = TV<T>::diag(L);
-  const int n = L.n, nc = L.ncol;
-  T* sx = (T*)lds;
-  T* sbv = sx + n;
-  T* sd = sbv + n;
-  int* srp = (int*)(sd + n);
-  int* scp = srp + n + 1;
-  int* slp = scp + nc + 1;
-  const bool all = tail_fits_all<T>(L, budget);
-  // 16-byte aligned start for the matrix entries
-  char* mend = (char*)(slp + nc + 1);
-  T* sval = (T*)(((size_t)mend + 15) & ~(size_t)15);
-  int* sci = (int*)(sval + (all ? L.nnz : 0));
-  const T* val = all ? (const T*)sval : TV<T>::val(L);
-  const int* ci = all ? (const int*)sci : L.ci;
+// Sweeps over a level staged in LDS: x, b, diagonal, row pointers, colour
+// and long-row bounds in LDS; weights and column indices in LDS or global.
+template <class T, class VP, class IP>
+__device__ __attribute__((always_inline)) inline void lds_sweeps(const TailLevel& L, int sweeps, LP<T> sx, LP<T> sbv,
+                                                                 LP<T> sd, LP<int> srp, LP<int> scp, LP<int> slp,
+                                                                 VP val, IP ci) {
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
-  for (int i = tid; i < n; i += TAIL_THREADS) { sx[i] = x[i]; sbv[i] = b[i]; sd[i] = dg[i]; srp[i] = L.rp[i]; }
-  for (int i = tid; i <= nc; i += TAIL_THREADS) { scp[i] = L.cptr[i]; slp[i] = L.lptr[i]; }
-  if (tid == 0) srp[n] = L.rp[n];
-  if (all) {
-    const T* gv = TV<T>::val(L);
-    for (int i = tid; i < L.nnz; i += TAIL_THREADS) { sval[i] = gv[i]; sci[i] = L.ci[i]; }
-  }
-  __syncthreads();
+  const int nc = L.ncol;
   for (int sw = 0; sw < sweeps; ++sw)
     for (int c = 0; c < nc; ++c) {
       const int c1 = scp[c + 1];
       for (int u = scp[c] + tid; u < c1; u += TAIL_THREADS) {
         const int p0 = srp[u], len = srp[u + 1] - p0;
         if (len > SHORT_ROW) continue;
-        sx[u] = (sbv[u] + row_seq_p<T>(val, ci, p0, len, (const T*)sx)) / sd[u];
+        sx[u] = (sbv[u] + row_seq_p<T>(val, ci, p0, len, sx)) / sd[u];
       }
       for (int k = slp[c] + wv; k < slp[c + 1]; k += TAIL_WAVES) {
         const int u = L.lrows[k];
@@ -210,12 +199,121 @@ __device__ __attribute__((always_inline)) inline void tail_gs_lds(const TailLeve
       }
       __syncthreads();
     }
+}
+template <class T, bool MV>
+__device__ __attribute__((always_inline)) inline void tail_gs_lds(const TailLevel& L, ColOf<MV> C, char* lds,
+                                                                  int budget, int sweeps) {
+  auto x = C.v(L, TV<T>::x(L));
+  auto b = C.v(L, TV<T>::b(L));
+  const T* dg = TV<T>::diag(L);
+  const int n = L.n, nc = L.ncol;
+  LP<T> sx = (LP<T>)lds;
+  LP<T> sbv = sx + n;
+  LP<T> sd = sbv + n;
+  LP<int> srp = (LP<int>)(sd + n);
+  LP<int> scp = srp + n + 1;
+  LP<int> slp = scp + nc + 1;
+  const bool all = tail_fits_all<T>(L, budget);
+  // 16-byte aligned start for the matrix entries
+  const unsigned mend = (unsigned)(size_t)(slp + nc + 1);
+  LP<T> sval = (LP<T>)(size_t)((mend + 15u) & ~15u);
+  LP<int> sci = (LP<int>)(sval + (all ? L.nnz : 0));
+  const int tid = threadIdx.x;
+  for (int i = tid; i < n; i += TAIL_THREADS) { sx[i] = x[i]; sbv[i] = b[i]; sd[i] = dg[i]; srp[i] = L.rp[i]; }
+  for (int i = tid; i <= nc; i += TAIL_THREADS) { scp[i] = L.cptr[i]; slp[i] = L.lptr[i]; }
+  if (tid == 0) srp[n] = L.rp[n];
+  if (all) {
+    const T* gv = TV<T>::val(L);
+    for (int i = tid; i < L.nnz; i += TAIL_THREADS) { sval[i] = gv[i]; sci[i] = L.ci[i]; }
+  }
+  __syncthreads();
+  if (all) lds_sweeps<T>(L, sweeps, sx, sbv, sd, srp, scp, slp, sval, sci);
+  else lds_sweeps<T>(L, sweeps, sx, sbv, sd, srp, scp, slp, TV<T>::val(L), L.ci);
   for (int i = tid; i < n; i += TAIL_THREADS) x[i] = sx[i];
 }
+// Sweeps of a small level (n <= R * TAIL_THREADS rows): thread t owns rows
+// t, t + TAIL_THREADS, ... for the whole op.  Each row's colour, first RMAX
+// weights and column indices, b and diagonal stay in registers and x lives
+// in LDS, so a colour phase is one round of LDS gathers before the barrier.
+// The sums run left to right as in every other relaxation path; entries past
+// RMAX come from global memory, long rows (> 64) from the wavefront path.
+template <class T, bool MV, int R>
+__device__ __attribute__((always_inline)) inline void tail_gs_small(const TailLevel& L, ColOf<MV> C, char* lds,
+                                                                    int sweeps) {
+  constexpr int RMAX = 8;
+  auto x = C.v(L, TV<T>::x(L));
+  auto b = C.v(L, TV<T>::b(L));
+  const T* dg = TV<T>::diag(L);
+  const T* val = TV<T>::val(L);
+  const int n = L.n, nc = L.ncol;
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+  LP<T> sx = (LP<T>)lds;
+  int col[R], p0[R], len[R], cj[R][RMAX];
+  T bu[R], du[R], wj[R][RMAX];
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    const int u = tid + k * TAIL_THREADS;
+    col[k] = -1;
+    len[k] = 0;
+    p0[k] = 0;
+    bu[k] = T(0);
+    du[k] = T(1);
+    if (u < n) {
+      sx[u] = x[u];
+      bu[k] = b[u];
+      du[k] = dg[u];
+      p0[k] = L.rp[u];
+      len[k] = L.rp[u + 1] - p0[k];
+      for (int c = 0; c < nc; ++c)
+        if (u >= L.cptr[c] && u < L.cptr[c + 1]) col[k] = c;
+      if (len[k] > SHORT_ROW) col[k] = -1;  // long rows: wavefront path below
+    }
+#pragma unroll
+    for (int q = 0; q < RMAX; ++q) {
+      const bool in = q < len[k];
+      cj[k][q] = in ? L.ci[p0[k] + q] : 0;
+      wj[k][q] = in ? val[p0[k] + q] : T(0);
+    }
+  }
+  __syncthreads();
+  for (int sw = 0; sw < sweeps; ++sw)
+    for (int c = 0; c < nc; ++c) {
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        if (col[k] != c) continue;
+        T xg[RMAX];
+#pragma unroll
+        for (int q = 0; q < RMAX; ++q) xg[q] = sx[cj[k][q]];
+        T s = 0;
+#pragma unroll
+        for (int q = 0; q < RMAX; ++q)
+          if (q < len[k]) s += wj[k][q] * xg[q];
+        for (int t = RMAX; t < len[k]; ++t) s += val[p0[k] + t] * sx[L.ci[p0[k] + t]];
+        sx[tid + k * TAIL_THREADS] = (bu[k] + s) / du[k];
+      }
+      for (int k = L.lptr[c] + wv; k < L.lptr[c + 1]; k += TAIL_WAVES) {
+        const int u = L.lrows[k];
+        const int q0 = L.rp[u], ln = L.rp[u + 1] - q0;
+        const T s = dev::row_sum_wave<T>(ln, lane, [&](int t) { return val[q0 + t] * sx[L.ci[q0 + t]]; });
+        if (lane == 0) sx[u] = (b[u] + s) / dg[u];
+      }
+      __syncthreads();
+    }
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    const int u = tid + k * TAIL_THREADS;
+    if (u < n) x[u] = sx[u];
+  }
+}
+
 template <class T, bool MV>
 __device__ __attribute__((always_inline)) inline void tail_sweeps(const TailLevel& L, ColOf<MV> C, char* lds,
                                                                   int budget, int sweeps) {
-  if (tail_fits<T>(L, budget)) {
+  if (L.n <= TAIL_THREADS && (size_t)L.n * sizeof(T) <= (size_t)budget) {
+    tail_gs_small<T, MV, 1>(L, C, lds, sweeps);
+  } else if (L.n <= 2 * TAIL_THREADS && (size_t)L.n * sizeof(T) <= (size_t)budget) {
+    tail_gs_small<T, MV, 2>(L, C, lds, sweeps);
+  } else if (tail_fits<T>(L, budget)) {
     tail_gs_lds<T, MV>(L, C, lds, budget, sweeps);
   } else {
     for (int sw = 0; sw < sweeps; ++sw) tail_gs<T, MV>(L, C);
@@ -224,8 +322,8 @@ __device__ __attribute__((always_inline)) inline void tail_sweeps(const TailLeve
 
 template <class T, bool MV>
 __device__ __attribute__((always_inline)) inline void tail_res(const TailLevel& L, ColOf<MV> C, Col<T, MV> out) {
-  auto x = C(TV<T>::x(L));
-  auto b = C(TV<T>::b(L));
+  auto x = C.v(L, TV<T>::x(L));
+  auto b = C.v(L, TV<T>::b(L));
   const T* dg = TV<T>::diag(L);
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
   for (int u = tid; u < L.n; u += TAIL_THREADS)
@@ -262,31 +360,34 @@ __device__ inline void block_sums(double (&v)[NV], double (*sh)[TAIL_WAVES]) {
 // side); sh: reduction scratch.  Multi-vector form: column C.j of every block
 // (stride P.kc), each column with its own recombination coefficients and mean.
 template <class T, bool MV>
-__device__ void run_ops(const TailParams& P, const int4* __restrict__ prog, int nops, char* lds,
-                        double (*sh)[TAIL_WAVES], ColOf<MV> C) {
-  double* sb = (double*)lds;
+__device__ __attribute__((always_inline)) inline void run_ops(const TailParams& P, const TailLevel* Ls,
+                                                              const int4* __restrict__ prog, int nops, char* lds,
+                                                              int budget, double (*sh)[TAIL_WAVES], ColOf<MV> C) {
+  LP<double> sb = (LP<double>)lds;
   const int tid = threadIdx.x;
+  const TailParams PP = P;  // one read of the parameters, not one per op
+  const int4* pg = prog;
   for (int i = 0; i < nops; ++i) {
-    const int4 op = prog[i];
-    const TailLevel& L = P.L[op.y - P.lc];
+    const int4 op = pg[i];
+    const TailLevel& L = Ls[op.y - PP.lc];
     switch (op.x) {
       case OP_GS:
-        tail_sweeps<T, MV>(L, C, lds, P.lds_bytes, 1);
+        tail_sweeps<T, MV>(L, C, lds, budget, op.z);
         break;
       case OP_RES:
-        tail_res<T, MV>(L, C, C(op.z == 0 ? TV<T>::r(L) : TV<T>::R(L, op.z - 1)));
+        tail_res<T, MV>(L, C, C.v(L, op.z == 0 ? TV<T>::r(L) : TV<T>::R(L, op.z - 1)));
         break;
       case OP_SAVEX: {
-        auto x = C(TV<T>::x(L));
-        auto X = C(TV<T>::X(L, op.z));
+        auto x = C.v(L, TV<T>::x(L));
+        auto X = C.v(L, TV<T>::X(L, op.z));
         for (int u = tid; u < L.n; u += TAIL_THREADS) X[u] = x[u];
         break;
       }
       case OP_RAGG: {
-        const TailLevel& Lc = P.L[op.y + 1 - P.lc];
-        auto src = C(op.z == 0 ? TV<T>::r(L) : TV<T>::R(L, op.z - 1));
-        auto bc = C(TV<T>::b(Lc));
-        const T mu = op.w ? (T)P.mu : T(1);
+        const TailLevel& Lc = Ls[op.y + 1 - PP.lc];
+        auto src = C.v(L, op.z == 0 ? TV<T>::r(L) : TV<T>::R(L, op.z - 1));
+        auto bc = C.v(Lc, TV<T>::b(Lc));
+        const T mu = op.w ? (T)PP.mu : T(1);
         for (int U = tid; U < L.nc; U += TAIL_THREADS) {
           T s = 0;
           for (int j = L.agg_ptr[U]; j < L.agg_ptr[U + 1]; ++j) s += src[L.members[j]];
@@ -297,16 +398,16 @@ __device__ void run_ops(const TailParams& P, const int4* __restrict__ prog, int 
       case OP_RRAGG: {
         // one thread per aggregate: residuals of its members (rows summed left
         // to right), saved iterate, restricted sum, zeroed coarse iterate
-        const TailLevel& Lc = P.L[op.y + 1 - P.lc];
-        auto dst = C(op.z == 0 ? TV<T>::r(L) : TV<T>::R(L, op.z - 1));
+        const TailLevel& Lc = Ls[op.y + 1 - PP.lc];
+        auto dst = C.v(L, op.z == 0 ? TV<T>::r(L) : TV<T>::R(L, op.z - 1));
         const bool save = op.z != 0;
-        auto Xs = C(save ? TV<T>::X(L, op.z - 1) : TV<T>::x(L));
-        auto x = C(TV<T>::x(L));
-        auto b = C(TV<T>::b(L));
+        auto Xs = C.v(L, save ? TV<T>::X(L, op.z - 1) : TV<T>::x(L));
+        auto x = C.v(L, TV<T>::x(L));
+        auto b = C.v(L, TV<T>::b(L));
         const T* dg = TV<T>::diag(L);
-        auto bc = C(TV<T>::b(Lc));
-        auto xc = C(TV<T>::x(Lc));
-        const T mu = op.w ? (T)P.mu : T(1);
+        auto bc = C.v(Lc, TV<T>::b(Lc));
+        auto xc = C.v(Lc, TV<T>::x(Lc));
+        const T mu = op.w ? (T)PP.mu : T(1);
         for (int U = tid; U < L.nc; U += TAIL_THREADS) {
           T s = 0;
           for (int j = L.agg_ptr[U]; j < L.agg_ptr[U + 1]; ++j) {
@@ -324,22 +425,22 @@ __device__ void run_ops(const TailParams& P, const int4* __restrict__ prog, int 
         break;
       }
       case OP_ZERO: {
-        auto x = C(TV<T>::x(L));
+        auto x = C.v(L, TV<T>::x(L));
         for (int u = tid; u < L.n; u += TAIL_THREADS) x[u] = T(0);
         break;
       }
       case OP_IAGG: {
-        const TailLevel& Lc = P.L[op.y + 1 - P.lc];
-        auto e = C(TV<T>::x(Lc));
-        auto x = C(TV<T>::x(L));
+        const TailLevel& Lc = Ls[op.y + 1 - PP.lc];
+        auto e = C.v(Lc, TV<T>::x(Lc));
+        auto x = C.v(L, TV<T>::x(L));
         for (int u = tid; u < L.n; u += TAIL_THREADS) x[u] += e[L.agg[u]];
         break;
       }
       case OP_RELIM: {
-        const TailLevel& Lc = P.L[op.y + 1 - P.lc];
-        auto r = C(TV<T>::r(L));
+        const TailLevel& Lc = Ls[op.y + 1 - PP.lc];
+        auto r = C.v(L, TV<T>::r(L));
         const T* er = TV<T>::er(L);
-        auto bc = C(TV<T>::b(Lc));
+        auto bc = C.v(Lc, TV<T>::b(Lc));
         for (int c = tid; c < L.nc; c += TAIL_THREADS) {
           T s = 0;
           for (int j = L.er_rp[c]; j < L.er_rp[c + 1]; ++j) s += er[j] * r[L.er_ci[j]];
@@ -348,12 +449,12 @@ __device__ void run_ops(const TailParams& P, const int4* __restrict__ prog, int 
         break;
       }
       case OP_IELIM: {
-        const TailLevel& Lc = P.L[op.y + 1 - P.lc];
-        auto e = C(TV<T>::x(Lc));
-        auto r = C(TV<T>::r(L));
+        const TailLevel& Lc = Ls[op.y + 1 - PP.lc];
+        auto e = C.v(Lc, TV<T>::x(Lc));
+        auto r = C.v(L, TV<T>::r(L));
         const T* val = TV<T>::val(L);
         const T* dg = TV<T>::diag(L);
-        auto x = C(TV<T>::x(L));
+        auto x = C.v(L, TV<T>::x(L));
         for (int u = tid; u < L.n; u += TAIL_THREADS) {
           const int c = L.cidx[u];
           if (c >= 0) { x[u] += e[c]; continue; }
@@ -365,11 +466,11 @@ __device__ void run_ops(const TailParams& P, const int4* __restrict__ prog, int 
       }
       case OP_RECOMB: {
         const int th = op.z;
-        auto r = C(TV<T>::r(L));
+        auto r = C.v(L, TV<T>::r(L));
         tail_res<T, MV>(L, C, r);
         __syncthreads();
-        auto R0 = C(TV<T>::R(L, 0));
-        auto R1 = C(TV<T>::R(L, 1));
+        auto R0 = C.v(L, TV<T>::R(L, 0));
+        auto R1 = C.v(L, TV<T>::R(L, 1));
         double v[6] = {0, 0, 0, 0, 0, 0};
         for (int u = tid; u < L.n; u += TAIL_THREADS) {
           const double ru = (double)r[u];
@@ -394,9 +495,9 @@ __device__ void run_ops(const TailParams& P, const int4* __restrict__ prog, int 
             if (G11 > tiny) a1 = -g1 / G11;
           }
         }
-        auto x = C(TV<T>::x(L));
-        auto X0 = C(TV<T>::X(L, 0));
-        auto X1 = C(TV<T>::X(L, 1));
+        auto x = C.v(L, TV<T>::x(L));
+        auto X0 = C.v(L, TV<T>::X(L, 0));
+        auto X1 = C.v(L, TV<T>::X(L, 1));
         for (int u = tid; u < L.n; u += TAIL_THREADS) {
           const double xu = (double)x[u];
           double y = xu;
@@ -407,27 +508,38 @@ __device__ void run_ops(const TailParams& P, const int4* __restrict__ prog, int 
         break;
       }
       case OP_COARSE: {
-        if (P.crelax) {
-          tail_sweeps<T, MV>(L, C, lds, P.lds_bytes, P.csweeps);
+        if (PP.crelax) {
+          tail_sweeps<T, MV>(L, C, lds, budget, PP.csweeps);
           break;
         }
-        // x = M^-1 b: one wavefront per row, coalesced row loads
-        auto b = C(TV<T>::b(L));
-        auto x = C(TV<T>::x(L));
-        for (int j = tid; j < P.nL; j += TAIL_THREADS) sb[j] = (double)b[j];
-        __syncthreads();
+        // x = M^-1 b: one wavefront per row, coalesced row loads; b staged
+        // in LDS unless it already sits there or does not fit
+        auto b = C.v(L, TV<T>::b(L));
+        auto x = C.v(L, TV<T>::x(L));
         const int wv = tid >> 6, lane = tid & 63;
-        for (int r = wv; r < P.nL; r += TAIL_WAVES) {
-          const double* row = P.Minv + (size_t)r * P.nL;
+        if (L.vres || (size_t)PP.nL * sizeof(double) > (size_t)budget) {
+          for (int r = wv; r < PP.nL; r += TAIL_WAVES) {
+            const double* row = PP.Minv + (size_t)r * PP.nL;
+            double s = 0;
+            for (int j = lane; j < PP.nL; j += 64) s += row[j] * (double)b[j];
+            s = dev::wave_fold(s);
+            if (lane == 0) x[r] = (T)s;
+          }
+          break;
+        }
+        for (int j = tid; j < PP.nL; j += TAIL_THREADS) sb[j] = (double)b[j];
+        __syncthreads();
+        for (int r = wv; r < PP.nL; r += TAIL_WAVES) {
+          const double* row = PP.Minv + (size_t)r * PP.nL;
           double s = 0;
-          for (int j = lane; j < P.nL; j += 64) s += row[j] * sb[j];
+          for (int j = lane; j < PP.nL; j += 64) s += row[j] * sb[j];
           s = dev::wave_fold(s);
           if (lane == 0) x[r] = (T)s;
         }
         break;
       }
       case OP_MEAN: {
-        auto x = C(TV<T>::x(L));
+        auto x = C.v(L, TV<T>::x(L));
         double v[1] = {0};
         for (int u = tid; u < L.n; u += TAIL_THREADS) v[0] += (double)x[u];
         block_sums<1>(v, sh);
@@ -442,11 +554,172 @@ __device__ void run_ops(const TailParams& P, const int4* __restrict__ prog, int 
   }
 }
 
+// The interpreter is entered through a call (once per launch, so the call
+// costs nothing).  Force-inlining the whole interpreter into the FP32 tail
+// kernel gave wrong FP32 cycles on the GPU (the same code called this way, and
+// the FP64 kernel either way, were right); the cause was not found.
+// ---------------------------------------------------------- LDS residency
+// At the start of a program the level descriptors are copied into LDS and
+// the largest suffix of (coarsest) levels whose arrays fit P.res_bytes is
+// copied there too: CSR, diagonal, colour and long-row lists, the transfer
+// into the next level and all work vectors of the precision T.  Those levels'
+// ops then touch no global memory.  Vectors of the levels below the entry
+// level are produced inside the program, so only the entry level's x and b are
+// loaded, and its x written back at the end.  Every thread computes the same
+// plan; one thread rewrites a descriptor after all threads have read it.
+__device__ inline size_t al16(size_t b) { return (b + 15) & ~(size_t)15; }
+
+template <class T>
+__device__ inline size_t res_footprint(const TailLevel& L) {
+  const size_t n = L.n, nz = L.nnz, nc = L.nc;
+  size_t s = al16((n + 1) * 4) + al16(nz * 4) + al16(nz * sizeof(T)) + al16(n * sizeof(T)) +
+             2 * al16((L.ncol + 1) * 4) + al16((size_t)(L.nlong > 0 ? L.nlong : 1) * 4);
+  if (L.agg) s += al16(n * 4) + al16((nc + 1) * 4) + al16(n * 4);
+  if (L.cidx) {
+    const size_t ne = L.nner;
+    s += al16(n * 4) + al16(nc * 4) + al16((nc + 1) * 4) + al16(ne * 4) + al16(ne * sizeof(T));
+  }
+  return s + 7 * al16(n * sizeof(T));
+}
+
+// Copies count elements src -> LDS at cur (all threads), returns the copy.
+template <class U>
+__device__ inline U* lds_put(char*& cur, const U* src, size_t count) {
+  U* dst = (U*)cur;
+  if (src)
+    for (size_t i = threadIdx.x; i < count; i += TAIL_THREADS) dst[i] = src[i];
+  cur += al16(count * sizeof(U));
+  return dst;
+}
+template <class U>
+__device__ inline U* lds_take(char*& cur, size_t count) {
+  U* dst = (U*)cur;
+  cur += al16(count * sizeof(U));
+  return dst;
+}
+
+template <class T> struct TSet;
+template <> struct TSet<double> {
+  __device__ static void mats(TailLevel& L, const double* v, const double* d, const double* e) {
+    L.val64 = v; L.diag64 = d; L.er64 = e;
+  }
+  __device__ static void vecs(TailLevel& L, double* const (&w)[7]) {
+    L.x64 = w[0]; L.b64 = w[1]; L.r64 = w[2]; L.X64[0] = w[3]; L.X64[1] = w[4]; L.R64[0] = w[5]; L.R64[1] = w[6];
+  }
+};
+template <> struct TSet<float> {
+  __device__ static void mats(TailLevel& L, const float* v, const float* d, const float* e) {
+    L.val32 = v; L.diag32 = d; L.er32 = e;
+  }
+  __device__ static void vecs(TailLevel& L, float* const (&w)[7]) {
+    L.x32 = w[0]; L.b32 = w[1]; L.r32 = w[2]; L.X32[0] = w[3]; L.X32[1] = w[4]; L.R32[0] = w[5]; L.R32[1] = w[6];
+  }
+};
+
+template <class T, bool MV>
+__device__ __attribute__((always_inline)) inline void run_resident(const TailParams& P, const int4* prog, int nops,
+                                                                   char* lds, double (*sh)[TAIL_WAVES]) {
+  const int tid = threadIdx.x;
+  const ColOf<MV> C{MV ? (int)blockIdx.x : 0, MV ? P.kc : 1};
+  const int nlev = P.nlev;
+  TailLevel* dl = (TailLevel*)lds;
+  {
+    const unsigned long long* src = (const unsigned long long*)P.L;
+    unsigned long long* dst = (unsigned long long*)dl;
+    const int words = nlev * (int)(sizeof(TailLevel) / 8);
+    for (int w = tid; w < words; w += TAIL_THREADS) dst[w] = src[w];
+  }
+  __syncthreads();
+  char* cur = lds + al16((size_t)nlev * sizeof(TailLevel));
+  int rfrom = nlev;
+  {
+    // a level joins only while the LDS left over still stages the vectors
+    // of every level above the resident ones that relaxes (a level followed
+    // by an elimination level has no sweeps)
+    const size_t free0 = (size_t)P.lds_bytes - al16((size_t)nlev * sizeof(TailLevel));
+    size_t tot = 0;
+    for (int i = nlev - 1; i >= 0; --i) {
+      const size_t b = res_footprint<T>(dl[i]);
+      size_t stage = 0;
+      for (int a = 0; a < i; ++a)
+        if (!dl[a].cidx) stage = max(stage, tail_vec_bytes<T>(dl[a]) + 64);
+      if (tot + b > (size_t)P.res_bytes || tot + b + stage > free0) break;
+      tot += b;
+      rfrom = i;
+    }
+  }
+  T* x0 = nullptr;  // the entry level's x in global memory (written back at the end)
+  for (int i = rfrom; i < nlev; ++i) {
+    const TailLevel o = dl[i];
+    __syncthreads();  // every thread holds the original pointers
+    const size_t n = o.n, nz = o.nnz, nc = o.nc;
+    TailLevel& L = dl[i];
+    const int* rp = lds_put(cur, o.rp, n + 1);
+    const int* ci = lds_put(cur, o.ci, nz);
+    const T* val = lds_put(cur, TV<T>::val(o), nz);
+    const T* dg = lds_put(cur, TV<T>::diag(o), n);
+    const int* cp = lds_put(cur, o.cptr, (size_t)o.ncol + 1);
+    const int* lp = lds_put(cur, o.lptr, (size_t)o.ncol + 1);
+    const int* lr = lds_put(cur, o.lrows, (size_t)(o.nlong > 0 ? o.nlong : 1));
+    const int *ag = nullptr, *agp = nullptr, *mem = nullptr, *cx = nullptr, *cf = nullptr, *erp = nullptr,
+              *eci = nullptr;
+    const T* er = nullptr;
+    if (o.agg) {
+      ag = lds_put(cur, o.agg, n);
+      agp = lds_put(cur, o.agg_ptr, nc + 1);
+      mem = lds_put(cur, o.members, n);
+    }
+    if (o.cidx) {
+      cx = lds_put(cur, o.cidx, n);
+      cf = lds_put(cur, o.cfine, nc);
+      erp = lds_put(cur, o.er_rp, nc + 1);
+      eci = lds_put(cur, o.er_ci, (size_t)o.nner);
+      er = lds_put(cur, TV<T>::er(o), (size_t)o.nner);
+    }
+    T* w[7];
+#pragma unroll
+    for (int q = 0; q < 7; ++q) w[q] = lds_take<T>(cur, n);
+    if (i == 0) {
+      // the entry level: its right-hand side and iterate come from outside
+      x0 = TV<T>::x(o);
+      auto gx = C.v(o, TV<T>::x(o));
+      auto gb = C.v(o, TV<T>::b(o));
+      for (size_t k = tid; k < n; k += TAIL_THREADS) {
+        w[0][k] = gx[(int)k];
+        w[1][k] = gb[(int)k];
+      }
+    }
+    if (tid == 0) {
+      L.rp = rp; L.ci = ci; L.cptr = cp; L.lptr = lp; L.lrows = lr;
+      L.agg = ag; L.agg_ptr = agp; L.members = mem;
+      L.cidx = cx; L.cfine = cf; L.er_rp = erp; L.er_ci = eci;
+      TSet<T>::mats(L, val, dg, er);
+      TSet<T>::vecs(L, w);
+      L.vres = 1;
+    }
+  }
+  __syncthreads();
+  const int budget = P.lds_bytes - (int)(cur - lds);
+  run_ops<T, MV>(P, dl, prog, nops, cur, budget, sh, C);
+  if (rfrom == 0) {
+    // write the entry level's iterate back (the caller interpolates from it)
+    const Col<T, MV> gx{MV ? x0 + C.j : x0, C.k};
+    const T* sx = TV<T>::x(dl[0]);
+    for (int k = tid; k < dl[0].n; k += TAIL_THREADS) gx[k] = sx[k];
+    __syncthreads();
+  }
+}
+
+template <class T, bool MV>
+__device__ __attribute__((noinline)) void run_program(const TailParams& P, const int4* prog, int nops, char* lds,
+                                                      double (*sh)[TAIL_WAVES]) {
+  run_resident<T, MV>(P, prog, nops, lds, sh);
+}
 template <class T, bool MV>
 __global__ __launch_bounds__(TAIL_THREADS) void k_tail(TailParams P, const int4* __restrict__ prog, int nops) {
   __shared__ double sh[6][TAIL_WAVES];
   extern __shared__ double lds_d[];
-  run_ops<T, MV>(P, prog, nops, (char*)lds_d, sh, ColOf<MV>{MV ? (int)blockIdx.x : 0, MV ? P.kc : 1});
+  run_program<T, MV>(P, prog, nops, (char*)lds_d, sh);
 }
 
 // ------------------------------------------------------ program generation
@@ -474,7 +747,7 @@ struct Gen {
       return;
     }
     const bool rec = H->o.ec == LAMG_EC_RECOMBINE;
-    for (int i = 0; i < H->o.nu_pre; ++i) op(OP_GS, l);
+    if (H->o.nu_pre > 0) op(OP_GS, l, H->o.nu_pre);
     const int src = rec ? 1 + sub : 0;
     op(OP_RRAGG, l, src, rec ? 0 : 1);
     const int64_t c = count[l]++;
@@ -482,7 +755,7 @@ struct Gen {
     const int th = (int)(std::ceil((double)(c + 1) * gl) - std::ceil((double)c * gl));
     visit(l + 1, th);
     op(OP_IAGG, l);
-    for (int i = 0; i < H->o.nu_post; ++i) op(OP_GS, l);
+    if (H->o.nu_post > 0) op(OP_GS, l, H->o.nu_post);
   }
 };
 
@@ -532,6 +805,8 @@ std::vector<TailLevel> build_desc(Hierarchy* H, int lc) {
     TailLevel& t = d[l - lc];
     std::memset(&t, 0, sizeof(t));
     t.n = L.n; t.nnz = L.nnz; t.ncol = L.ncol; t.nc = l + 1 < nl ? H->lv[l + 1].n : 0;
+    t.nlong = (int)L.long_rows.size();
+    t.nner = l + 1 < nl && H->lv[l + 1].type == LT_ELIM ? (int)H->lv[l + 1].er_tiles.nnz : 0;
     t.rp = L.rp; t.ci = L.ci; t.val64 = L.val; t.diag64 = L.diag; t.val32 = L.val32; t.diag32 = L.diag32;
     t.cptr = L.d_cptr; t.lptr = L.d_lptr; t.lrows = L.d_lrows;
     if (l + 1 < nl) {
@@ -599,6 +874,8 @@ void launch_tail(Hierarchy* H, const void* levels, int kc) {
   // TAIL_LDS covers the coarsest right-hand side too: n_L <= 8192 doubles
   const size_t lds = TAIL_LDS;
   P.lds_bytes = (int)lds;
+  P.res_bytes = TAIL_RES;
+  P.nlev = (int)H->lv.size() - H->tail_lc;
   static bool attr_set = false;
   if (!attr_set) {
     LAMG_HIP(hipFuncSetAttribute((const void*)k_tail<T, MV>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
@@ -680,6 +957,15 @@ struct BatchOut {
   int cycles, status;
 };
 
+// One cycle's op program for a graph of the batch.  Called once per cycle,
+// so the call costs nothing; inlining the interpreter into the batch loop
+// would spill registers in its hot paths.
+template <class T>
+__device__ __attribute__((noinline)) void run_cycle(const TailParams& P, const int4* prog, int nops, char* lds,
+                                                    double (*sh)[TAIL_WAVES]) {
+  run_resident<T, false>(P, prog, nops, lds, sh);
+}
+
 // Fixed-order workgroup sum of f(i) over i < n.
 template <class F>
 __device__ inline double wg_sum(int n, double (*sh)[TAIL_WAVES], F f) {
@@ -689,7 +975,8 @@ __device__ inline double wg_sum(int n, double (*sh)[TAIL_WAVES], F f) {
   return v[0];
 }
 
-__device__ void solve_graph(const BatchGraph& g, BatchOut* out, char* lds, double (*sh)[TAIL_WAVES]) {
+__device__ __attribute__((always_inline)) inline void solve_graph(const BatchGraph& g, BatchOut* out, char* lds,
+                                                                  double (*sh)[TAIL_WAVES]) {
   const int tid = threadIdx.x, n = g.n;
   const TailLevel& L0 = g.P.L[0];
   double* b64 = L0.b64;
@@ -711,7 +998,7 @@ __device__ void solve_graph(const BatchGraph& g, BatchOut* out, char* lds, doubl
   if (nb > 0) {
     while (rk > g.tol * nb && it < g.max_cycles && isfinite(rk)) {
       if (!g.fp32) {
-        run_ops<double, false>(g.P, g.prog, g.nops, lds, sh, C1);
+        run_cycle<double>(g.P, g.prog, g.nops, lds, sh);
       } else {
         float* b32 = L0.b32;
         float* x32 = L0.x32;
@@ -721,7 +1008,7 @@ __device__ void solve_graph(const BatchGraph& g, BatchOut* out, char* lds, doubl
           x32[i] = 0.0f;
         }
         __syncthreads();
-        run_ops<float, false>(g.P, g.prog, g.nops, lds, sh, C1);
+        run_cycle<float>(g.P, g.prog, g.nops, lds, sh);
         for (int i = tid; i < n; i += TAIL_THREADS) x64[i] += (double)x32[i];
         __syncthreads();
         const double mx = wg_sum(n, sh, [&](int i) { return x64[i]; }) / (double)n;
@@ -823,6 +1110,7 @@ lamg_status solve_graphs(int count, Hierarchy* const* hs, const double* const* B
     g.P.csweeps = H->o.coarsest_sweeps;
     g.P.mu = H->o.mu;
     g.P.kc = 1;
+    g.P.nlev = (int)H->lv.size();
     g.prog = H->full_prog;
     g.nops = H->full_nops;
     g.n = H->lv[0].n;
@@ -868,7 +1156,10 @@ lamg_status solve_graphs(int count, Hierarchy* const* hs, const double* const* B
   BatchOut* dout = (BatchOut*)(buf + 2 * gb + 2 * (size_t)count * sizeof(int) + 256);
   for (int v = 0; v < 2; ++v) {
     const int lds = v == 0 ? 128 * 1024 : 64 * 1024;
-    for (BatchGraph& g : G) g.P.lds_bytes = lds;
+    for (BatchGraph& g : G) {
+      g.P.lds_bytes = lds;
+      g.P.res_bytes = lds / 2;
+    }
     LAMG_HIP(hipMemcpyAsync(dG[v], G.data(), gb, hipMemcpyHostToDevice, s));
     LAMG_HIP(hipStreamSynchronize(s));
   }
