@@ -320,14 +320,16 @@ def cpu_baseline(name):
                 "cycles": cyc, "solve_s": dt, "edges": g.m}
     elif name == "graph_batch_256":
         gs = W.graph_batch()[:24]
-        sample = "the first 24 graphs of the batch, FP64 solves to 1e-8 one after another, 1 thread (setup not timed)"
+        sample = ("the first 24 graphs of the batch, 4 right-hand sides each, FP64 solves to 1e-8 one after "
+                  "another, 1 thread (setup not timed)")
         dt, ec = 0.0, 0
         for i, g in enumerate(gs):
             H = O.Hierarchy(g.n, g.eu, g.ev, g.w)
-            t0 = time.perf_counter()
-            x, info, _ = H.solve(W.rhs_normal(g.n, 1, 1000 + i))
-            dt += time.perf_counter() - t0
-            ec += g.m * info["cycles"]
+            for j in range(4):
+                t0 = time.perf_counter()
+                x, info, _ = H.solve(W.rhs_normal(g.n, 1, 1000 + i + 7919 * j))
+                dt += time.perf_counter() - t0
+                ec += g.m * info["cycles"]
         return {"value": ec / dt, "unit": "edges*cycles/s", "cores": 1, "kind": "oracle", "sample": sample,
                 "solve_s": dt}
     else:

@@ -320,19 +320,100 @@ __device__ __attribute__((always_inline)) inline void tail_sweeps(const TailLeve
   }
 }
 
+// Residual rows out_u = (b_u + sum_v w_uv x_v) - a_uu x_u of a level, two
+// rows per thread per pass with both rows' index and weight loads issued
+// before their gathers; x, b, diagonal and row pointers through accessors
+// (LDS copies or global memory).  Rows longer than 64 entries: one wavefront
+// each in the canonical chunk order.  Optionally also writes the residual to
+// an LDS copy rl and the iterate to Xs.
+template <class T, bool MV, class XA, class BA, class DA, class RA>
+__device__ __attribute__((always_inline)) inline void res_rows(const TailLevel& L, XA xa, BA ba, DA da, RA rpa,
+                                                               const T* val, Col<T, MV> out, LP<T> rl, bool use_rl,
+                                                               bool save, Col<T, MV> Xs) {
+  constexpr int Q = 8;
+  const int n = L.n, tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+  for (int u0 = tid; u0 < n; u0 += 2 * TAIL_THREADS) {
+    const int u[2] = {u0, u0 + TAIL_THREADS};
+    int p0[2], len[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      p0[k] = 0;
+      len[k] = 0;
+      if (u[k] < n) {
+        p0[k] = rpa[u[k]];
+        len[k] = rpa[u[k] + 1] - p0[k];
+      }
+    }
+    int cj[2][Q];
+    T wj[2][Q], xg[2][Q];
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const bool in = q < len[k] && len[k] <= SHORT_ROW;
+        cj[k][q] = in ? L.ci[p0[k] + q] : 0;
+        wj[k][q] = in ? val[p0[k] + q] : T(0);
+      }
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+      for (int q = 0; q < Q; ++q) xg[k][q] = xa[cj[k][q]];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      if (u[k] >= n || len[k] > SHORT_ROW) continue;
+      T s = 0;
+#pragma unroll
+      for (int q = 0; q < Q; ++q)
+        if (q < len[k]) s += wj[k][q] * xg[k][q];
+      for (int t = Q; t < len[k]; ++t) s += val[p0[k] + t] * xa[L.ci[p0[k] + t]];
+      const T xu = xa[u[k]];
+      const T r = (ba[u[k]] + s) - da[u[k]] * xu;
+      out[u[k]] = r;
+      if (use_rl) rl[u[k]] = r;
+      if (save) Xs[u[k]] = xu;
+    }
+  }
+  for (int k = wv; k < L.nlong; k += TAIL_WAVES) {
+    const int u = L.lrows[k];
+    const int q0 = rpa[u], ln = rpa[u + 1] - q0;
+    const T s = dev::row_sum_wave<T>(ln, lane, [&](int t) { return val[q0 + t] * xa[L.ci[q0 + t]]; });
+    if (lane == 0) {
+      const T xu = xa[u];
+      const T r = (ba[u] + s) - da[u] * xu;
+      out[u] = r;
+      if (use_rl) rl[u] = r;
+      if (save) Xs[u] = xu;
+    }
+  }
+}
+
+// The residual of a level into out, its x, b, diagonal and row pointers
+// staged in LDS when they fit (and the level does not already sit in LDS).
+// Returns whether an LDS copy of the residual was left at *rl.
 template <class T, bool MV>
-__device__ __attribute__((always_inline)) inline void tail_res(const TailLevel& L, ColOf<MV> C, Col<T, MV> out) {
+__device__ __attribute__((always_inline)) inline bool tail_residual(const TailLevel& L, ColOf<MV> C, char* lds,
+                                                                    int budget, Col<T, MV> out, bool save,
+                                                                    Col<T, MV> Xs, LP<T>* rl) {
   auto x = C.v(L, TV<T>::x(L));
   auto b = C.v(L, TV<T>::b(L));
   const T* dg = TV<T>::diag(L);
-  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
-  for (int u = tid; u < L.n; u += TAIL_THREADS)
-    if (L.rp[u + 1] - L.rp[u] <= SHORT_ROW) out[u] = (b[u] + row_short<T>(L, u, x)) - dg[u] * x[u];
-  for (int k = wv; k < L.lptr[L.ncol]; k += TAIL_WAVES) {
-    const int u = L.lrows[k];
-    const T s = row_long<T>(L, u, x, lane);
-    if (lane == 0) out[u] = (b[u] + s) - dg[u] * x[u];
+  const T* val = TV<T>::val(L);
+  const int n = L.n, tid = threadIdx.x;
+  if (!L.vres && (size_t)n * (4 * sizeof(T) + 4) + 64 <= (size_t)budget) {
+    LP<T> sx = (LP<T>)lds;
+    LP<T> sb = sx + n;
+    LP<T> sd = sb + n;
+    LP<T> sr = sd + n;
+    LP<int> srp = (LP<int>)(sr + n);
+    for (int i = tid; i < n; i += TAIL_THREADS) { sx[i] = x[i]; sb[i] = b[i]; sd[i] = dg[i]; srp[i] = L.rp[i]; }
+    if (tid == 0) srp[n] = L.rp[n];
+    __syncthreads();
+    res_rows<T, MV>(L, sx, sb, sd, srp, val, out, sr, true, save, Xs);
+    *rl = sr;
+    return true;
   }
+  res_rows<T, MV>(L, x, b, dg, L.rp, val, out, (LP<T>)lds, false, save, Xs);
+  return false;
 }
 
 // Fixed-order sum of NV values per thread over the workgroup: a butterfly
@@ -374,9 +455,12 @@ __device__ __attribute__((always_inline)) inline void run_ops(const TailParams& 
       case OP_GS:
         tail_sweeps<T, MV>(L, C, lds, budget, op.z);
         break;
-      case OP_RES:
-        tail_res<T, MV>(L, C, C.v(L, op.z == 0 ? TV<T>::r(L) : TV<T>::R(L, op.z - 1)));
+      case OP_RES: {
+        auto dst = C.v(L, op.z == 0 ? TV<T>::r(L) : TV<T>::R(L, op.z - 1));
+        LP<T> rl;
+        tail_residual<T, MV>(L, C, lds, budget, dst, false, dst, &rl);
         break;
+      }
       case OP_SAVEX: {
         auto x = C.v(L, TV<T>::x(L));
         auto X = C.v(L, TV<T>::X(L, op.z));
@@ -396,29 +480,25 @@ __device__ __attribute__((always_inline)) inline void run_ops(const TailParams& 
         break;
       }
       case OP_RRAGG: {
-        // one thread per aggregate: residuals of its members (rows summed left
-        // to right), saved iterate, restricted sum, zeroed coarse iterate
+        // residual rows (saved iterate alongside), then one thread per
+        // aggregate: restricted sum of its members in ascending order, zeroed
+        // coarse iterate
         const TailLevel& Lc = Ls[op.y + 1 - PP.lc];
         auto dst = C.v(L, op.z == 0 ? TV<T>::r(L) : TV<T>::R(L, op.z - 1));
         const bool save = op.z != 0;
         auto Xs = C.v(L, save ? TV<T>::X(L, op.z - 1) : TV<T>::x(L));
-        auto x = C.v(L, TV<T>::x(L));
-        auto b = C.v(L, TV<T>::b(L));
-        const T* dg = TV<T>::diag(L);
+        LP<T> rl;
+        const bool inl = tail_residual<T, MV>(L, C, lds, budget, dst, save, Xs, &rl);
+        __syncthreads();
         auto bc = C.v(Lc, TV<T>::b(Lc));
         auto xc = C.v(Lc, TV<T>::x(Lc));
         const T mu = op.w ? (T)PP.mu : T(1);
         for (int U = tid; U < L.nc; U += TAIL_THREADS) {
           T s = 0;
-          for (int j = L.agg_ptr[U]; j < L.agg_ptr[U + 1]; ++j) {
-            const int m = L.members[j];
-            const int p0 = L.rp[m];
-            const T xm = x[m];
-            const T rm = (b[m] + row_seq<T>(L, p0, L.rp[m + 1] - p0, x)) - dg[m] * xm;
-            dst[m] = rm;
-            if (save) Xs[m] = xm;
-            s += rm;
-          }
+          if (inl)
+            for (int j = L.agg_ptr[U]; j < L.agg_ptr[U + 1]; ++j) s += rl[L.members[j]];
+          else
+            for (int j = L.agg_ptr[U]; j < L.agg_ptr[U + 1]; ++j) s += dst[L.members[j]];
           bc[U] = mu * s;
           xc[U] = T(0);
         }
@@ -467,7 +547,8 @@ __device__ __attribute__((always_inline)) inline void run_ops(const TailParams& 
       case OP_RECOMB: {
         const int th = op.z;
         auto r = C.v(L, TV<T>::r(L));
-        tail_res<T, MV>(L, C, r);
+        LP<T> rl;
+        tail_residual<T, MV>(L, C, lds, budget, r, false, r, &rl);
         __syncthreads();
         auto R0 = C.v(L, TV<T>::R(L, 0));
         auto R1 = C.v(L, TV<T>::R(L, 1));
@@ -982,7 +1063,6 @@ __device__ __attribute__((always_inline)) inline void solve_graph(const BatchGra
   double* b64 = L0.b64;
   double* x64 = L0.x64;
   double* r64 = g.r64;
-  const ColOf<false> C1{0, 1};
   const double mean = wg_sum(n, sh, [&](int i) { return g.b[i]; }) / (double)n;
   for (int i = tid; i < n; i += TAIL_THREADS) {
     b64[i] = g.b[g.perm[i]] - mean;
@@ -990,7 +1070,8 @@ __device__ __attribute__((always_inline)) inline void solve_graph(const BatchGra
   }
   __syncthreads();
   const double nb = sqrt(wg_sum(n, sh, [&](int i) { return b64[i] * b64[i]; }));
-  tail_res<double, false>(L0, C1, Col<double, false>{r64, 1});
+  res_rows<double, false>(L0, x64, b64, L0.diag64, L0.rp, L0.val64, Col<double, false>{r64, 1}, (LP<double>)lds,
+                          false, false, Col<double, false>{r64, 1});
   __syncthreads();
   const double r0 = sqrt(wg_sum(n, sh, [&](int i) { return r64[i] * r64[i]; }));
   double rk = r0;
@@ -1015,7 +1096,8 @@ __device__ __attribute__((always_inline)) inline void solve_graph(const BatchGra
         for (int i = tid; i < n; i += TAIL_THREADS) x64[i] -= mx;
         __syncthreads();
       }
-      tail_res<double, false>(L0, C1, Col<double, false>{r64, 1});
+      res_rows<double, false>(L0, x64, b64, L0.diag64, L0.rp, L0.val64, Col<double, false>{r64, 1}, (LP<double>)lds,
+                              false, false, Col<double, false>{r64, 1});
       __syncthreads();
       rk = sqrt(wg_sum(n, sh, [&](int i) { return r64[i] * r64[i]; }));
       ++it;

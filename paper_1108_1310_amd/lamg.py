@@ -357,11 +357,13 @@ def colour(rp, ci, n, seed=0, level=0):
     return out
 
 
-KERNELS = {0: "gs_fp64", 1: "residual_fp64", 2: "gs_fp32", 3: "residual_fp32"}
+KERNELS = {0: "gs_fp64", 1: "residual_fp64", 2: "gs_fp32", 3: "residual_fp32",
+           4: "mv_gs_fp64", 5: "mv_residual_fp64", 6: "mv_gs_fp32", 7: "mv_residual_fp32"}
 
 
 def prof_enable(on: bool = True):
-    """Bracket every relaxation / residual launch with HIP events (see lamg_test.h)."""
+    """Time the relaxation / residual kernels with HIP event spans on their
+    stream (whole sweeps; see lamg_test.h)."""
     lib().lamg_t_prof_enable(1 if on else 0)
 
 
