@@ -57,8 +57,8 @@ def copy_calibration(nbytes):
 # --pmc FETCH_SIZE, then WRITE_SIZE, on this benchmark), scaled by the same
 # counters on a plain copy; valid only while the kernel source is unchanged.
 TRAFFIC = {
-    # profiles/gs_fp64_chung_lu_2p20.md: FETCH_SIZE 7416.4 KiB x 1.9999 + WRITE_SIZE 109.1 KiB x 1.0000
-    "chung_lu_2p20": {"bytes_per_launch": 15300025, "kernel_sha": "247d4ced337e59df"},
+    # profiles/gs_fp64_chung_lu_2p20.md: FETCH_SIZE 7417.0 KiB x 1.9999 + WRITE_SIZE 109.0 KiB x 1.0000
+    "chung_lu_2p20": {"bytes_per_launch": 15301206, "kernel_sha": "601b197140d00e38"},
 }
 
 

@@ -46,11 +46,11 @@ constexpr int ROW_CHUNK = 512;
 struct Tiles {
   int64_t rows = 0, nnz = 0;  // rows and entries covered (algorithmic bytes per launch)
   int nstream = 0;
-  int* stream = nullptr;      // [nstream] (first, end) row ranges of stream tiles (device int2)
+  int4* stream = nullptr;     // [nstream] stream tiles: (first row, end row, first entry, entries)
   int nvlong = 0;
-  int* vlong = nullptr;       // very long rows, longest first (device)
+  int4* vlong = nullptr;      // very long rows, longest first: (row, first entry, entries, 0)
   int nmed = 0, nmed_blocks = 0;
-  int* med = nullptr;         // medium rows, longest first (device)
+  int4* med = nullptr;        // medium rows, longest first: (row, first entry, entries, 0)
   int* longrows = nullptr;    // every row longer than SHORT_ROW (device; setup kernels)
   int nlong = 0;
   int blocks() const { return nvlong + nmed_blocks + nstream; }

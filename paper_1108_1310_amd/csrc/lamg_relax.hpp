@@ -55,8 +55,8 @@ template <class T, int MODE>
 __global__ __launch_bounds__(RELAX_THREADS) void k_relax(
     const int* __restrict__ rp, const int* __restrict__ ci, const T* __restrict__ val,
     const T* __restrict__ diag, const T* __restrict__ b, T* x, T* __restrict__ r,
-    const int* __restrict__ vlong, int nvlong, const int* __restrict__ med, int nmed, int nmed_blocks,
-    const int2* __restrict__ sblk, int nstream, const int* __restrict__ map) {
+    const int4* __restrict__ vlong, int nvlong, const int4* __restrict__ med, int nmed, int nmed_blocks,
+    const int4* __restrict__ sblk, int nstream, const int* __restrict__ map) {
   constexpr int PER = TILE_NNZ / RELAX_THREADS;  // entries per thread in a stream tile
   constexpr int MAXC = 64;                       // chunk sums staged per pass
   __shared__ T prod[TILE_NNZ];
@@ -66,8 +66,8 @@ __global__ __launch_bounds__(RELAX_THREADS) void k_relax(
   int bid = blockIdx.x;
   if (bid < nvlong) {
     // a very long row: chunks k = wv, wv+4, ... per pass; chunk sums added in order
-    const int u = vlong[bid];
-    const int p0 = rp[u], len = rp[u + 1] - p0;
+    const int4 e = vlong[bid];  // (row, first entry, entries)
+    const int u = e.x, p0 = e.y, len = e.z;
     const int nch = (len + ROW_CHUNK - 1) / ROW_CHUNK;
     T total = 0;
     for (int pass = 0; pass < nch; pass += MAXC) {
@@ -88,8 +88,8 @@ __global__ __launch_bounds__(RELAX_THREADS) void k_relax(
   if (bid < nmed_blocks) {
     const int idx = bid * LONG_PER_BLOCK + wv;
     if (idx >= nmed) return;
-    const int u = med[idx];
-    const int p0 = rp[u], len = rp[u + 1] - p0;
+    const int4 e = med[idx];
+    const int u = e.x, p0 = e.y, len = e.z;
     const T sk = chunk_sum<T>(ci, val, x, p0, 0, len, lane);
     T total = 0;
     total += sk;
@@ -97,13 +97,12 @@ __global__ __launch_bounds__(RELAX_THREADS) void k_relax(
     return;
   }
   bid -= nmed_blocks;
-  const int2 rr = sblk[bid];
+  const int4 rr = sblk[bid];  // (first row, end row, first entry, entries)
   const int nr = rr.y - rr.x;
+  const int base = rr.z, cnt = rr.w;
+  // the row pointers go to LDS while the index and weight loads are in
+  // flight; then all gathers: PER loads in flight per thread
   for (int i = threadIdx.x; i <= nr; i += RELAX_THREADS) srp[i] = rp[rr.x + i];
-  __syncthreads();
-  const int base = srp[0];
-  const int cnt = srp[nr] - base;
-  // all index and weight loads first, then all gathers: PER loads in flight per thread
   int cj[PER];
   T wj[PER], xj[PER];
 #pragma unroll

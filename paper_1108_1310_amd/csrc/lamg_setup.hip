@@ -466,14 +466,20 @@ static void upload_tiles(Hierarchy* H, Tiles& t, const std::vector<int2>& blocks
   t.nmed = (int)md.size();
   t.nmed_blocks = (t.nmed + LONG_PER_BLOCK - 1) / LONG_PER_BLOCK;
   t.nlong = (int)all.size();
-  t.stream = (int*)dnew<int2>(H, blocks.size());
-  t.vlong = dnew<int>(H, vl.size());
-  t.med = dnew<int>(H, md.size());
+  // work-list entries carry the row extents, so a block starts its entry
+  // loads without first reading the row pointers
+  std::vector<int4> sb(blocks.size()), v4(vl.size()), m4(md.size());
+  for (size_t i = 0; i < blocks.size(); ++i)
+    sb[i] = make_int4(blocks[i].x, blocks[i].y, rph[blocks[i].x], rph[blocks[i].y] - rph[blocks[i].x]);
+  for (size_t i = 0; i < vl.size(); ++i) v4[i] = make_int4(vl[i], rph[vl[i]], rph[vl[i] + 1] - rph[vl[i]], 0);
+  for (size_t i = 0; i < md.size(); ++i) m4[i] = make_int4(md[i], rph[md[i]], rph[md[i] + 1] - rph[md[i]], 0);
+  t.stream = dnew<int4>(H, sb.size());
+  t.vlong = dnew<int4>(H, v4.size());
+  t.med = dnew<int4>(H, m4.size());
   t.longrows = dnew<int>(H, all.size());
-  if (!blocks.empty())
-    LAMG_HIP(hipMemcpyAsync(t.stream, blocks.data(), blocks.size() * sizeof(int2), hipMemcpyHostToDevice, s));
-  if (!vl.empty()) LAMG_HIP(hipMemcpyAsync(t.vlong, vl.data(), vl.size() * sizeof(int), hipMemcpyHostToDevice, s));
-  if (!md.empty()) LAMG_HIP(hipMemcpyAsync(t.med, md.data(), md.size() * sizeof(int), hipMemcpyHostToDevice, s));
+  if (!sb.empty()) LAMG_HIP(hipMemcpyAsync(t.stream, sb.data(), sb.size() * sizeof(int4), hipMemcpyHostToDevice, s));
+  if (!v4.empty()) LAMG_HIP(hipMemcpyAsync(t.vlong, v4.data(), v4.size() * sizeof(int4), hipMemcpyHostToDevice, s));
+  if (!m4.empty()) LAMG_HIP(hipMemcpyAsync(t.med, m4.data(), m4.size() * sizeof(int4), hipMemcpyHostToDevice, s));
   if (!all.empty()) LAMG_HIP(hipMemcpyAsync(t.longrows, all.data(), all.size() * sizeof(int), hipMemcpyHostToDevice, s));
   LAMG_HIP(hipStreamSynchronize(s));
 }

@@ -91,7 +91,7 @@ static void launch_relax(hipStream_t s, const int* rp, const int* ci, const Tile
   if (grid == 0) return;
   if (MODE == 2) {
     hipLaunchKernelGGL((k_relax<T, MODE>), dim3(grid), dim3(RELAX_THREADS), 0, s, rp, ci, val, diag, b, x, r,
-                       t.vlong, t.nvlong, t.med, t.nmed, t.nmed_blocks, (const int2*)t.stream, t.nstream, map);
+                       (const int4*)t.vlong, t.nvlong, (const int4*)t.med, t.nmed, t.nmed_blocks, (const int4*)t.stream, t.nstream, map);
     LAMG_HIP(hipGetLastError());
     return;
   }
@@ -103,7 +103,7 @@ static void launch_relax(hipStream_t s, const int* rp, const int* ci, const Tile
                         3 * t.rows * (int64_t)sizeof(T);
   if (prof) prof_count(kid, bytes);
   hipLaunchKernelGGL((k_relax<T, MODE>), dim3(grid), dim3(RELAX_THREADS), 0, s, rp, ci, val, diag, b, x, r,
-                     t.vlong, t.nvlong, t.med, t.nmed, t.nmed_blocks, (const int2*)t.stream, t.nstream, map);
+                     (const int4*)t.vlong, t.nvlong, (const int4*)t.med, t.nmed, t.nmed_blocks, (const int4*)t.stream, t.nstream, map);
   LAMG_HIP(hipGetLastError());
 }
 

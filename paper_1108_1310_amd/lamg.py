@@ -284,12 +284,18 @@ class LaplacianSolve(torch.autograd.Function):
 
     Backward (the adjoint reuses the hierarchy because A is symmetric):
     lam = A^+ (g - mean g); dL/db = lam; dL/dw_e = -(lam_u - lam_v)(x_u - x_v).
-    The hierarchy is built in forward and kept on the context.
+    The hierarchy is built in forward and kept on the context.  The adjoint
+    solve uses the energy correction `adjoint_ec` (default 1, the flat mu of
+    eq. galerkin2): its right-hand side is typically smooth (a function of x
+    on a node subset), a regime in which residual-minimising recombination
+    can stall on large graphs while the flat correction converges.
     """
 
     @staticmethod
     def forward(ctx, b, w, eu, ev, n, opts=None):
-        H = Hierarchy(int(n), eu, ev, w.detach(), **(opts or {}))
+        opts = dict(opts or {})
+        ctx.adjoint_ec = int(opts.pop("adjoint_ec", EC_FLAT_MU))
+        H = Hierarchy(int(n), eu, ev, w.detach(), **opts)
         x, info = H.solve(b.detach())
         if info["status"] != OK:
             raise LamgError(info["status"], "LaplacianSolve.forward")
@@ -300,6 +306,7 @@ class LaplacianSolve(torch.autograd.Function):
     @staticmethod
     def backward(ctx, g):
         x, eu, ev = ctx.saved_tensors
+        ctx.H.set_solve_options(ec=ctx.adjoint_ec)
         lam, info = ctx.H.solve(g.detach().to(torch.float64))
         if info["status"] != OK:
             raise LamgError(info["status"], "LaplacianSolve.backward")

@@ -10,7 +10,7 @@ if ROOT not in sys.path:
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (runs through the HIP library)")
-    config.addinivalue_line("markers", "slow: larger CPU cases")
+    config.addinivalue_line("markers", "slow: larger cases (full benchmark sizes on the GPU, larger CPU cases)")
 
 
 @pytest.fixture(scope="session")
