@@ -293,6 +293,34 @@ def main_batch(a):
     print(json.dumps(rec), flush=True)
 
 
+def adjoint_step(g, b, steps, warmup):
+    """One gradient evaluation of the differentiable solve: setup on the
+    weights, forward solve, loss = sum of x^2 on the held-out nodes, backward
+    (adjoint solve on the same hierarchy + edge-gradient kernel)."""
+    import torch
+    from paper_1108_1310_amd import lamg, workloads as W
+    _, hold = W.label_split(g.n)
+    d = lambda a, t=torch.float64: torch.tensor(a, dtype=t, device="cuda")
+    eu, ev, bt, ht = d(g.eu, torch.int32), d(g.ev, torch.int32), d(b), torch.tensor(hold, device="cuda")
+
+    def one():
+        wt = d(g.w).requires_grad_(True)
+        x = lamg.laplacian_solve(bt, wt, eu, ev, g.n)
+        (x[ht] ** 2).sum().backward()
+        return wt.grad
+
+    for _ in range(warmup):
+        one()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        gw = one()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"ms_per_gradient": dt * 1e3 / steps, "includes": "setup + forward solve + adjoint solve + edge gradient",
+            "grad_norm": float(torch.linalg.norm(gw))}
+
+
 def cpu_baseline(name):
     """The CPU reference (serial C++) on a bounded sample of the same workload recipe."""
     from oracle import oracle as O
@@ -391,14 +419,20 @@ def main():
         print(f"[bench] fp32+refine {r32['seconds']:.3f}s cycles={r32['cycles']}", file=sys.stderr, flush=True)
 
     p = i64["prof"]
-    achieved = p["bytes"] / (p["ms"] * 1e6) if p["ms"] > 0 else 0.0
+    achieved = p["bytes"] / (p["ms"] * 1e6) if p["ms"] > 0 else None
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic(a.workload),
-                "kernel": "k_relax<double,0> (multicolour GS)",
+                "frac": achieved / HBM_PEAK_GBS if achieved is not None else None,
+                "traffic": recorded_traffic(a.workload),
+                "kernel": "k_relax<double,0> (multicolour GS)" if achieved is not None else
+                          "none: every level runs in the single-workgroup tail (latency-bound)",
                 "avg_launch_us": 1e3 * p["ms"] / max(1, p["launches"]), "launches": p["launches"],
                 "bytes_per_launch": p["bytes"] / max(1, p["launches"]),
                 "kernel_share_of_step": p["ms"] / (i64["seconds"] * 1e3),
                 "instrumented_ms_per_step": i64["seconds"] * 1e3 / a.steps}
+    adj = None
+    if a.workload == "rgg_2p20":
+        adj = adjoint_step(g, b, a.steps, a.warmup)
+        print(f"[bench] gradient {adj['ms_per_gradient']:.1f} ms", file=sys.stderr, flush=True)
     cpu = None
     if not a.no_cpu:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
@@ -424,6 +458,7 @@ def main():
         "rel_residual": r64["rel_residual"],
         "edges_solved_per_s": g.m * a.steps / r64["seconds"],
         "fp32_refine": out32,
+        "adjoint": adj,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

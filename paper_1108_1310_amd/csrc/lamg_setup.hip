@@ -320,41 +320,149 @@ __global__ void k_degrees(int n, const int* __restrict__ rp, int* __restrict__ d
   const int u = blockIdx.x * blockDim.x + threadIdx.x;
   if (u < n) deg[u] = rp[u + 1] - rp[u];
 }
-// One Jones-Plassmann round: a node whose higher-priority neighbours are all
-// coloured takes the smallest colour none of them uses (greedy first fit in
-// priority order).  Colours written in the same round are final, so reading
-// them early gives the same answer.
-__global__ void k_colour_round(int n, const int* __restrict__ rp, const int* __restrict__ ci, const int* __restrict__ deg,
-                               const uint64_t* __restrict__ h, int* col, int* done, int* maxc) {
-  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+// Greedy first fit in priority order as a topological sweep: pending[u]
+// counts u's higher-priority neighbours not yet coloured.  A round colours the
+// ready frontier (pending 0; pairwise non-adjacent, since of two neighbours
+// the lower one waits for the higher), and each frontier node decrements its
+// lower-priority neighbours; those reaching 0 form the next frontier.  A
+// node's colour is the smallest one its higher-priority neighbours do not
+// use, exactly as in the sequential rule.  The sweep takes as many rounds as
+// the longest chain of decreasing priority; on power-law graphs most rounds
+// hold a few hubs, so a node of more than COL_HEAVY entries gets a whole
+// block and the others a wavefront each.
+constexpr int COL_HEAVY = 64;
+constexpr int COL_BLOCK = 1024;
+
+// frontier lists of one round: heavy and light nodes, with their counts at
+// cnt[2 * (r % 3)] and cnt[2 * (r % 3) + 1]
+struct Frontier {
+  int* heavy;
+  int* light;
+};
+
+__device__ inline void col_append(int w, const int* __restrict__ rp, Frontier G, int* __restrict__ gcnt) {
+  if (rp[w + 1] - rp[w] > COL_HEAVY) G.heavy[atomicAdd(&gcnt[0], 1)] = w;
+  else G.light[atomicAdd(&gcnt[1], 1)] = w;
+}
+
+__device__ inline uint64_t wave_or(uint64_t m) {
+  unsigned lo = (unsigned)m, hi = (unsigned)(m >> 32);
+  for (int o = 32; o > 0; o >>= 1) {
+    lo |= __shfl_xor(lo, o, 64);
+    hi |= __shfl_xor(hi, o, 64);
+  }
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__global__ void __launch_bounds__(256) k_pending(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                                 const int* __restrict__ deg, const uint64_t* __restrict__ h,
+                                                 int* __restrict__ pending, Frontier F, int* __restrict__ cnt) {
+  const int lane = threadIdx.x & 63;
+  const int u = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
   if (u >= n) return;
-  if (__hip_atomic_load(&col[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= 0) return;
-  const int p0 = rp[u], p1 = rp[u + 1];
-  for (int base = 0;; base += 64) {
-    uint64_t mask = 0;
-    for (int t = p0; t < p1; ++t) {
-      const int v = ci[t];
-      if (!higher(v, u, deg, h)) continue;
-      const int cv = __hip_atomic_load(&col[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (cv < 0) return;  // not ready this round
+  int c = 0;
+  for (int t = rp[u] + lane; t < rp[u + 1]; t += 64) c += higher(ci[t], u, deg, h) ? 1 : 0;
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+  if (lane == 0) {
+    pending[u] = c;
+    if (c == 0) col_append(u, rp, F, cnt);
+  }
+}
+
+// One pass over u's row by `width` threads (lane k of them): the colours of
+// higher neighbours in [base, base + 64) as a bit mask; on the first pass
+// also the decrements of the lower neighbours.
+__device__ inline uint64_t col_pass(int u, int p0, int p1, int k, int width, int base, bool first,
+                                    const int* __restrict__ rp, const int* __restrict__ ci,
+                                    const int* __restrict__ deg, const uint64_t* __restrict__ h,
+                                    const int* __restrict__ col, int* __restrict__ pending, Frontier G,
+                                    int* __restrict__ gcnt) {
+  uint64_t mask = 0;
+  for (int t = p0 + k; t < p1; t += width) {
+    const int v = ci[t];
+    if (higher(v, u, deg, h)) {
+      const int cv = col[v];
       if (cv >= base && cv < base + 64) mask |= 1ULL << (cv - base);
-    }
-    if (mask != ~0ULL) {
-      const int c = base + __builtin_ctzll(~mask);
-      __hip_atomic_store(&col[u], c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      atomicAdd(done, 1);
-      atomicMax(maxc, c);
-      return;
+    } else if (first && atomicSub(&pending[v], 1) == 1) {
+      col_append(v, rp, G, gcnt);
     }
   }
+  return mask;
+}
+
+// Round r: blocks take the heavy frontier nodes one each, then every
+// wavefront takes light nodes one each.  The counters of the round after
+// next are cleared here: the previous round, which read them, has finished.
+__global__ void __launch_bounds__(COL_BLOCK) k_frontier(Frontier F, Frontier G, int* cnt, int r,
+                                                        int* __restrict__ pending, const int* __restrict__ rp,
+                                                        const int* __restrict__ ci, const int* __restrict__ deg,
+                                                        const uint64_t* __restrict__ h, int* __restrict__ col) {
+  __shared__ uint64_t red[COL_BLOCK / 64];
+  __shared__ int chosen;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (blockIdx.x == 0 && threadIdx.x < 2) cnt[2 * ((r + 2) % 3) + threadIdx.x] = 0;
+  const int nh = cnt[2 * (r % 3)], nl = cnt[2 * (r % 3) + 1];
+  int* gcnt = cnt + 2 * ((r + 1) % 3);
+  for (int i = blockIdx.x; i < nh; i += gridDim.x) {
+    const int u = F.heavy[i];
+    const int p0 = rp[u], p1 = rp[u + 1];
+    int c = -1;
+    for (int base = 0; c < 0; base += 64) {
+      uint64_t m = wave_or(col_pass(u, p0, p1, threadIdx.x, COL_BLOCK, base, base == 0, rp, ci, deg, h, col,
+                                    pending, G, gcnt));
+      if (lane == 0) red[wid] = m;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        uint64_t all = 0;
+        for (int w = 0; w < COL_BLOCK / 64; ++w) all |= red[w];
+        chosen = all != ~0ULL ? base + __builtin_ctzll(~all) : -1;
+      }
+      __syncthreads();
+      c = chosen;
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) col[u] = c;
+  }
+  const int gw = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  const int nw = (int)((gridDim.x * blockDim.x) >> 6);
+  for (int i = gw; i < nl; i += nw) {
+    const int u = F.light[i];
+    const int p0 = rp[u], p1 = rp[u + 1];
+    int c = -1;
+    for (int base = 0; c < 0; base += 64) {
+      const uint64_t m = wave_or(col_pass(u, p0, p1, lane, 64, base, base == 0, rp, ci, deg, h, col, pending, G,
+                                          gcnt));
+      if (m != ~0ULL) c = base + __builtin_ctzll(~m);
+    }
+    if (lane == 0) col[u] = c;
+  }
+}
+
+__global__ void k_max_i(int n, const int* __restrict__ a, int* __restrict__ out) {
+  int m = -1;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) m = max(m, a[i]);
+  for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) atomicMax(out, m);
 }
 __global__ void k_inverse(int n, const int* __restrict__ perm, int* __restrict__ inv) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) inv[perm[i]] = i;
 }
+// Histogram of labels: per-block LDS counters for labels < 1024, global
+// atomics for the rest.
 __global__ void k_count_colours(int n, const int* __restrict__ col, int* __restrict__ cnt) {
+  __shared__ int lc[1024];
+  for (int i = threadIdx.x; i < 1024; i += blockDim.x) lc[i] = 0;
+  __syncthreads();
   const int u = blockIdx.x * blockDim.x + threadIdx.x;
-  if (u < n) atomicAdd(&cnt[col[u]], 1);
+  if (u < n) {
+    const int c = col[u];
+    if (c < 1024) atomicAdd(&lc[c], 1);
+    else atomicAdd(&cnt[c], 1);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 1024; i += blockDim.x)
+    if (lc[i]) atomicAdd(&cnt[i], lc[i]);
 }
 __global__ void k_perm_deg(int n, const int* __restrict__ perm, const int* __restrict__ rp, int* __restrict__ deg,
                            const double* __restrict__ dold, double* __restrict__ dnew_) {
@@ -390,14 +498,28 @@ int colour_greedy(hipStream_t s, int n, const int* rp, const int* ci, uint64_t s
   hipLaunchKernelGGL(k_degrees, grid1(n), dim3(256), 0, s, n, rp, deg);
   hipLaunchKernelGGL(k_prio_hash, grid1(n), dim3(256), 0, s, n, seed, (uint64_t)level, h);
   LAMG_HIP(hipMemsetAsync(col, 0xff, (size_t)n * sizeof(int), s));
-  LAMG_HIP(hipMemsetAsync(ctr, 0, 2 * sizeof(int), s));
-  for (int round = 0;; ++round) {
-    for (int r = 0; r < 4; ++r)
-      hipLaunchKernelGGL(k_colour_round, grid1(n), dim3(256), 0, s, n, rp, ci, deg, h, col, ctr, ctr + 1);
+  LAMG_HIP(hipMemsetAsync(ctr, 0xff, 2 * sizeof(int), s));
+  Frontier fr[2] = {{tmp.get<int>(n), tmp.get<int>(n)}, {tmp.get<int>(n), tmp.get<int>(n)}};
+  int* cnt = tmp.get<int>(6);
+  int* pending = tmp.get<int>(n);
+  LAMG_HIP(hipMemsetAsync(cnt, 0, 6 * sizeof(int), s));
+  hipLaunchKernelGGL(k_pending, dim3((unsigned)(((int64_t)n + 3) / 4)), dim3(256), 0, s, n, rp, ci, deg, h, pending,
+                     fr[0], cnt);
+  // rounds until every node is coloured; the host checks every 16 rounds
+  // (rounds past the last are empty)
+  const int grid = std::max(1, std::min(256, (n + 15) / 16));
+  int r = 0;
+  for (;;) {
+    for (int k = 0; k < 16; ++k, ++r)
+      hipLaunchKernelGGL(k_frontier, dim3(grid), dim3(COL_BLOCK), 0, s, fr[r & 1], fr[(r + 1) & 1], cnt, r, pending,
+                         rp, ci, deg, h, col);
     LAMG_HIP(hipGetLastError());
-    if (to_host(s, ctr) >= n) break;
-    if (round > 1000000) throw DevError{hipErrorUnknown};
+    const int c0 = to_host(s, cnt + 2 * (r % 3)), c1 = to_host(s, cnt + 2 * (r % 3) + 1);
+    if (c0 == 0 && c1 == 0) break;
+    if (r > n + 16) throw DevError{hipErrorUnknown};
   }
+  hipLaunchKernelGGL(k_max_i, dim3(std::max(1, std::min(1024, (n + 255) / 256))), dim3(256), 0, s, n, (const int*)col,
+                     ctr + 1);
   return to_host(s, ctr + 1) + 1;
 }
 
