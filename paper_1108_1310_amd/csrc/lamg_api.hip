@@ -82,11 +82,13 @@ void body(Hierarchy* H, int l, int sub, std::vector<int64_t>& count) {
   const T* val = Prec<T>::val(L);
   const T* dg = Prec<T>::diag(L);
   if (C.type == LT_ELIM) {
-    residual<T>(s, L, val, dg, v.b, v.x, v.r);
-    restrict_elim<T>(s, C, v.r, vc.b);
+    const T* r = v.r;
+    if (l == 0 && H->top_res_known) r = sizeof(T) == 8 ? (const T*)H->r64 : v.b;
+    else residual<T>(s, L, val, dg, v.b, v.x, v.r);
+    restrict_elim<T>(s, C, r, vc.b);
     fill<T>(s, vc.x, T(0), C.n);
     visit<T>(H, l + 1, 1, count);
-    interp_elim<T>(s, L, C, val, dg, v.r, vc.x, v.x);
+    interp_elim<T>(s, L, C, val, dg, r, vc.x, v.x);
     return;
   }
   const bool rec = H->o.ec == LAMG_EC_RECOMBINE;
@@ -117,25 +119,35 @@ void visit(Hierarchy* H, int l, int th, std::vector<int64_t>& count) {
 }  // namespace
 
 template <class T>
-void cycle(Hierarchy* H) {
+void cycle(Hierarchy* H, bool top_res_known) {
   tail_prepare(H);
   H->tail_cursor = 0;
   std::vector<int64_t> count(H->lv.size(), 0);
-  visit<T>(H, 0, 1, count);
+  H->top_res_known = top_res_known;
+  try {
+    visit<T>(H, 0, 1, count);
+  } catch (...) {
+    H->top_res_known = false;
+    throw;
+  }
+  H->top_res_known = false;
   Level& L = H->lv[0];
   if (H->tail_lc != 0) subtract_mean<T>(H->s, H, Prec<T>::v(L).x, L.n);  // else in the tail program
   LAMG_HIP(hipGetLastError());
 }
-template void cycle<double>(Hierarchy*);
-template void cycle<float>(Hierarchy*);
+template void cycle<double>(Hierarchy*, bool);
+template void cycle<float>(Hierarchy*, bool);
 
 // The kernel sequence of a cycle depends only on the hierarchy and the solve
-// options, so it is captured once into a graph and replayed.  Capture runs on
+// options, so it is captured once into a graph and replayed.  The replays
+// serve the single-vector solve loop, which enters every cycle with the
+// finest residual known (FP64: r64 from the stopping test; FP32: x = 0, so
+// the residual is b), so the recorded cycle does not recompute it.  Capture runs on
 // the hierarchy's private stream; replays go to the caller's stream.  With
 // instrumentation on, the cycle is launched eagerly instead.
 template <class T>
 void cycle_graph(Hierarchy* H, int inst) {
-  if (prof_on()) { cycle<T>(H); return; }
+  if (prof_on()) { cycle<T>(H, true); return; }
   const int p = sizeof(T) == 8 ? 0 : 1;
   tail_prepare(H);  // uploads with synchronous copies: before any capture
   if (!H->gexec[p][inst]) {
@@ -145,7 +157,7 @@ void cycle_graph(Hierarchy* H, int inst) {
     hipGraph_t g = nullptr;
     LAMG_HIP(hipStreamBeginCapture(H->cs, hipStreamCaptureModeThreadLocal));
     try {
-      cycle<T>(H);
+      cycle<T>(H, true);
     } catch (...) {
       (void)hipStreamEndCapture(H->cs, &g);
       if (g) (void)hipGraphDestroy(g);

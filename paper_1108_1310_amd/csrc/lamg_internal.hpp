@@ -166,6 +166,9 @@ struct Hierarchy {
   int4* tail_prog = nullptr;      // device op program of one finest cycle
   std::vector<int2> tail_segs;    // (offset, length) per entry into the tail
   int tail_cursor = 0;
+  // set while a cycle is recorded whose finest residual is already known:
+  // FP64, in r64 (the stopping test's); FP32, equal to b (x starts at 0)
+  bool top_res_known = false;
   std::vector<TailLevel> tail_host;  // host copy of the descriptors
   MVWork mv;
   // whole-hierarchy op program (every level, from level 0) for the
@@ -253,7 +256,7 @@ void finish_levels(Hierarchy* H);
 int64_t cycle_bytes(const Hierarchy* H, int prec);
 int64_t cycle_bytes_k(const Hierarchy* H, int prec, int k);
 template <class T>
-void cycle(Hierarchy* H);
+void cycle(Hierarchy* H, bool top_res_known = false);
 // Replay one captured cycle (capturing it on first use); `inst` alternates.
 template <class T>
 void cycle_graph(Hierarchy* H, int inst);

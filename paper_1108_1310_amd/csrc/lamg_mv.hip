@@ -482,13 +482,15 @@ void body_mv(Hierarchy* H, int l, int sub, std::vector<int64_t>& count) {
   Vecs<T>& vc = PrecM<T>::v(H, l + 1);
   const int64_t nk = (int64_t)L.n * k, nck = (int64_t)C.n * k;
   if (C.type == LT_ELIM) {
-    residual_mv<T>(s, L, k, v.b, v.x, v.r);
-    relax_mv<T, 2>(s, C.er_rp, C.er_ci, PrecM<T>::er(C), (const T*)nullptr, (const T*)nullptr, v.r, vc.b, C.cfine, k,
+    const T* r = v.r;
+    if (l == 0 && H->top_res_known) r = v.b;  // x = 0 on entry
+    else residual_mv<T>(s, L, k, v.b, v.x, v.r);
+    relax_mv<T, 2>(s, C.er_rp, C.er_ci, PrecM<T>::er(C), (const T*)nullptr, (const T*)nullptr, const_cast<T*>(r), vc.b, C.cfine, k,
                    0, C.n, C.er_tiles);
     fill_mv<T>(s, vc.x, nck);
     visit_mv<T>(H, l + 1, 1, count);
     hipLaunchKernelGGL(k_interp_elim_mv<T>, gridn(nk), dim3(MVT), 0, s, L.n, k, C.cidx, L.rp, L.ci,
-                       PrecM<T>::val(L), PrecM<T>::diag(L), (const T*)v.r, (const T*)vc.x, v.x);
+                       PrecM<T>::val(L), PrecM<T>::diag(L), r, (const T*)vc.x, v.x);
     return;
   }
   const bool rec = H->o.ec == LAMG_EC_RECOMBINE;
@@ -519,20 +521,29 @@ void visit_mv(Hierarchy* H, int l, int th, std::vector<int64_t>& count) {
 }
 
 template <class T>
-void cycle_mv(Hierarchy* H) {
+void cycle_mv(Hierarchy* H, bool top_res_known = false) {
   tail_prepare_mv(H);
   H->tail_cursor = 0;
   std::vector<int64_t> count(H->lv.size(), 0);
-  visit_mv<T>(H, 0, 1, count);
+  H->top_res_known = top_res_known;
+  try {
+    visit_mv<T>(H, 0, 1, count);
+  } catch (...) {
+    H->top_res_known = false;
+    throw;
+  }
+  H->top_res_known = false;
   if (H->tail_lc != 0) subtract_mean_mv<T>(H->s, H, PrecM<T>::v(H, 0).x, H->lv[0].n, nullptr);
   LAMG_HIP(hipGetLastError());
 }
 
 // Captured once per precision and workspace, replayed per cycle (eager when
-// instrumented, so each relaxation launch has its own event pair).
+// instrumented, so each relaxation launch has its own event pair).  The
+// solve loop runs the cycle in correction form (x = 0 on entry), so the
+// finest residual of the recorded cycle is b itself.
 template <class T>
 void cycle_graph_mv(Hierarchy* H) {
-  if (prof_on()) { cycle_mv<T>(H); return; }
+  if (prof_on()) { cycle_mv<T>(H, true); return; }
   MVWork& W = H->mv;
   const int p = sizeof(T) == 8 ? 0 : 1;
   tail_prepare_mv(H);  // synchronous uploads: before any capture
@@ -543,7 +554,7 @@ void cycle_graph_mv(Hierarchy* H) {
     hipGraph_t g = nullptr;
     LAMG_HIP(hipStreamBeginCapture(H->cs, hipStreamCaptureModeThreadLocal));
     try {
-      cycle_mv<T>(H);
+      cycle_mv<T>(H, true);
     } catch (...) {
       (void)hipStreamEndCapture(H->cs, &g);
       if (g) (void)hipGraphDestroy(g);

@@ -18,13 +18,33 @@ namespace lamg {
 // it writes are never read in the same launch.
 // MODE 0: GS update; MODE 1: residual; MODE 2: elimination restriction
 // out_u = x_{map(u)} + sum (the gathered vector is the fine residual).
+// The per-row operands are loaded as soon as the row is known (relax_pre),
+// so that their latency overlaps the gathers; none of them is written in
+// the same launch (a GS pass writes only x of its own colour, which it does
+// not read for its own rows).
+template <class T>
+struct RowOps {
+  T a, d;  // MODE 0: b_u, a_uu; MODE 1: b_u - a_uu x_u; MODE 2: x_{map(u)}
+};
 template <class T, int MODE>
-__device__ inline void relax_store(int u, T s, const T* __restrict__ diag, const T* __restrict__ b, T* x,
-                                   T* __restrict__ r, const int* __restrict__ map) {
-  if (MODE == 2) { r[u] = x[map[u]] + s; return; }
-  const T bu = b ? b[u] : T(0);
-  if (MODE == 0) x[u] = (bu + s) / diag[u];
-  else r[u] = (bu + s) - diag[u] * x[u];
+__device__ inline RowOps<T> relax_pre(int u, const T* __restrict__ diag, const T* __restrict__ b, const T* x,
+                                      const int* __restrict__ map) {
+  RowOps<T> o;
+  if (MODE == 2) {
+    o.a = x[map[u]];
+    o.d = T(0);
+    return o;
+  }
+  o.a = b ? b[u] : T(0);
+  o.d = diag[u];
+  if (MODE == 1) o.d *= x[u];
+  return o;
+}
+template <class T, int MODE>
+__device__ inline void relax_store(int u, T s, RowOps<T> o, T* x, T* __restrict__ r) {
+  if (MODE == 2) r[u] = o.a + s;
+  else if (MODE == 0) x[u] = (o.a + s) / o.d;
+  else r[u] = (o.a + s) - o.d;
 }
 
 // One 512-entry chunk of a long row, one wavefront: lane j sums the chunk's
@@ -69,6 +89,8 @@ __global__ __launch_bounds__(RELAX_THREADS) void k_relax(
     const int4 e = vlong[bid];  // (row, first entry, entries)
     const int u = e.x, p0 = e.y, len = e.z;
     const int nch = (len + ROW_CHUNK - 1) / ROW_CHUNK;
+    RowOps<T> o{};
+    if (threadIdx.x == 0) o = relax_pre<T, MODE>(u, diag, b, x, map);
     T total = 0;
     for (int pass = 0; pass < nch; pass += MAXC) {
       const int lim = min(MAXC, nch - pass);
@@ -81,7 +103,7 @@ __global__ __launch_bounds__(RELAX_THREADS) void k_relax(
         for (int k = 0; k < lim; ++k) total += csum[k];
       __syncthreads();
     }
-    if (threadIdx.x == 0) relax_store<T, MODE>(u, total, diag, b, x, r, map);
+    if (threadIdx.x == 0) relax_store<T, MODE>(u, total, o, x, r);
     return;
   }
   bid -= nvlong;
@@ -90,10 +112,12 @@ __global__ __launch_bounds__(RELAX_THREADS) void k_relax(
     if (idx >= nmed) return;
     const int4 e = med[idx];
     const int u = e.x, p0 = e.y, len = e.z;
+    RowOps<T> o{};
+    if (lane == 0) o = relax_pre<T, MODE>(u, diag, b, x, map);
     const T sk = chunk_sum<T>(ci, val, x, p0, 0, len, lane);
     T total = 0;
     total += sk;
-    if (lane == 0) relax_store<T, MODE>(u, total, diag, b, x, r, map);
+    if (lane == 0) relax_store<T, MODE>(u, total, o, x, r);
     return;
   }
   bid -= nmed_blocks;
@@ -103,6 +127,8 @@ __global__ __launch_bounds__(RELAX_THREADS) void k_relax(
   // the row pointers go to LDS while the index and weight loads are in
   // flight; then all gathers: PER loads in flight per thread
   for (int i = threadIdx.x; i <= nr; i += RELAX_THREADS) srp[i] = rp[rr.x + i];
+  RowOps<T> o{};
+  if (threadIdx.x < nr) o = relax_pre<T, MODE>(rr.x + threadIdx.x, diag, b, x, map);
   int cj[PER];
   T wj[PER], xj[PER];
 #pragma unroll
@@ -123,7 +149,7 @@ __global__ __launch_bounds__(RELAX_THREADS) void k_relax(
     const int j1 = srp[threadIdx.x + 1] - base;
     T s = 0;
     for (int j = srp[threadIdx.x] - base; j < j1; ++j) s += prod[j];
-    relax_store<T, MODE>(rr.x + threadIdx.x, s, diag, b, x, r, map);
+    relax_store<T, MODE>(rr.x + threadIdx.x, s, o, x, r);
   }
 }
 
