@@ -57,8 +57,8 @@ def copy_calibration(nbytes):
 # --pmc FETCH_SIZE, then WRITE_SIZE, on this benchmark), scaled by the same
 # counters on a plain copy; valid only while the kernel source is unchanged.
 TRAFFIC = {
-    # profiles/gs_fp64_chung_lu_2p20.md: FETCH_SIZE 7417.0 KiB x 1.9999 + WRITE_SIZE 109.0 KiB x 1.0000
-    "chung_lu_2p20": {"bytes_per_launch": 15301206, "kernel_sha": "601b197140d00e38"},
+    # profiles/gs_fp64_chung_lu_2p20.md: FETCH_SIZE 7453.7 KiB x 1.9999 + WRITE_SIZE 108.9 KiB x 1.0000
+    "chung_lu_2p20": {"bytes_per_launch": 15376196, "kernel_sha": "ab1773a00a985b16"},
 }
 
 
