@@ -57,8 +57,8 @@ def copy_calibration(nbytes):
 # --pmc FETCH_SIZE, then WRITE_SIZE, on this benchmark), scaled by the same
 # counters on a plain copy; valid only while the kernel source is unchanged.
 TRAFFIC = {
-    # profiles/gs_fp64_chung_lu_2p20.md: FETCH_SIZE 7453.7 KiB x 1.9999 + WRITE_SIZE 108.9 KiB x 1.0000
-    "chung_lu_2p20": {"bytes_per_launch": 15376196, "kernel_sha": "ab1773a00a985b16"},
+    # profiles/gs_fp64_chung_lu_2p20.md: FETCH_SIZE 16412.1 KiB x 1.9999 + WRITE_SIZE 333.1 KiB x 1.0000
+    "chung_lu_2p20": {"bytes_per_launch": 33952095, "kernel_sha": "ab1773a00a985b16"},
 }
 
 
@@ -105,8 +105,9 @@ def timed_solves(H, b, precision, steps, warmup, lamg, instrument=False):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     prof = lamg.prof_read(kid)
+    hub = lamg.prof_read(8 if precision == lamg.FP64 else 9)
     lamg.prof_enable(False)
-    return dict(seconds=dt, cycles=cycles, bytes=byts, rel_residual=worst, prof=prof, x=x)
+    return dict(seconds=dt, cycles=cycles, bytes=byts, rel_residual=worst, prof=prof, hub=hub, x=x)
 
 
 def timed_multi(H, B, precision, steps, warmup, lamg, instrument=False):
@@ -429,6 +430,12 @@ def main():
                 "bytes_per_launch": p["bytes"] / max(1, p["launches"]),
                 "kernel_share_of_step": p["ms"] / (i64["seconds"] * 1e3),
                 "instrumented_ms_per_step": i64["seconds"] * 1e3 / a.steps}
+    hb = i64["hub"]
+    if hb["launches"] > 0:
+        # the hub colours of every sweep (partial-sum launch + single-workgroup phases)
+        roofline["hub_sweep"] = {"ms_per_step": hb["ms"] / a.steps, "launches": hb["launches"],
+                                 "gbps": hb["bytes"] / (hb["ms"] * 1e6),
+                                 "share_of_step": hb["ms"] / (i64["seconds"] * 1e3)}
     adj = None
     if a.workload == "rgg_2p20":
         adj = adjoint_step(g, b, a.steps, a.warmup)

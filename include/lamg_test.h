@@ -92,17 +92,29 @@ lamg_status lamg_t_gs32(int32_t n, const int32_t* rp, const int32_t* ci, const f
 lamg_status lamg_t_residual(int32_t n, const int32_t* rp, const int32_t* ci, const double* val, const double* diag,
                             const double* b, const double* x, double* r, void* stream);
 
-/* Greedy colouring by Jones-Plassmann rounds, priority (degree desc,
- * hash(seed, level, id) asc, id asc) on a DEVICE CSR; DEVICE colour[n] out. */
+/* Greedy colouring (first fit in priority order: degree desc, hash(seed,
+ * level, id) asc, id asc) on a DEVICE CSR, computed as a topological sweep
+ * over the priority order; DEVICE colour[n] out. */
 lamg_status lamg_t_colour(int32_t n, const int32_t* rp, const int32_t* ci, uint64_t seed, int32_t level,
                           int32_t* colour, void* stream);
+
+/* Hub sweep of level l (Section 3.1.1, eq. gs, multicolour order): out[4] =
+ * first hub colour (-1: the level's sweeps do not take the hub path), first
+ * hub row, hub rows, hub-to-hub entries.  HOST out. */
+lamg_status lamg_t_hub_info(lamg_handle h, int32_t l, int64_t* out);
+
+/* `sweeps` GS sweeps of the solve on level l of a hierarchy, hub path where
+ * taken: DEVICE b (may be NULL: b = 0) and x of n_l entries in the level's
+ * colour order, FP64 (precision 0, the level's FP64 matrix) or FP32
+ * (precision 1, its FP32 copy). */
+lamg_status lamg_t_level_gs(lamg_handle h, int32_t l, int32_t precision, int32_t sweeps, const void* b, void* x);
 
 /* Instrumentation of the relaxation kernel (Section 3.1.1, eq. gs) and of the
  * residual kernel.  lamg_t_prof_enable(1) clears the counters and brackets
  * every later launch with HIP events on the launch's stream; kernel ids:
- * 0 GS FP64, 1 residual FP64, 2 GS FP32, 3 residual FP32, and 4..7 the same
- * four for the multi-vector kernels.  lamg_t_prof_read
- * waits for the recorded events and returns the summed kernel time (ms), the
+ * 0 GS FP64, 1 residual FP64, 2 GS FP32, 3 residual FP32, 4..7 the same
+ * four for the multi-vector kernels, 8 / 9 the hub sweep (FP64 / FP32; its
+ * colours are not in 0 / 2).  lamg_t_prof_read waits for the recorded events and returns the summed kernel time (ms), the
  * number of launches and their algorithmic bytes (HOST outputs). */
 void lamg_t_prof_enable(int on);
 lamg_status lamg_t_prof_read(int kernel, double* ms, int64_t* launches, int64_t* bytes);

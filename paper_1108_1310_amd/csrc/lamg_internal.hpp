@@ -43,6 +43,23 @@ constexpr int TILE_NNZ = 4096;
 constexpr int LONG_PER_BLOCK = RELAX_THREADS / 64;
 constexpr int ROW_CHUNK = 512;
 
+// Hub sweep of a relaxed level.  On power-law levels the last colour classes
+// hold few rows (the hubs) with long rows, and a GS sweep spends most of its
+// time in their dependent phases.  From colour hub_k on, once colours
+// < hub_k are final for the sweep, every hub row's sum over those colours is
+// one launch (k_hub_partial), and the remaining colour phases run in one
+// workgroup with the hubs' x in LDS and only the hub-to-hub entries left to
+// gather (k_hub_sweep).  Taken when the hub rows are at most HUB_MAX_ROWS,
+// at least HUB_MIN_COLOURS colours are hub colours, and the chunk table has
+// at most HUB_MAX_CHUNKS entries.
+constexpr int HUB_MAX_ROWS = 4096;
+constexpr int HUB_MIN_COLOURS = 8;
+constexpr int HUB_THREADS = 1024;
+constexpr int HUB_PER = 4;                          // entries per thread per chunk
+constexpr int HUB_CHUNK = HUB_THREADS * HUB_PER;    // products staged per chunk
+static_assert(HUB_CHUNK >= HUB_MAX_ROWS, "a hub row's hub-to-hub entries fit one chunk");
+constexpr int HUB_MAX_CHUNKS = 1024;
+
 struct Tiles {
   int64_t rows = 0, nnz = 0;  // rows and entries covered (algorithmic bytes per launch)
   int nstream = 0;
@@ -95,6 +112,15 @@ struct Level {
   int* state = nullptr;
   Vecs<double> v64;
   Vecs<float> v32;
+  // hub sweep (hub_k < 0: not taken): hub rows [hub_r0, n) in colours
+  // [hub_k, ncol); their hub-to-hub entries as a CSR with local column ids
+  int hub_k = -1, hub_r0 = 0, hub_n = 0, hub_nnz = 0;
+  int64_t hub_low_nnz = 0;                  // entries of hub rows into colours < hub_k
+  int *hub_rp = nullptr, *hub_ci = nullptr; // [hub_n + 1], [hub_nnz]
+  int2* hub_ck = nullptr;                   // [hub_nck] chunks: (first row, end row), local ids
+  int hub_nck = 0;
+  double *hub_val = nullptr, *hub_p = nullptr;
+  float *hub_val32 = nullptr, *hub_p32 = nullptr;
 };
 
 // Device descriptor of one level for the single-workgroup tail program.
@@ -181,8 +207,10 @@ struct Hierarchy {
 // -------------------------------------------------------- instrumentation
 // When enabled, every relaxation / residual launch is bracketed by HIP events
 // on its stream and its algorithmic bytes are accumulated per kernel:
-// 0 GS FP64, 1 residual FP64, 2 GS FP32, 3 residual FP32, and 4..7 the same
-// four for the multi-vector kernels.
+// 0 GS FP64, 1 residual FP64, 2 GS FP32, 3 residual FP32, 4..7 the same
+// four for the multi-vector kernels, 8 / 9 the hub sweep (FP64 / FP32: the
+// partial-sum launch and the single-workgroup sweep of each GS sweep).
+constexpr int PROF_KERNELS = 10;
 // Spans: prof_begin records the opening event of a run of launches of one
 // kernel, prof_count adds each launch (and its algorithmic bytes) of that
 // kernel to the open span, prof_end records the closing event.
@@ -251,6 +279,7 @@ bool try_eliminate(Hierarchy* H, int l);
 // 1: coarse level added; 0: no coarsening possible; 2: relaxation is fast
 int aggregate(Hierarchy* H, int l, int agg_index);
 void finish_levels(Hierarchy* H);
+void build_hub(Hierarchy* H, Level& L);
 
 // solve
 int64_t cycle_bytes(const Hierarchy* H, int prec);

@@ -1228,7 +1228,97 @@ __global__ void k_to_f32(int64_t n, const double* __restrict__ a, float* __restr
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) b[i] = (float)a[i];
 }
+// Hub rows [r0, r0 + nh): entries into the hub rows themselves.  Columns are
+// sorted within a row and hub ids are the largest, so they are each row's
+// suffix; the count is found by bisection.
+__global__ void k_hub_count(int nh, int r0, const int* __restrict__ rp, const int* __restrict__ ci,
+                            int* __restrict__ cnt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nh) return;
+  const int end = rp[r0 + i + 1];
+  int lo = rp[r0 + i], hi = end;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (ci[mid] < r0) lo = mid + 1;
+    else hi = mid;
+  }
+  cnt[i] = end - lo;
+}
+// One wavefront per hub row copies its suffix with local column ids.
+__global__ void k_hub_fill(int nh, int r0, const int* __restrict__ rp, const int* __restrict__ ci,
+                           const double* __restrict__ val, const float* __restrict__ val32,
+                           const int* __restrict__ hrp, int* __restrict__ hci, double* __restrict__ hv,
+                           float* __restrict__ hv32) {
+  const int i = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6), lane = threadIdx.x & 63;
+  if (i >= nh) return;
+  const int dst = hrp[i], len = hrp[i + 1] - dst;
+  const int src = rp[r0 + i + 1] - len;
+  for (int j = lane; j < len; j += 64) {
+    hci[dst + j] = ci[src + j] - r0;
+    hv[dst + j] = val[src + j];
+    hv32[dst + j] = val32[src + j];
+  }
+}
 }  // namespace
+
+void build_hub(Hierarchy* H, Level& L) {
+  L.hub_k = -1;
+  const int n = L.n, nc = L.ncol;
+  if (n <= HUB_MAX_ROWS || nc < HUB_MIN_COLOURS || (int)L.cptr.size() != nc + 1) return;
+  // the smallest K >= 1 whose colours >= K hold at most HUB_MAX_ROWS rows
+  int K = nc;
+  for (int c = nc - 1; c >= 1; --c) {
+    if (n - L.cptr[c] > HUB_MAX_ROWS) break;
+    K = c;
+  }
+  if (nc - K < HUB_MIN_COLOURS) return;
+  hipStream_t s = H->s;
+  Tmp tmp;
+  const int r0 = L.cptr[K], nh = n - r0;
+  int* cnt = tmp.get<int>(nh + 1);
+  int* hrp = dnew<int>(H, (size_t)nh + 1);
+  hipLaunchKernelGGL(k_hub_count, grid1(nh), dim3(256), 0, s, nh, r0, (const int*)L.rp, (const int*)L.ci, cnt);
+  excl_scan(s, tmp, cnt, hrp, nh);
+  const int hnnz = to_host(s, hrp + nh);
+  int* hci = dnew<int>(H, std::max(hnnz, 1));
+  double* hv = dnew<double>(H, std::max(hnnz, 1));
+  float* hv32 = dnew<float>(H, std::max(hnnz, 1));
+  hipLaunchKernelGGL(k_hub_fill, dim3((unsigned)(((int64_t)nh * 64 + 255) / 256)), dim3(256), 0, s, nh, r0,
+                     (const int*)L.rp, (const int*)L.ci, (const double*)L.val, (const float*)L.val32, (const int*)hrp,
+                     hci, hv, hv32);
+  // chunks of whole rows of one colour, at most HUB_CHUNK entries each
+  std::vector<int> hr(nh + 1);
+  LAMG_HIP(hipMemcpyAsync(hr.data(), hrp, (size_t)(nh + 1) * sizeof(int), hipMemcpyDeviceToHost, s));
+  LAMG_HIP(hipStreamSynchronize(s));
+  std::vector<int2> ck;
+  for (int c = K; c < nc; ++c) {
+    const int a = L.cptr[c] - r0, z = L.cptr[c + 1] - r0;
+    int first = a;
+    for (int u = a; u < z; ++u)
+      if (hr[u + 1] - hr[first] > HUB_CHUNK) {
+        ck.push_back(make_int2(first, u));
+        first = u;
+      }
+    ck.push_back(make_int2(first, z));
+  }
+  if ((int)ck.size() > HUB_MAX_CHUNKS) return;  // (the device arrays stay with the handle, unused)
+  L.hub_ck = dnew<int2>(H, ck.size());
+  LAMG_HIP(hipMemcpyAsync(L.hub_ck, ck.data(), ck.size() * sizeof(int2), hipMemcpyHostToDevice, s));
+  L.hub_nck = (int)ck.size();
+  const int low0 = to_host(s, L.rp + r0);
+  L.hub_low_nnz = (int64_t)L.nnz - low0 - hnnz;
+  L.hub_p = dnew<double>(H, nh);
+  L.hub_p32 = dnew<float>(H, nh);
+  L.hub_rp = hrp;
+  L.hub_ci = hci;
+  L.hub_val = hv;
+  L.hub_val32 = hv32;
+  L.hub_r0 = r0;
+  L.hub_n = nh;
+  L.hub_nnz = hnnz;
+  LAMG_HIP(hipStreamSynchronize(s));  // ck leaves scope
+  L.hub_k = K;
+}
 
 void finish_levels(Hierarchy* H) {
   hipStream_t s = H->s;
@@ -1257,6 +1347,7 @@ void finish_levels(Hierarchy* H) {
     };
     mk64(L.v64);
     mk32(L.v32);
+    build_hub(H, L);
   }
   if (H->lv.back().n > H->o.dense_max) H->coarsest_relax = true;
   if (!H->coarsest_relax) coarsest_factor(H, H->lv.back());

@@ -30,8 +30,8 @@ struct Prof {
   Pair cur{};
   std::vector<Pair> pend;  // closed spans whose events are not read yet
   std::vector<hipEvent_t> pool;
-  double ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  int64_t bytes[8] = {0, 0, 0, 0, 0, 0, 0, 0}, launches[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double ms[PROF_KERNELS] = {};
+  int64_t bytes[PROF_KERNELS] = {}, launches[PROF_KERNELS] = {};
 };
 Prof g_prof;
 hipEvent_t new_event() {
@@ -107,15 +107,219 @@ static void launch_relax(hipStream_t s, const int* rp, const int* ci, const Tile
   LAMG_HIP(hipGetLastError());
 }
 
+// ------------------------------------------------------------------ hubs
+// Partial sums of the hub rows once colours < hub_k are final for the sweep:
+// p_u = b_u + the row's entries into those colours (its column prefix), one
+// wavefront per row, 64 strided partial sums folded by the butterfly.
+template <class T>
+__global__ __launch_bounds__(256) void k_hub_partial(int nh, int r0, const int* __restrict__ rp,
+                                                     const int* __restrict__ ci, const T* __restrict__ val,
+                                                     const int* __restrict__ hrp, const T* __restrict__ b,
+                                                     const T* __restrict__ x, T* __restrict__ p) {
+  const int i = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6), lane = threadIdx.x & 63;
+  if (i >= nh) return;
+  const int u = r0 + i;
+  const int p0 = rp[u];
+  const int pe = rp[u + 1] - (hrp[i + 1] - hrp[i]);
+  const T bu = b ? b[u] : T(0);
+  T s = 0;
+  int t = p0 + lane;
+  for (; t + 192 < pe; t += 256) {
+    const int c0 = ci[t], c1 = ci[t + 64], c2 = ci[t + 128], c3 = ci[t + 192];
+    const T w0 = val[t], w1 = val[t + 64], w2 = val[t + 128], w3 = val[t + 192];
+    const T x0 = x[c0], x1 = x[c1], x2 = x[c2], x3 = x[c3];
+    s += w0 * x0;
+    s += w1 * x1;
+    s += w2 * x2;
+    s += w3 * x3;
+  }
+  for (; t < pe; t += 64) s += val[t] * x[ci[t]];
+  s = dev::wave_fold(s);
+  if (lane == 0) p[i] = bu + s;
+}
+
+// Sum over the 16 lanes of a DPP row: swap neighbours, swap pairs, mirror of
+// 8, mirror of 16.  The two operands of every add are the same pair in every
+// lane, so all 16 lanes end with the same value.  The 16 lanes must be all
+// active or all inactive.
+template <int CTRL>
+__device__ inline float dpp_f(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ inline double dpp_f(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+template <class T>
+__device__ inline T row16_sum(T s) {
+  s += dpp_f<0xB1>(s);   // quad_perm(1, 0, 3, 2)
+  s += dpp_f<0x4E>(s);   // quad_perm(2, 3, 0, 1)
+  s += dpp_f<0x141>(s);  // row_half_mirror
+  s += dpp_f<0x140>(s);  // row_mirror
+  return s;
+}
+
+// The hub colour phases in one workgroup.  x, p and the diagonal of the hub
+// rows stay in LDS for the whole sweep.  The phases are cut into chunks of
+// whole rows of one colour with at most HUB_CHUNK hub-to-hub entries (a
+// chunk table built at setup; no row is longer, since its columns are
+// distinct hub rows).  A chunk stages the products of its entries in LDS,
+// then each group of 16 lanes takes rows of the chunk, sums a row's products
+// with 16 strided partial sums folded by DPP (row16_sum), and sets
+// x_u = (p_u + sum) / a_uu.  Rows of one colour are not adjacent, so a chunk
+// never reads what it writes.  The index and weight loads of a chunk do not
+// depend on x: they are issued HUB_DEPTH chunks ahead, into HUB_DEPTH
+// register sets used in turn.  A chunk is bound by the LDS traffic of its
+// one compute unit (x gathers, product writes and reads: 24 bytes per FP64
+// entry), not by these loads.
+constexpr int HUB_DEPTH = 2;
+template <class T>
+struct HubSm {
+  T *prod, *xs, *ps, *ds;
+  int* srp;
+  int2* sck;
+};
+template <class T>
+__device__ __forceinline__ void hub_load(const HubSm<T>& m, int k, int nck, const int* __restrict__ hci,
+                                         const T* __restrict__ hval, int (&cj)[HUB_PER], T (&wj)[HUB_PER]) {
+  int e0 = 0, e1 = 0;
+  if (k < nck) {
+    const int2 c = m.sck[k];
+    e0 = m.srp[c.x];
+    e1 = m.srp[c.y];
+  }
+#pragma unroll
+  for (int q = 0; q < HUB_PER; ++q) {
+    const int e = e0 + (int)threadIdx.x + q * HUB_THREADS;
+    cj[q] = e < e1 ? hci[e] : 0;
+    wj[q] = e < e1 ? hval[e] : T(0);
+  }
+}
+template <class T>
+__device__ __forceinline__ void hub_chunk(const HubSm<T>& m, int k, int nck, const int* __restrict__ hci,
+                                          const T* __restrict__ hval, int (&cj)[HUB_PER], T (&wj)[HUB_PER]) {
+  const int t = threadIdx.x, g = t >> 4, gl = t & 15;
+  const int2 c = m.sck[k];
+  const int e0 = m.srp[c.x], e1 = m.srp[c.y];
+#pragma unroll
+  for (int q = 0; q < HUB_PER; ++q) {
+    const int e = e0 + t + q * HUB_THREADS;
+    if (e < e1) m.prod[e - e0] = wj[q] * m.xs[cj[q]];
+  }
+  hub_load<T>(m, k + HUB_DEPTH, nck, hci, hval, cj, wj);
+  __syncthreads();
+  for (int u = c.x + g; u < c.y; u += HUB_THREADS / 16) {
+    const int a = m.srp[u] - e0, z = m.srp[u + 1] - e0;
+    const T pu = m.ps[u], du = m.ds[u];
+    T s = 0;
+    int e = a + gl;
+    for (; e + 48 < z; e += 64) {
+      const T v0 = m.prod[e], v1 = m.prod[e + 16], v2 = m.prod[e + 32], v3 = m.prod[e + 48];
+      s += v0;
+      s += v1;
+      s += v2;
+      s += v3;
+    }
+    for (; e < z; e += 16) s += m.prod[e];
+    s = row16_sum<T>(s);
+    if (gl == 0) m.xs[u] = (pu + s) / du;
+  }
+  __syncthreads();
+}
+template <class T>
+__global__ __launch_bounds__(HUB_THREADS) void k_hub_sweep(int nh, int nck, const int2* __restrict__ ck,
+                                                          const int* __restrict__ hrp, const int* __restrict__ hci,
+                                                          const T* __restrict__ hval, const T* __restrict__ p,
+                                                          const T* __restrict__ dg, T* __restrict__ xh) {
+  extern __shared__ __align__(16) unsigned char hub_smem[];
+  constexpr int HT = HUB_THREADS;
+  HubSm<T> m;
+  m.prod = (T*)hub_smem;       // [HUB_CHUNK]
+  m.xs = m.prod + HUB_CHUNK;   // [nh]
+  m.ps = m.xs + nh;            // [nh]
+  m.ds = m.ps + nh;            // [nh]
+  m.srp = (int*)(m.ds + nh);   // [nh + 1]
+  const size_t ck_off = ((size_t)HUB_CHUNK * sizeof(T) + 3 * (size_t)nh * sizeof(T) + ((size_t)nh + 1) * 4 + 7) & ~(size_t)7;
+  m.sck = (int2*)(hub_smem + ck_off);  // [nck]
+  const int t = threadIdx.x;
+  for (int i = t; i < nh; i += HT) {
+    m.xs[i] = xh[i];
+    m.ps[i] = p[i];
+    m.ds[i] = dg[i];
+  }
+  for (int i = t; i <= nh; i += HT) m.srp[i] = hrp[i];
+  for (int i = t; i < nck; i += HT) m.sck[i] = ck[i];
+  __syncthreads();
+  int cja[HUB_PER], cjb[HUB_PER];
+  T wja[HUB_PER], wjb[HUB_PER];
+  hub_load<T>(m, 0, nck, hci, hval, cja, wja);
+  hub_load<T>(m, 1, nck, hci, hval, cjb, wjb);
+  for (int k = 0; k < nck; k += HUB_DEPTH) {
+    hub_chunk<T>(m, k, nck, hci, hval, cja, wja);
+    if (k + 1 < nck) hub_chunk<T>(m, k + 1, nck, hci, hval, cjb, wjb);
+  }
+  for (int i = t; i < nh; i += HT) xh[i] = m.xs[i];
+}
+
+template <class T>
+struct HubVals;
+template <>
+struct HubVals<double> {
+  static const double* val(const Level& L) { return L.hub_val; }
+  static double* p(const Level& L) { return L.hub_p; }
+};
+template <>
+struct HubVals<float> {
+  static const float* val(const Level& L) { return L.hub_val32; }
+  static float* p(const Level& L) { return L.hub_p32; }
+};
+
+// The colours >= hub_k of one GS sweep: the partial sums, then the phases.
+template <class T>
+static void hub_sweep(hipStream_t s, const Level& L, const T* val, const T* diag, const T* b, T* x) {
+  const int nh = L.hub_n, r0 = L.hub_r0;
+  const size_t lds = (((size_t)HUB_CHUNK * sizeof(T) + 3 * (size_t)nh * sizeof(T) + ((size_t)nh + 1) * 4 + 7) &
+                      ~(size_t)7) + (size_t)L.hub_nck * sizeof(int2);
+  static bool attr_set = false;
+  if (!attr_set) {
+    LAMG_HIP(hipFuncSetAttribute((const void*)k_hub_sweep<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)(HUB_CHUNK * sizeof(T) + 3 * HUB_MAX_ROWS * sizeof(T) +
+                                       (HUB_MAX_ROWS + 2) * sizeof(int) + HUB_MAX_CHUNKS * sizeof(int2))));
+    attr_set = true;
+  }
+  if (nh > HUB_MAX_ROWS || L.hub_nck < 1 || L.hub_nck > HUB_MAX_CHUNKS) throw DevError{hipErrorInvalidValue};
+  T* p = HubVals<T>::p(L);
+  const bool prof = prof_on();
+  const int kid = sizeof(T) == 8 ? 8 : 9;
+  const int64_t s_v = sizeof(T);
+  if (prof) prof_count(kid, L.hub_low_nnz * (4 + s_v) + (int64_t)nh * (8 + 3 * s_v));
+  hipLaunchKernelGGL(k_hub_partial<T>, dim3((unsigned)(((int64_t)nh * 64 + 255) / 256)), dim3(256), 0, s, nh, r0,
+                     (const int*)L.rp, (const int*)L.ci, val, (const int*)L.hub_rp, b, (const T*)x, p);
+  LAMG_HIP(hipGetLastError());
+  if (prof) prof_count(kid, (int64_t)L.hub_nnz * (4 + s_v) + (int64_t)nh * (4 + 4 * s_v));
+  hipLaunchKernelGGL(k_hub_sweep<T>, dim3(1), dim3(HUB_THREADS), lds, s, nh, L.hub_nck, (const int2*)L.hub_ck,
+                     (const int*)L.hub_rp, (const int*)L.hub_ci, HubVals<T>::val(L), (const T*)p, diag + r0, x + r0);
+  LAMG_HIP(hipGetLastError());
+}
+
 template <class T>
 void gs_colour(hipStream_t s, const Level& L, int c, const T* val, const T* diag, const T* b, T* x) {
   launch_relax<T, 0>(s, L.rp, L.ci, L.tiles[c], val, diag, b, x, (T*)nullptr);
 }
 template <class T>
 void gs_sweep(hipStream_t s, const Level& L, const T* val, const T* diag, const T* b, T* x) {
+  const int K = L.hub_k >= 0 ? L.hub_k : L.ncol;
   prof_begin(s, sizeof(T) == 4 ? 2 : 0);
-  for (int c = 0; c < L.ncol; ++c) gs_colour<T>(s, L, c, val, diag, b, x);
+  for (int c = 0; c < K; ++c) gs_colour<T>(s, L, c, val, diag, b, x);
   prof_end(s);
+  if (K < L.ncol) {
+    prof_begin(s, sizeof(T) == 4 ? 9 : 8);
+    hub_sweep<T>(s, L, val, diag, b, x);
+    prof_end(s);
+  }
 }
 template <class T>
 void residual(hipStream_t s, const Level& L, const T* val, const T* diag, const T* b, const T* x, T* r) {
@@ -533,11 +737,11 @@ void lamg_t_prof_enable(int on) {
   } catch (const lamg::DevError&) {
   }
   P.on = on != 0;
-  for (int k = 0; k < 8; ++k) { P.ms[k] = 0; P.bytes[k] = 0; P.launches[k] = 0; }
+  for (int k = 0; k < lamg::PROF_KERNELS; ++k) { P.ms[k] = 0; P.bytes[k] = 0; P.launches[k] = 0; }
 }
 lamg_status lamg_t_prof_read(int kernel, double* ms, int64_t* launches, int64_t* bytes) {
   lamg::Prof& P = lamg::g_prof;
-  if (kernel < 0 || kernel > 7 || !ms || !launches || !bytes) return LAMG_E_INVALID_ARG;
+  if (kernel < 0 || kernel >= lamg::PROF_KERNELS || !ms || !launches || !bytes) return LAMG_E_INVALID_ARG;
   try {
     lamg::prof_flush();
   } catch (const lamg::DevError&) {

@@ -152,6 +152,34 @@ lamg_status lamg_t_gs(int32_t n, const int32_t* rp, const int32_t* ci, const dou
   return LAMG_OK;
 }
 
+lamg_status lamg_t_hub_info(lamg_handle h, int32_t l, int64_t* out) {
+  if (!h || !out || l < 0 || l >= (int)h->H.lv.size()) return LAMG_E_INVALID_ARG;
+  const Level& L = h->H.lv[l];
+  out[0] = L.hub_k;
+  out[1] = L.hub_k >= 0 ? L.hub_r0 : 0;
+  out[2] = L.hub_k >= 0 ? L.hub_n : 0;
+  out[3] = L.hub_k >= 0 ? L.hub_nnz : 0;
+  return LAMG_OK;
+}
+
+lamg_status lamg_t_level_gs(lamg_handle h, int32_t l, int32_t precision, int32_t sweeps, const void* b, void* x) {
+  if (!h || !x || l < 0 || l >= (int)h->H.lv.size() || sweeps < 0 || (precision != 0 && precision != 1))
+    return LAMG_E_INVALID_ARG;
+  try {
+    Hierarchy* H = &h->H;
+    const Level& L = H->lv[l];
+    for (int i = 0; i < sweeps; ++i) {
+      if (precision == 0) gs_sweep<double>(H->s, L, L.val, L.diag, (const double*)b, (double*)x);
+      else gs_sweep<float>(H->s, L, L.val32, L.diag32, (const float*)b, (float*)x);
+    }
+    LAMG_HIP(hipStreamSynchronize(H->s));
+  } catch (const DevError& e) {
+    set_last_error("lamg_t_level_gs", e.e);
+    return LAMG_E_DEVICE;
+  }
+  return LAMG_OK;
+}
+
 lamg_status lamg_t_gs32(int32_t n, const int32_t* rp, const int32_t* ci, const float* val, const float* diag,
                         int32_t ncol, const int32_t* cptr, const float* b, float* x, int32_t sweeps, void* stream) {
   if (n < 1 || !rp || !ci || !val || !diag || !x || ncol < 1 || !cptr || cptr[0] != 0 || cptr[ncol] != n)

@@ -86,6 +86,8 @@ def lib():
             "lamg_t_gs32": (C.c_int, [i32, vp, vp, vp, vp, i32, vp, vp, vp, i32, vp]),
             "lamg_t_residual": (C.c_int, [i32, vp, vp, vp, vp, vp, vp, vp, vp]),
             "lamg_t_colour": (C.c_int, [i32, vp, vp, u64, i32, vp, vp]),
+            "lamg_t_hub_info": (C.c_int, [vp, i32, vp]),
+            "lamg_t_level_gs": (C.c_int, [vp, i32, i32, i32, vp, vp]),
             "lamg_t_prof_enable": (None, [C.c_int]),
             "lamg_t_prof_read": (C.c_int, [C.c_int, C.POINTER(d), C.POINTER(i64), C.POINTER(i64)]),
         }
@@ -233,6 +235,21 @@ class Hierarchy:
         return dict(tv=tv.reshape(n, K), aff=aff, ok=ok, weak=weak, hub=hub, state=st, delta1=scal[0],
                     alpha1=scal[1], alpha2=scal[2], stage=int(scal[3]), rate=scal[4], K=K)
 
+    def hub_info(self, l: int) -> dict:
+        """The hub split of level l's GS sweeps (k = -1: not taken)."""
+        d = (C.c_int64 * 4)()
+        _check(lib().lamg_t_hub_info(self.h, l, d), "lamg_t_hub_info")
+        return dict(k=d[0], r0=d[1], n=d[2], nnz=d[3])
+
+    def level_gs(self, l: int, b_perm, x_perm, sweeps: int = 1, precision: int = 0):
+        """The solve's GS sweeps on level l (colour order), FP64 or FP32."""
+        t = torch.float64 if precision == 0 else torch.float32
+        b = None if b_perm is None else _dev(b_perm, t).contiguous()
+        x = _dev(x_perm, t).clone().contiguous()
+        _check(lib().lamg_t_level_gs(self.h, l, precision, sweeps, None if b is None else _ptr(b), _ptr(x)),
+               "lamg_t_level_gs")
+        return x
+
     def cycle(self, b_perm, x_perm):
         b = _dev(b_perm, torch.float64)
         x = _dev(x_perm, torch.float64).clone()
@@ -365,7 +382,8 @@ def colour(rp, ci, n, seed=0, level=0):
 
 
 KERNELS = {0: "gs_fp64", 1: "residual_fp64", 2: "gs_fp32", 3: "residual_fp32",
-           4: "mv_gs_fp64", 5: "mv_residual_fp64", 6: "mv_gs_fp32", 7: "mv_residual_fp32"}
+           4: "mv_gs_fp64", 5: "mv_residual_fp64", 6: "mv_gs_fp32", 7: "mv_residual_fp32",
+           8: "hub_sweep_fp64", 9: "hub_sweep_fp32"}
 
 
 def prof_enable(on: bool = True):

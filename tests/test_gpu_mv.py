@@ -79,17 +79,21 @@ def test_mv_flat_equals_single_vector(lg, name, k, tail):
     of the multi-vector cycle repeats the single-vector GPU cycle: the same
     relaxation, residual and transfer sums in the same order (16-byte column
     slices for k = 4, 8, 32; scalar columns for k = 3, 5), long hub rows
-    included.  Only the final mean is summed in another order."""
+    included.  Only the final mean is summed in another order, and, where a
+    level's single-vector sweeps take the hub path, the hub rows' sums (low
+    colours first, then the hub-to-hub entries): 1e-13 there."""
     _case(f"mv flat {name} k={k} tail={tail}")
     n, eu, ev, w = graph(name)
     kw = {} if tail else {"tail_max_n": 0}
     Hg = lg.Hierarchy(n, eu, ev, w, **kw)
     Hg.set_solve_options(ec=1)
+    hubs = any(Hg.hub_info(l)["k"] >= 0 for l in range(Hg.num_levels))
+    tol = 1e-13 if hubs else 1e-14
     B = _block(n, k, 6)
     X = Hg.mv_cycle(B, np.zeros((n, k))).cpu().numpy()
     for j in range(k):
         x1 = Hg.cycle(B[:, j], np.zeros(n)).cpu().numpy()
-        assert np.linalg.norm(X[:, j] - x1) <= 1e-14 * np.linalg.norm(x1), j
+        assert np.linalg.norm(X[:, j] - x1) <= tol * np.linalg.norm(x1), j
 
 
 @pytest.mark.parametrize("name", ["grid3d16", "chung_lu16k", "rgg16k"])
