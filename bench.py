@@ -377,8 +377,8 @@ def main():
     if a.copy_bytes:
         return copy_calibration(a.copy_bytes)
     if a.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU path is not part of "
-              "this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}): the solver has no multi-GPU path",
+              file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_1108_1310_amd import lamg
