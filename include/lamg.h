@@ -72,6 +72,17 @@ typedef struct lamg_options {
   int warm_start;           /* 1: x holds the initial guess on entry */
   uint64_t seed;            /* colouring priorities and test vectors */
   void* stream;             /* hipStream_t */
+  /* Device memory of the hierarchy, its workspaces and the setup's
+   * temporaries (e.g. a framework's caching allocator): alloc(bytes, ctx)
+   * returns a device pointer aligned to at least 256 bytes, or NULL (the call
+   * then fails with LAMG_E_OUT_OF_MEMORY); dealloc(ptr, ctx) releases one.
+   * Called on the calling thread, never concurrently for one handle; memory
+   * of a handle is released by lamg_free, temporaries before the call
+   * returns.  Both NULL: hipMalloc / hipFree.  Set both or neither; fixed at
+   * setup (lamg_set_solve_options ignores them). */
+  void* (*alloc)(size_t bytes, void* ctx);
+  void (*dealloc)(void* ptr, void* ctx);
+  void* alloc_ctx;
 } lamg_options;
 
 typedef struct lamg_info {

@@ -289,6 +289,9 @@ void lamg_options_default(lamg_options* o) {
   o->warm_start = 0;
   o->seed = 0;
   o->stream = nullptr;
+  o->alloc = nullptr;
+  o->dealloc = nullptr;
+  o->alloc_ctx = nullptr;
 }
 
 const char* lamg_last_error(void) { return g_last_error; }
@@ -311,7 +314,8 @@ static bool opts_ok(const lamg_options& o) {
   return o.gamma >= 1.0 && o.gamma <= 2.0 && o.nu_pre >= 0 && o.nu_post >= 0 && o.tv_k_min >= 1 &&
          o.tv_k_max >= o.tv_k_min && o.tv_k_max <= 10 && o.tv_sweeps >= 0 && o.q_max > 1.0 && o.coarsest_max_n >= 2 &&
          o.elim_max_degree >= 0 && o.stage1_quantile >= 0.0 && o.stage1_quantile <= 1.0 && o.tol >= 0 &&
-         o.max_cycles >= 0 && o.coarsest_sweeps >= 1 && o.dense_max >= 1 && o.dense_max <= 8192 && o.tail_max_n >= 0;
+         o.max_cycles >= 0 && o.coarsest_sweeps >= 1 && o.dense_max >= 1 && o.dense_max <= 8192 && o.tail_max_n >= 0 &&
+         (o.alloc == nullptr) == (o.dealloc == nullptr);
 }
 
 lamg_status lamg_setup(int64_t n, int64_t m, const int32_t* eu, const int32_t* ev, const double* w,
@@ -331,6 +335,7 @@ lamg_status lamg_setup(int64_t n, int64_t m, const int32_t* eu, const int32_t* e
   Hierarchy* H = &h->H;
   H->o = opt;
   H->s = (hipStream_t)opt.stream;
+  AllocScope scope(&H->o);  // setup temporaries through the same allocator
   H->n = (int)n;
   H->m = m;
   auto t0 = std::chrono::steady_clock::now();
@@ -546,7 +551,7 @@ void lamg_free(lamg_handle h) {
   drop_graphs(H);
   mv_release(H);
   if (H->cs) (void)hipStreamDestroy(H->cs);
-  for (void* p : H->owned) (void)hipFree(p);
+  for (void* p : H->owned) dev_free(H->o, p);
   if (H->hred) (void)hipHostFree(H->hred);
   delete h;
 }

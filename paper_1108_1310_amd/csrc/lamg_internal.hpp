@@ -165,8 +165,14 @@ struct MVWork {
   std::vector<double> rel, removed;
 };
 
-struct Hierarchy {
+inline lamg_options options_defaults() {
   lamg_options o;
+  lamg_options_default(&o);
+  return o;
+}
+
+struct Hierarchy {
+  lamg_options o = options_defaults();
   hipStream_t s = nullptr;
   int n = 0;
   int64_t m = 0;
@@ -225,6 +231,16 @@ void prof_flush();
 void set_last_error(const char* where, hipError_t e);
 
 // ------------------------------------------------------------- allocation
+// Device memory through the options' allocator (hipMalloc / hipFree when
+// none is set); dev_alloc throws DevError{hipErrorOutOfMemory} on failure.
+void* dev_alloc(const lamg_options& o, size_t bytes);
+void dev_free(const lamg_options& o, void* p);
+// The allocator of the setup running on this thread (for its temporaries).
+struct AllocScope {
+  const lamg_options* prev;
+  explicit AllocScope(const lamg_options* o);
+  ~AllocScope();
+};
 void* dalloc(Hierarchy* H, size_t bytes);
 template <class T>
 T* dnew(Hierarchy* H, size_t count) { return (T*)dalloc(H, count * sizeof(T) + 16); }

@@ -617,7 +617,7 @@ void mv_drop_graphs(Hierarchy* H) {
 void mv_release(Hierarchy* H) {
   MVWork& W = H->mv;
   mv_drop_graphs(H);
-  for (void* p : W.owned) (void)hipFree(p);
+  for (void* p : W.owned) dev_free(H->o, p);
   if (W.hres) (void)hipHostFree(W.hres);
   if (W.hmask) (void)hipHostFree(W.hmask);
   W = MVWork();
@@ -631,8 +631,7 @@ void mv_alloc(Hierarchy* H, int k) {
   else LAMG_HIP(hipDeviceSynchronize());
   mv_release(H);
   auto A = [&](size_t bytes) {
-    void* p = nullptr;
-    LAMG_HIP(hipMalloc(&p, bytes + 16));
+    void* p = dev_alloc(H->o, bytes + 16);
     W.owned.push_back(p);
     return p;
   };

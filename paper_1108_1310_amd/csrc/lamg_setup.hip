@@ -18,23 +18,43 @@
 
 namespace lamg {
 
-void* dalloc(Hierarchy* H, size_t bytes) {
+void* dev_alloc(const lamg_options& o, size_t bytes) {
   void* p = nullptr;
-  if (hipMalloc(&p, std::max<size_t>(bytes, 16)) != hipSuccess) throw DevError{hipErrorOutOfMemory};
+  bytes = std::max<size_t>(bytes, 16);
+  if (o.alloc) p = o.alloc(bytes, o.alloc_ctx);
+  else if (hipMalloc(&p, bytes) != hipSuccess) p = nullptr;
+  if (!p) throw DevError{hipErrorOutOfMemory};
+  return p;
+}
+void dev_free(const lamg_options& o, void* p) {
+  if (!p) return;
+  if (o.dealloc) o.dealloc(p, o.alloc_ctx);
+  else (void)hipFree(p);
+}
+
+namespace {
+thread_local const lamg_options* t_scope_alloc = nullptr;
+}  // namespace
+AllocScope::AllocScope(const lamg_options* o) : prev(t_scope_alloc) { t_scope_alloc = o; }
+AllocScope::~AllocScope() { t_scope_alloc = prev; }
+
+void* dalloc(Hierarchy* H, size_t bytes) {
+  void* p = dev_alloc(H->o, bytes);
   H->owned.push_back(p);
   return p;
 }
 
 namespace {
 
-// Temporary device buffers of one setup step, released at scope exit.
+// Temporary device buffers of one setup step, released at scope exit, through
+// the allocator of the setup running on this thread.
 struct Tmp {
+  lamg_options o = t_scope_alloc ? *t_scope_alloc : options_defaults();
   std::vector<void*> ps;
-  ~Tmp() { for (void* p : ps) (void)hipFree(p); }
+  ~Tmp() { for (void* p : ps) dev_free(o, p); }
   template <class T>
   T* get(size_t count) {
-    void* p = nullptr;
-    if (hipMalloc(&p, std::max<size_t>(count * sizeof(T), 16)) != hipSuccess) throw DevError{hipErrorOutOfMemory};
+    void* p = dev_alloc(o, count * sizeof(T));
     ps.push_back(p);
     return (T*)p;
   }

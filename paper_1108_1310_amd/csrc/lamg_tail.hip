@@ -992,8 +992,7 @@ void tail_prepare_mv(Hierarchy* H) {
     t.x32 = f.x; t.b32 = f.b; t.r32 = f.r;
     for (int i = 0; i < 2; ++i) { t.X64[i] = a.X[i]; t.R64[i] = a.R[i]; t.X32[i] = f.X[i]; t.R32[i] = f.R[i]; }
   }
-  void* p = nullptr;
-  LAMG_HIP(hipMalloc(&p, d.size() * sizeof(TailLevel)));
+  void* p = dev_alloc(H->o, d.size() * sizeof(TailLevel));
   W.owned.push_back(p);
   LAMG_HIP(hipMemcpy(p, d.data(), d.size() * sizeof(TailLevel), hipMemcpyHostToDevice));
   W.tail = (TailLevel*)p;
@@ -1225,13 +1224,14 @@ lamg_status solve_graphs(int count, Hierarchy* const* hs, const double* const* B
   }
   // device copies: graphs (one copy per LDS budget), orders, queue, results
   const size_t gb = (size_t)count * sizeof(BatchGraph);
-  char* buf = nullptr;
   const size_t bytes = 2 * gb + 2 * (size_t)count * sizeof(int) + 256 + (size_t)count * sizeof(BatchOut);
-  LAMG_HIP(hipMalloc((void**)&buf, bytes));
+  const lamg_options& ao = hs[0]->o;  // the call's buffers through the first handle's allocator
+  char* buf = (char*)dev_alloc(ao, bytes);
   struct Free {
+    const lamg_options& o;
     char* p;
-    ~Free() { (void)hipFree(p); }
-  } guard{buf};
+    ~Free() { dev_free(o, p); }
+  } guard{ao, buf};
   BatchGraph* dG[2] = {(BatchGraph*)buf, (BatchGraph*)(buf + gb)};
   int* dorder[2] = {(int*)(buf + 2 * gb), (int*)(buf + 2 * gb) + count};
   int* queue = (int*)(buf + 2 * gb + 2 * (size_t)count * sizeof(int));

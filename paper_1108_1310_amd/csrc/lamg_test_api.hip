@@ -24,7 +24,7 @@ struct Scratch {
   Hierarchy H;
   ~Scratch() {
     (void)hipStreamSynchronize(H.s);
-    for (void* p : H.owned) (void)hipFree(p);
+    for (void* p : H.owned) dev_free(H.o, p);
   }
 };
 Level borrowed_level(Scratch& S, int n, const int32_t* rp, const int32_t* ci, int ncol, const int32_t* cptr) {

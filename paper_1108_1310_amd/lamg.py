@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import sys
 
 import numpy as np
 import torch
@@ -21,6 +22,11 @@ FP64, FP32_REFINE = 0, 1
 EC_RECOMBINE, EC_FLAT_MU = 0, 1
 
 
+# Device allocator hooks of lamg_options (alloc(bytes, ctx) -> ptr, dealloc(ptr, ctx)).
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+DEALLOC_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
 class Options(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("gamma", C.c_double), ("nu_pre", C.c_int), ("nu_post", C.c_int),
                 ("tv_k_min", C.c_int), ("tv_k_max", C.c_int), ("tv_sweeps", C.c_int),
@@ -30,7 +36,8 @@ class Options(C.Structure):
                 ("relax_fast_ratio", C.c_double), ("coarsest_sweeps", C.c_int), ("dense_max", C.c_int),
                 ("tail_max_n", C.c_int),
                 ("ec", C.c_int), ("precision", C.c_int), ("tol", C.c_double), ("max_cycles", C.c_int),
-                ("warm_start", C.c_int), ("seed", C.c_uint64), ("stream", C.c_void_p)]
+                ("warm_start", C.c_int), ("seed", C.c_uint64), ("stream", C.c_void_p),
+                ("alloc", ALLOC_FN), ("dealloc", DEALLOC_FN), ("alloc_ctx", C.c_void_p)]
 
 
 class Info(C.Structure):
@@ -133,16 +140,50 @@ def _dev(t, dtype):
     return t.to(device="cuda", dtype=dtype).contiguous()
 
 
+class TorchAllocator:
+    """Device memory of hierarchies from torch's caching allocator (blocks on
+    the current stream, 512-byte aligned), through the allocator hooks of
+    lamg_options.  Keeps the callbacks alive and counts the live blocks."""
+
+    def __init__(self):
+        self.live = {}
+        self.allocs = 0
+        self.frees = 0
+
+        def _alloc(nbytes, ctx):
+            try:
+                p = int(torch.cuda.caching_allocator_alloc(int(nbytes)))
+            except RuntimeError:
+                return None
+            self.live[p] = int(nbytes)
+            self.allocs += 1
+            return p
+
+        def _dealloc(ptr, ctx):
+            self.live.pop(int(ptr), None)
+            self.frees += 1
+            torch.cuda.caching_allocator_delete(int(ptr))
+
+        self.c_alloc = ALLOC_FN(_alloc)
+        self.c_dealloc = DEALLOC_FN(_dealloc)
+
+
 class Hierarchy:
     """A LAMG hierarchy of the Laplacian of a weighted undirected graph.
 
     ``eu, ev`` (int32) and ``w`` (float64) describe the edges (any order;
     duplicates of a pair are summed).  Arrays are moved to the GPU if needed.
+    ``allocator``: a TorchAllocator to take the hierarchy's device memory
+    from torch's caching allocator (default: the library's hipMalloc).
     """
 
-    def __init__(self, n: int, eu, ev, w, **opts):
+    def __init__(self, n: int, eu, ev, w, allocator: "TorchAllocator" = None, **opts):
         eu, ev, w = _dev(eu, torch.int32), _dev(ev, torch.int32), _dev(w, torch.float64)
         self.opts = options(stream=_stream(), **opts)
+        self._allocator = allocator
+        if allocator is not None:
+            self.opts.alloc = allocator.c_alloc
+            self.opts.dealloc = allocator.c_dealloc
         h = C.c_void_p()
         rc = lib().lamg_setup(int(n), int(eu.numel()), _ptr(eu), _ptr(ev), _ptr(w), C.byref(self.opts), C.byref(h))
         _check(rc, "lamg_setup")
@@ -156,11 +197,15 @@ class Hierarchy:
             self.h = None
 
     def __del__(self):
-        # at interpreter exit the module globals may already be gone; the
-        # process teardown releases device memory then
-        if _lib is not None and getattr(self, "h", None):
-            _lib.lamg_free(self.h)
-            self.h = None
+        # at interpreter exit the module globals (or torch, for a hierarchy on
+        # torch's allocator) may already be gone; the process teardown
+        # releases device memory then
+        if _lib is None or not getattr(self, "h", None):
+            return
+        if getattr(self, "_allocator", None) is not None and sys.is_finalizing():
+            return
+        _lib.lamg_free(self.h)
+        self.h = None
 
     def set_solve_options(self, **kw):
         for k, v in kw.items():

@@ -48,6 +48,13 @@ def test_host_only_entry_points():
     bad.struct_size = 3
     assert L.lamg_setup(4, 0, None, None, None, ctypes.byref(bad), ctypes.byref(h)) == lamg.E_INVALID_ARG
     assert L.lamg_setup(4, 3, None, None, None, None, ctypes.byref(h)) == lamg.E_INVALID_ARG
+    # allocator hooks: both or neither
+    half = lamg.options()
+    half.alloc = lamg.ALLOC_FN(lambda nbytes, ctx: None)
+    assert L.lamg_setup(4, 0, None, None, None, ctypes.byref(half), ctypes.byref(h)) == lamg.E_INVALID_ARG
+    half = lamg.options()
+    half.dealloc = lamg.DEALLOC_FN(lambda ptr, ctx: None)
+    assert L.lamg_setup(4, 0, None, None, None, ctypes.byref(half), ctypes.byref(h)) == lamg.E_INVALID_ARG
     assert h.value is None
     L.lamg_free(None)  # no-op
     # batch launch configuration: only -1 (autotune) and 0..3
