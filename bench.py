@@ -93,10 +93,11 @@ def timed_solves(H, b, precision, steps, warmup, lamg, instrument=False):
     torch.cuda.synchronize()
     kid = 0 if precision == lamg.FP64 else 2
     lamg.prof_enable(instrument)
-    cycles, byts, worst = 0, 0, 0.0
+    cycles, byts, worst, acf = 0, 0, 0.0, 0.0
     t0 = time.perf_counter()
     for _ in range(steps):
         x, info = H.solve(b)
+        acf = info["acf"]
         cycles += info["cycles"]
         byts += info["bytes_moved"]
         worst = max(worst, info["rel_residual"])
@@ -107,7 +108,28 @@ def timed_solves(H, b, precision, steps, warmup, lamg, instrument=False):
     prof = lamg.prof_read(kid)
     hub = lamg.prof_read(8 if precision == lamg.FP64 else 9)
     lamg.prof_enable(False)
-    return dict(seconds=dt, cycles=cycles, bytes=byts, rel_residual=worst, prof=prof, hub=hub, x=x)
+    return dict(seconds=dt, cycles=cycles, bytes=byts, rel_residual=worst, acf=acf, prof=prof, hub=hub, x=x)
+
+
+def mvm_time_us(H, lamg, reps=20):
+    """Time of one finest-level FP64 matrix-vector product (r = b - A x over
+    the finest CSR, the residual kernel of the solve), the paper's work unit
+    (Section 5.1): kernel time from the instrumentation spans."""
+    import torch
+    L = H.level(0)
+    d = lambda a, t=torch.float64: torch.tensor(a, dtype=t, device="cuda")
+    rp, ci, val, dg = d(L["rp"], torch.int32), d(L["ci"], torch.int32), d(L["val"]), d(L["diag"])
+    x = torch.randn(H.n, dtype=torch.float64, device="cuda")
+    bb = torch.randn(H.n, dtype=torch.float64, device="cuda")
+    lamg.residual(rp, ci, val, dg, bb, x)
+    torch.cuda.synchronize()
+    lamg.prof_enable(True)
+    for _ in range(reps):
+        lamg.residual(rp, ci, val, dg, bb, x)
+    torch.cuda.synchronize()
+    p = lamg.prof_read(1)
+    lamg.prof_enable(False)
+    return 1e3 * p["ms"] / max(1, p["launches"])
 
 
 def timed_multi(H, B, precision, steps, warmup, lamg, instrument=False):
@@ -443,6 +465,20 @@ def main():
         roofline["hub_sweep"] = {"ms_per_step": hb["ms"] / a.steps, "launches": hb["launches"],
                                  "gbps": hb["bytes"] / (hb["ms"] * 1e6),
                                  "share_of_step": hb["ms"] / (i64["seconds"] * 1e3)}
+    mvm_us = mvm_time_us(H, lamg)
+    ms64 = r64["seconds"] * 1e3 / a.steps
+    digits = -math.log10(max(r64["rel_residual"], 1e-300))
+    mvm = {"mvm_us": mvm_us, "solve_mvm": 1e3 * ms64 / mvm_us,
+           "solve_mvm_per_digit": 1e3 * ms64 / mvm_us / digits, "digits": digits}
+    vcyc = None
+    if a.workload == "grid2d_64":
+        # the literal V(1,2) cycle (gamma = 1) beside the paper's gamma = 1.5
+        Hv = lamg.Hierarchy(g.n, g.eu, g.ev, g.w, gamma=1.0)
+        rv = timed_solves(Hv, bd, lamg.FP64, a.steps, a.warmup, lamg)
+        vcyc = {"gamma": 1.0, "value": g.m * rv["cycles"] / rv["seconds"],
+                "ms_per_step": rv["seconds"] * 1e3 / a.steps, "cycles_per_solve": rv["cycles"] / a.steps,
+                "acf": rv["acf"], "rel_residual": rv["rel_residual"]}
+        Hv.close()
     adj = None
     if a.workload == "rgg_2p20":
         adj = adjoint_step(g, b, a.steps, a.warmup)
@@ -469,8 +505,11 @@ def main():
                    "levels": len(levels), "setup_ms": setup_ms},
         "gbps": r64["bytes"] / r64["seconds"] / 1e9,
         "cycles_per_solve": r64["cycles"] / a.steps,
+        "acf": r64["acf"],
         "rel_residual": r64["rel_residual"],
         "edges_solved_per_s": g.m * a.steps / r64["seconds"],
+        "mvm_units": mvm,
+        "v_cycle": vcyc,
         "fp32_refine": out32,
         "adjoint": adj,
         "roofline": roofline,
