@@ -349,16 +349,50 @@ CPU_MIN_S = 10.0  # timed oracle solve work per baseline (right-hand sides added
 
 def _oracle_rhs_loop(H, g, rhs, max_solves):
     """Solve seeded right-hand sides rhs(j) one after another on the oracle
-    hierarchy until CPU_MIN_S of solve time (or max_solves); setup untimed."""
-    dt, cyc, k = 0.0, 0, 0
+    hierarchy until CPU_MIN_S of solve time (or max_solves); setup untimed.
+    Returns the solve time, cycles, solves and mean digits gained."""
+    dt, cyc, k, dig = 0.0, 0, 0, 0.0
     while dt < CPU_MIN_S and k < max_solves:
         b = rhs(k)
         t0 = time.perf_counter()
         x, info, _ = H.solve(b)
         dt += time.perf_counter() - t0
         cyc += info["cycles"]
+        dig += -math.log10(max(info["rel_residual"], 1e-300))
         k += 1
-    return dt, cyc, k
+    return dt, cyc, k, dig / max(1, k)
+
+
+def host_cpu():
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"model": model, "nproc": os.cpu_count()}
+
+
+def copy_ceiling_gbps():
+    """Measured device-copy bandwidth (1 GiB read + 1 GiB written per copy):
+    the practical HBM ceiling beside the 8 TB/s spec."""
+    import torch
+    a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbps = 2 * a.numel() * 8 * 5 / (e0.elapsed_time(e1) * 1e6)
+    del a, b
+    torch.cuda.empty_cache()
+    return gbps
 
 
 def cpu_baseline(name):
@@ -381,7 +415,7 @@ def cpu_baseline(name):
         sample = (f"the first 24 graphs of the batch, {k} right-hand side(s) each, FP64 solves to 1e-8 one after "
                   "another, 1 thread (setup not timed)")
         return {"value": ec / dt, "unit": "edges*cycles/s", "cores": 1, "kind": "oracle", "sample": sample,
-                "solve_s": dt}
+                "solve_s": dt, "host": host_cpu()}
     if name == "chung_lu_2p20":
         g = W.chung_lu(1 << 19)
         seed, what, cap = W.SEEDS["chung_lu"], "Chung-Lu recipe at n0 = 2^19 (half the workload)", 64
@@ -394,11 +428,23 @@ def cpu_baseline(name):
     else:
         g, _ = W.config(name)
         seed, what, cap = 0, "full workload", 4096
+    t0 = time.perf_counter()
     H = O.Hierarchy(g.n, g.eu, g.ev, g.w)
-    dt, cyc, k = _oracle_rhs_loop(H, g, lambda j: W.rhs_normal(g.n, 1, seed + 7919 * j), cap)
+    setup_s = time.perf_counter() - t0
+    dt, cyc, k, dig = _oracle_rhs_loop(H, g, lambda j: W.rhs_normal(g.n, 1, seed + 7919 * j), cap)
+    # the oracle's finest-level matrix-vector product (its residual), the paper's work unit
+    A0 = H.level(0).A
+    xr, br = W.rhs_normal(g.n, 1, seed + 1), W.rhs_normal(g.n, 1, seed + 2)
+    O.residual(A0, br, xr)
+    t0 = time.perf_counter()
+    for _ in range(5):
+        O.residual(A0, br, xr)
+    mvm_s = (time.perf_counter() - t0) / 5
     sample = f"{what}, {k} seeded right-hand side(s) solved one after another, FP64 to 1e-8, 1 thread (setup not timed)"
     return {"value": g.m * cyc / dt, "unit": "edges*cycles/s", "cores": 1, "kind": "oracle", "sample": sample,
-            "cycles": cyc, "solves": k, "solve_s": dt, "edges": g.m}
+            "cycles": cyc, "solves": k, "solve_s": dt, "edges": g.m, "host": host_cpu(),
+            "setup_s": setup_s, "mvm_ms": mvm_s * 1e3, "setup_mvm": setup_s / mvm_s,
+            "solve_mvm_per_digit": dt / k / mvm_s / dig}
 
 
 def main():
@@ -469,7 +515,11 @@ def main():
     ms64 = r64["seconds"] * 1e3 / a.steps
     digits = -math.log10(max(r64["rel_residual"], 1e-300))
     mvm = {"mvm_us": mvm_us, "solve_mvm": 1e3 * ms64 / mvm_us,
-           "solve_mvm_per_digit": 1e3 * ms64 / mvm_us / digits, "digits": digits}
+           "solve_mvm_per_digit": 1e3 * ms64 / mvm_us / digits, "digits": digits,
+           "setup_mvm": 1e3 * setup_ms / mvm_us}
+    ceil = copy_ceiling_gbps()
+    roofline["copy_ceiling_gbps"] = ceil
+    roofline["frac_of_copy"] = achieved / ceil if achieved is not None else None
     vcyc = None
     if a.workload == "grid2d_64":
         # the literal V(1,2) cycle (gamma = 1) beside the paper's gamma = 1.5
