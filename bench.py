@@ -58,19 +58,21 @@ def copy_calibration(nbytes):
 # counters on a plain copy; valid only while the kernel source is unchanged.
 TRAFFIC = {
     # profiles/gs_fp64_chung_lu_2p20.md: FETCH_SIZE 16412.1 KiB x 1.9999 + WRITE_SIZE 333.1 KiB x 1.0000
-    "chung_lu_2p20": {"bytes_per_launch": 33952095, "kernel_sha": "ab1773a00a985b16"},
+    "chung_lu_2p20": {"bytes_per_launch": 33952095, "kernel_sha": "ab1773a00a985b16", "source": "lamg_relax.hpp"},
+    # profiles/mv_grid3d_128_k32.md: k_relax_mv<float, 0, 4>, FETCH_SIZE 7109.5 KiB x 1.9999 + WRITE_SIZE 1625.6 KiB x 1.0
+    "grid3d_128_k32": {"bytes_per_launch": 16224387, "kernel_sha": "517cf84af9f72bb0", "source": "lamg_mv.hip"},
 }
 
 
-def kernel_source_hash():
+def kernel_source_hash(name="lamg_relax.hpp"):
     import hashlib
-    src = os.path.join(ROOT, "paper_1108_1310_amd", "csrc", "lamg_relax.hpp")
+    src = os.path.join(ROOT, "paper_1108_1310_amd", "csrc", name)
     return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
 
 
 def recorded_traffic(workload):
     t = TRAFFIC.get(workload)
-    if not t or t["kernel_sha"] != kernel_source_hash():
+    if not t or t["kernel_sha"] != kernel_source_hash(t["source"]):
         return None
     return t["bytes_per_launch"]
 
@@ -183,7 +185,7 @@ def main_multi(a, g, B):
     p = i32["prof"]
     achieved = p["bytes"] / (p["ms"] * 1e6) if p["ms"] > 0 else 0.0
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic(a.workload),
                 "kernel": "k_relax_mv<float,0,4> (multi-vector multicolour GS, FP32)",
                 "avg_launch_us": 1e3 * p["ms"] / max(1, p["launches"]), "launches": p["launches"],
                 "bytes_per_launch": p["bytes"] / max(1, p["launches"]),
