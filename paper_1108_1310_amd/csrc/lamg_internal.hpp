@@ -51,7 +51,8 @@ constexpr int ROW_CHUNK = 512;
 // workgroup with the hubs' x in LDS and only the hub-to-hub entries left to
 // gather (k_hub_sweep).  Taken when the hub rows are at most HUB_MAX_ROWS,
 // at least HUB_MIN_COLOURS colours are hub colours, and the chunk table has
-// at most HUB_MAX_CHUNKS entries.
+// at most HUB_MAX_CHUNKS entries; the split point follows the cost model
+// below.
 constexpr int HUB_MAX_ROWS = 4096;
 constexpr int HUB_MIN_COLOURS = 8;
 constexpr int HUB_THREADS = 1024;
@@ -59,6 +60,13 @@ constexpr int HUB_PER = 4;                          // entries per thread per ch
 constexpr int HUB_CHUNK = HUB_THREADS * HUB_PER;    // products staged per chunk
 static_assert(HUB_CHUNK >= HUB_MAX_ROWS, "a hub row's hub-to-hub entries fit one chunk");
 constexpr int HUB_MAX_CHUNKS = 1024;
+// The split point: from the first colour whose classes onwards hold at most
+// HUB_MAX_ROWS rows, the later start that minimises the sweep's modelled
+// time, in tenths of a microsecond as measured on MI355X (FP64): a launch of
+// a small colour class about 10 us, a hub-sweep chunk about 1.8 us.  A later
+// start launches more colours but leaves fewer hub-to-hub entries.
+constexpr int HUB_COST_LAUNCH = 100;
+constexpr int HUB_COST_CHUNK = 18;
 
 struct Tiles {
   int64_t rows = 0, nnz = 0;  // rows and entries covered (algorithmic bytes per launch)

@@ -1281,22 +1281,88 @@ __global__ void k_hub_fill(int nh, int r0, const int* __restrict__ rp, const int
 }
 }  // namespace
 
+// Chunks of whole rows of one colour, at most HUB_CHUNK hub-to-hub entries
+// each, over the hub colours [K, nc); hr: hub row pointers (local rows from
+// the first hub row).  Returns the chunk count; appends the chunks if out.
+static int hub_chunks(const Level& L, int K, int r0, const std::vector<int>& hr, std::vector<int2>* out) {
+  int count = 0;
+  for (int c = K; c < L.ncol; ++c) {
+    const int a = L.cptr[c] - r0, z = L.cptr[c + 1] - r0;
+    int first = a;
+    for (int u = a; u < z; ++u)
+      if (hr[u + 1] - hr[first] > HUB_CHUNK) {
+        if (out) out->push_back(make_int2(first, u));
+        ++count;
+        first = u;
+      }
+    if (out) out->push_back(make_int2(first, z));
+    ++count;
+  }
+  return count;
+}
+
 void build_hub(Hierarchy* H, Level& L) {
   L.hub_k = -1;
   const int n = L.n, nc = L.ncol;
   if (n <= HUB_MAX_ROWS || nc < HUB_MIN_COLOURS || (int)L.cptr.size() != nc + 1) return;
-  // the smallest K >= 1 whose colours >= K hold at most HUB_MAX_ROWS rows
-  int K = nc;
+  // K0: the smallest K >= 1 whose colours >= K hold at most HUB_MAX_ROWS rows
+  int K0 = nc;
   for (int c = nc - 1; c >= 1; --c) {
     if (n - L.cptr[c] > HUB_MAX_ROWS) break;
-    K = c;
+    K0 = c;
   }
-  if (nc - K < HUB_MIN_COLOURS) return;
+  if (nc - K0 < HUB_MIN_COLOURS) return;
   hipStream_t s = H->s;
   Tmp tmp;
+  // hub-to-hub columns of the rows >= cptr[K0] (a later split keeps a suffix
+  // of each row), to price every admissible split on the host
+  auto count_fill = [&](int r0, int nh, int* hrp, int** hci_out, int* hnnz_out) {
+    int* cnt = tmp.get<int>(nh + 1);
+    hipLaunchKernelGGL(k_hub_count, grid1(nh), dim3(256), 0, s, nh, r0, (const int*)L.rp, (const int*)L.ci, cnt);
+    excl_scan(s, tmp, cnt, hrp, nh);
+    *hnnz_out = to_host(s, hrp + nh);
+    *hci_out = tmp.get<int>(std::max(*hnnz_out, 1));
+  };
+  int K = K0;
+  {
+    const int r0 = L.cptr[K0], nh = n - r0;
+    int* hrp0 = tmp.get<int>(nh + 1);
+    int* hci0 = nullptr;
+    int hnnz0 = 0;
+    count_fill(r0, nh, hrp0, &hci0, &hnnz0);
+    double* hv0 = tmp.get<double>(std::max(hnnz0, 1));
+    float* hv32_0 = tmp.get<float>(std::max(hnnz0, 1));
+    hipLaunchKernelGGL(k_hub_fill, dim3((unsigned)(((int64_t)nh * 64 + 255) / 256)), dim3(256), 0, s, nh, r0,
+                       (const int*)L.rp, (const int*)L.ci, (const double*)L.val, (const float*)L.val32,
+                       (const int*)hrp0, hci0, hv0, hv32_0);
+    std::vector<int> hr0(nh + 1), hc0(std::max(hnnz0, 1));
+    LAMG_HIP(hipMemcpyAsync(hr0.data(), hrp0, (size_t)(nh + 1) * sizeof(int), hipMemcpyDeviceToHost, s));
+    LAMG_HIP(hipMemcpyAsync(hc0.data(), hci0, (size_t)std::max(hnnz0, 1) * sizeof(int), hipMemcpyDeviceToHost, s));
+    LAMG_HIP(hipStreamSynchronize(s));
+    // cost of split K2: its extra launched colours plus the chunks of the
+    // hub sweep (hub rows' columns are sorted: the entries into colours
+    // >= K2 are each row's suffix)
+    int64_t best = -1;
+    std::vector<int> hr2;
+    for (int K2 = K0; nc - K2 >= HUB_MIN_COLOURS; ++K2) {
+      const int d = L.cptr[K2] - r0, nh2 = nh - d;
+      hr2.assign(nh2 + 1, 0);
+      for (int u = 0; u < nh2; ++u) {
+        const int* b0 = hc0.data() + hr0[d + u];
+        const int* b1 = hc0.data() + hr0[d + u + 1];
+        hr2[u + 1] = hr2[u] + (int)(b1 - std::lower_bound(b0, b1, d));
+      }
+      const int64_t cost = (int64_t)(K2 - K0) * HUB_COST_LAUNCH +
+                           (int64_t)hub_chunks(L, K2, L.cptr[K2], hr2, nullptr) * HUB_COST_CHUNK;
+      if (best < 0 || cost < best) {
+        best = cost;
+        K = K2;
+      }
+    }
+  }
   const int r0 = L.cptr[K], nh = n - r0;
-  int* cnt = tmp.get<int>(nh + 1);
   int* hrp = dnew<int>(H, (size_t)nh + 1);
+  int* cnt = tmp.get<int>(nh + 1);
   hipLaunchKernelGGL(k_hub_count, grid1(nh), dim3(256), 0, s, nh, r0, (const int*)L.rp, (const int*)L.ci, cnt);
   excl_scan(s, tmp, cnt, hrp, nh);
   const int hnnz = to_host(s, hrp + nh);
@@ -1306,21 +1372,11 @@ void build_hub(Hierarchy* H, Level& L) {
   hipLaunchKernelGGL(k_hub_fill, dim3((unsigned)(((int64_t)nh * 64 + 255) / 256)), dim3(256), 0, s, nh, r0,
                      (const int*)L.rp, (const int*)L.ci, (const double*)L.val, (const float*)L.val32, (const int*)hrp,
                      hci, hv, hv32);
-  // chunks of whole rows of one colour, at most HUB_CHUNK entries each
   std::vector<int> hr(nh + 1);
   LAMG_HIP(hipMemcpyAsync(hr.data(), hrp, (size_t)(nh + 1) * sizeof(int), hipMemcpyDeviceToHost, s));
   LAMG_HIP(hipStreamSynchronize(s));
   std::vector<int2> ck;
-  for (int c = K; c < nc; ++c) {
-    const int a = L.cptr[c] - r0, z = L.cptr[c + 1] - r0;
-    int first = a;
-    for (int u = a; u < z; ++u)
-      if (hr[u + 1] - hr[first] > HUB_CHUNK) {
-        ck.push_back(make_int2(first, u));
-        first = u;
-      }
-    ck.push_back(make_int2(first, z));
-  }
+  hub_chunks(L, K, r0, hr, &ck);
   if ((int)ck.size() > HUB_MAX_CHUNKS) return;  // (the device arrays stay with the handle, unused)
   L.hub_ck = dnew<int2>(H, ck.size());
   LAMG_HIP(hipMemcpyAsync(L.hub_ck, ck.data(), ck.size() * sizeof(int2), hipMemcpyHostToDevice, s));

@@ -34,23 +34,55 @@ def chung_lu(n0):
     return _G[n0]
 
 
+HUB_CHUNK, HUB_COST_LAUNCH, HUB_COST_CHUNK = 4096, 100, 18
+
+
+def _hub_counts(ptr, col, r0, n):
+    """Per row of [r0, n): entries into columns >= r0."""
+    return np.array([int(np.count_nonzero(col[ptr[u]:ptr[u + 1]] >= r0)) for u in range(r0, n)], np.int64)
+
+
+def _chunks(cptr, K, cnt):
+    """Chunks of whole rows of one colour with at most HUB_CHUNK entries."""
+    r0 = int(cptr[K])
+    hr = np.concatenate([[0], np.cumsum(cnt)])
+    total = 0
+    for c in range(K, len(cptr) - 1):
+        a, z = int(cptr[c]) - r0, int(cptr[c + 1]) - r0
+        first = a
+        for u in range(a, z):
+            if hr[u + 1] - hr[first] > HUB_CHUNK:
+                total += 1
+                first = u
+        total += 1
+    return total
+
+
 def expected_split(cptr, A):
-    """The split rule: the smallest K >= 1 whose colours >= K hold at most
-    HUB_MAX_ROWS rows, taken with at least HUB_MIN_COLOURS hub colours; the
+    """The split rule: K0 = the smallest K >= 1 whose colours >= K hold at
+    most HUB_MAX_ROWS rows (at least HUB_MIN_COLOURS hub colours needed);
+    then the K >= K0 (keeping HUB_MIN_COLOURS hub colours) minimising
+    (K - K0) launches + chunks, priced 100 / 18 (ties: the smallest K).  The
     hub-to-hub entries are those of rows >= cptr[K] into columns >= cptr[K]."""
     nc = len(cptr) - 1
     n = int(cptr[-1])
     if n <= HUB_MAX_ROWS or nc < HUB_MIN_COLOURS:
         return None
-    K = nc
+    K0 = nc
     for c in range(nc - 1, 0, -1):
         if n - cptr[c] > HUB_MAX_ROWS:
             break
-        K = c
-    if nc - K < HUB_MIN_COLOURS:
+        K0 = c
+    if nc - K0 < HUB_MIN_COLOURS:
         return None
-    r0 = int(cptr[K])
     ptr, col = np.asarray(A.ptr), np.asarray(A.col)
+    best, K = None, K0
+    for K2 in range(K0, nc - HUB_MIN_COLOURS + 1):
+        r2 = int(cptr[K2])
+        cost = (K2 - K0) * HUB_COST_LAUNCH + _chunks(cptr, K2, _hub_counts(ptr, col, r2, n)) * HUB_COST_CHUNK
+        if best is None or cost < best:
+            best, K = cost, K2
+    r0 = int(cptr[K])
     nnz = int(np.count_nonzero(col[ptr[r0]:ptr[n]] >= r0))
     return dict(k=K, r0=r0, n=n - r0, nnz=nnz)
 
