@@ -55,10 +55,13 @@ def copy_calibration(nbytes):
 
 # HBM traffic of the relaxation kernel from hardware counters (rocprofv3
 # --pmc FETCH_SIZE, then WRITE_SIZE, on this benchmark), scaled by the same
-# counters on a plain copy; valid only while the kernel source is unchanged.
+# counters on a plain copy; valid only while the kernel source is unchanged
+# and, where recorded, the levels split their colours at the same hub colour
+# (the split sets which colours the kernel's launches cover).
 TRAFFIC = {
-    # profiles/gs_fp64_chung_lu_2p20.md: FETCH_SIZE 16412.1 KiB x 1.9999 + WRITE_SIZE 333.1 KiB x 1.0000
-    "chung_lu_2p20": {"bytes_per_launch": 33952095, "kernel_sha": "ab1773a00a985b16", "source": "lamg_relax.hpp"},
+    # profiles/gs_fp64_chung_lu_2p20.md: FETCH_SIZE 12666.3 KiB x 1.9999 + WRITE_SIZE 224.2 KiB x 1.0000
+    "chung_lu_2p20": {"bytes_per_launch": 26169316, "kernel_sha": "ab1773a00a985b16", "source": "lamg_relax.hpp",
+                      "hub_split": [24, 27]},
     # profiles/mv_grid3d_128_k32.md: k_relax_mv<float, 0, 4>, FETCH_SIZE 7109.5 KiB x 1.9999 + WRITE_SIZE 1625.6 KiB x 1.0
     "grid3d_128_k32": {"bytes_per_launch": 16224387, "kernel_sha": "517cf84af9f72bb0", "source": "lamg_mv.hip"},
 }
@@ -70,9 +73,11 @@ def kernel_source_hash(name="lamg_relax.hpp"):
     return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
 
 
-def recorded_traffic(workload):
+def recorded_traffic(workload, H):
     t = TRAFFIC.get(workload)
     if not t or t["kernel_sha"] != kernel_source_hash(t["source"]):
+        return None
+    if "hub_split" in t and [H.hub_info(l)["k"] for l in range(H.num_levels)] != t["hub_split"]:
         return None
     return t["bytes_per_launch"]
 
@@ -185,7 +190,7 @@ def main_multi(a, g, B):
     p = i32["prof"]
     achieved = p["bytes"] / (p["ms"] * 1e6) if p["ms"] > 0 else 0.0
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic(a.workload),
+                "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic(a.workload, H),
                 "kernel": "k_relax_mv<float,0,4> (multi-vector multicolour GS, FP32)",
                 "avg_launch_us": 1e3 * p["ms"] / max(1, p["launches"]), "launches": p["launches"],
                 "bytes_per_launch": p["bytes"] / max(1, p["launches"]),
@@ -500,7 +505,7 @@ def main():
     achieved = p["bytes"] / (p["ms"] * 1e6) if p["ms"] > 0 else None
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS if achieved is not None else None,
-                "traffic": recorded_traffic(a.workload),
+                "traffic": recorded_traffic(a.workload, H),
                 "kernel": "k_relax<double,0> (multicolour GS)" if achieved is not None else
                           "none: every level runs in the single-workgroup tail (latency-bound)",
                 "avg_launch_us": 1e3 * p["ms"] / max(1, p["launches"]), "launches": p["launches"],
