@@ -53,7 +53,7 @@ __global__ void k_add_f32(int n, const float* __restrict__ e, double* __restrict
 }
 // mean of a device vector into reduction slot `slot` (device side only)
 void mean_to_slot(hipStream_t s, Hierarchy* H, const double* x, int n, int slot) {
-  sum_to_slot(s, H, x, n, slot, 1.0 / (double)n);
+  sum_to_slot(s, H, x, n, slot, (double)n);
 }
 double* res_slots(Hierarchy* H) { return H->red + k::RED_BLOCKS * 8; }
 

@@ -290,7 +290,7 @@ template <class T>
 void subtract_mean(hipStream_t s, Hierarchy* H, T* x, int n);
 void norm2_async(hipStream_t s, Hierarchy* H, const double* r, int n, double* dst_host);
 // sum of x times scale into result slot `slot` (device side)
-void sum_to_slot(hipStream_t s, Hierarchy* H, const double* x, int n, int slot, double scale);
+void sum_to_slot(hipStream_t s, Hierarchy* H, const double* x, int n, int slot, double div);
 void coarsest_solve(hipStream_t s, Hierarchy* H, const double* b, double* x);
 void coarsest_solve32(hipStream_t s, Hierarchy* H, const float* b, float* x);
 void coarsest_factor(Hierarchy* H, const Level& L);

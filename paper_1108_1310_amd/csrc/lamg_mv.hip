@@ -349,10 +349,10 @@ __device__ inline double col_total(int k, int rows, const double* part, int c) {
   return t;
 }
 __global__ __launch_bounds__(MVT) void k_colfinish(int k, int rows, const double* __restrict__ part,
-                                                   double* __restrict__ out, double scale) {
+                                                   double* __restrict__ out, double div) {
   const int c = blockIdx.x;
   const double t = col_total(k, rows, part, c);
-  if (threadIdx.x == 0) out[c] = t * scale;
+  if (threadIdx.x == 0) out[c] = t / div;  // a mean divides by n, as defined
 }
 // Per column: the th x th normal equations of min || r + sum_i alpha_i d_i ||
 // (eq. recomb), with the drop rules of the single-vector kernel.
@@ -410,16 +410,16 @@ enum { RS_BMEAN = 0, RS_BNORM = 1, RS_RNORM = 2, RS_RMEAN = 3, RS_XMEAN = 4, RS_
 int red_rows(const MVWork& W, int n) { return std::max(1, std::min(W.rows, n)); }
 
 template <class T>
-void col_reduce(hipStream_t s, Hierarchy* H, const T* x, int n, int squares, int slot, double scale) {
+void col_reduce(hipStream_t s, Hierarchy* H, const T* x, int n, int squares, int slot, double div) {
   MVWork& W = H->mv;
   const int rows = red_rows(W, n), k = W.k;
   hipLaunchKernelGGL(k_colsum<T>, gridn((int64_t)k * rows), dim3(MVT), 0, s, n, k, rows, x, squares, W.part);
-  hipLaunchKernelGGL(k_colfinish, dim3(k), dim3(MVT), 0, s, k, rows, (const double*)W.part, W.res + slot * k, scale);
+  hipLaunchKernelGGL(k_colfinish, dim3(k), dim3(MVT), 0, s, k, rows, (const double*)W.part, W.res + slot * k, div);
 }
 template <class T>
 void subtract_mean_mv(hipStream_t s, Hierarchy* H, T* x, int n, const int* mask) {
   const int k = H->mv.k;
-  col_reduce<T>(s, H, x, n, 0, RS_TMP, 1.0 / (double)n);
+  col_reduce<T>(s, H, x, n, 0, RS_TMP, (double)n);
   hipLaunchKernelGGL(k_colsub<T>, gridn((int64_t)n * k), dim3(MVT), 0, s, n, k, (const double*)(H->mv.res + RS_TMP * k),
                      mask, x);
 }
@@ -678,7 +678,7 @@ lamg_status solve_multi(Hierarchy* H, int k, const double* B, double* X, lamg_in
   double* res = W.res;
   double* hr = W.hres;
   // B <- B - mean(B) per column, in colour order
-  col_reduce<double>(s, H, B, n, 0, RS_BMEAN, 1.0 / (double)n);
+  col_reduce<double>(s, H, B, n, 0, RS_BMEAN, (double)n);
   hipLaunchKernelGGL(k_mv_gather, gridn(nk), dim3(MVT), 0, s, n, k, L.perm, B, (const double*)(res + RS_BMEAN * k),
                      W.B);
   if (H->o.warm_start)
@@ -705,7 +705,7 @@ lamg_status solve_multi(Hierarchy* H, int k, const double* B, double* X, lamg_in
   int it = 0;
   while (active > 0 && it < H->o.max_cycles) {
     LAMG_HIP(hipMemcpyAsync(W.mask, W.hmask, (size_t)k * sizeof(int), hipMemcpyHostToDevice, s));
-    col_reduce<double>(s, H, W.R, n, 0, RS_RMEAN, 1.0 / (double)n);
+    col_reduce<double>(s, H, W.R, n, 0, RS_RMEAN, (double)n);
     const double* rm = res + RS_RMEAN * k;
     if (!fp32) {
       Vecs<double>& v = W.v64[0];

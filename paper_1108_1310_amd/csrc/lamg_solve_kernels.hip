@@ -608,9 +608,11 @@ __global__ __launch_bounds__(k::RED_THREADS) void k_sumsq(int n, const T* __rest
   }
   block_sum_store<1>(v, part + blockIdx.x * NSLOT);
 }
-__global__ __launch_bounds__(256) void k_finish(int nblk, const double* part, double* res, int slot, double scale) {
+// res[slot] = (sum of the block partials) / div: a mean divides by n, as its
+// definition does (a constant vector then loses its mean exactly).
+__global__ __launch_bounds__(256) void k_finish(int nblk, const double* part, double* res, int slot, double div) {
   const double s = finish_slot(nblk, part, 0);
-  if (threadIdx.x == 0) res[slot] = s * scale;
+  if (threadIdx.x == 0) res[slot] = s / div;
 }
 template <class T>
 __global__ void k_sub_mean(int n, const double* __restrict__ res, int slot, T* __restrict__ x) {
@@ -618,17 +620,17 @@ __global__ void k_sub_mean(int n, const double* __restrict__ res, int slot, T* _
   if (u < n) x[u] = (T)((double)x[u] - res[slot]);
 }
 
-void sum_to_slot(hipStream_t s, Hierarchy* H, const double* x, int n, int slot, double scale) {
+void sum_to_slot(hipStream_t s, Hierarchy* H, const double* x, int n, int slot, double div) {
   const int nb = red_grid(n);
   hipLaunchKernelGGL(k_sum<double>, dim3(nb), dim3(k::RED_THREADS), 0, s, n, x, red_part(H));
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, nb, red_part(H), red_res(H), slot, scale);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, nb, red_part(H), red_res(H), slot, div);
 }
 
 template <class T>
 void subtract_mean(hipStream_t s, Hierarchy* H, T* x, int n) {
   const int nb = red_grid(n);
   hipLaunchKernelGGL(k_sum<T>, dim3(nb), dim3(k::RED_THREADS), 0, s, n, x, red_part(H));
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, nb, red_part(H), red_res(H), 4, 1.0 / (double)n);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, nb, red_part(H), red_res(H), 4, (double)n);
   hipLaunchKernelGGL(k_sub_mean<T>, g1(n), dim3(256), 0, s, n, red_res(H), 4, x);
   LAMG_HIP(hipGetLastError());
 }

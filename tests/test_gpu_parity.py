@@ -207,6 +207,30 @@ def test_input_errors(lg):
     assert info["status"] == lg.E_BREAKDOWN
 
 
+def test_degenerate_rhs(lg):
+    """b = 0 and a constant b (zero after the mean removal): x = 0 in no
+    cycles, FP64 and FP32 + refinement; the removed mean is reported."""
+    _print_case("degenerate rhs")
+    n, eu, ev, w = graphs()["chung_lu16k"]
+    H = lg.Hierarchy(n, eu, ev, w)
+    for prec in (0, 1):
+        for c in (0.0, 2.5):
+            x, info = H.solve(torch.full((n,), c, dtype=torch.float64, device="cuda"), precision=prec)
+            assert info["status"] == 0 and info["cycles"] == 0, (prec, c, info)
+            assert torch.count_nonzero(x).item() == 0
+            assert abs(info["removed_mean"] - c) <= 1e-15 * max(1.0, c)
+    # the same columns beside a regular one in a multi-vector solve
+    B = np.zeros((n, 3))
+    B[:, 0] = 2.5
+    B[:, 1] = W.rhs_normal(n, 1, 4)
+    X, info, cols, rc = H.solve_multi(B)
+    assert rc == 0
+    assert list(cols["cycles"][[0, 2]]) == [0, 0] and cols["cycles"][1] > 0
+    X = X.cpu().numpy()
+    assert np.count_nonzero(X[:, 0]) == 0 and np.count_nonzero(X[:, 2]) == 0
+    assert cols["removed_mean"][0] == 2.5
+
+
 def test_multi_rhs_equals_single(ora, lg):
     _print_case("multi-rhs")
     n, eu, ev, w = graphs()["grid64"]
