@@ -712,6 +712,81 @@ int setup(Hier& H, i64 n, i64 m, const i32* eu, const i32* ev, const double* w) 
   return 0;
 }
 
+// ----------------------------------------------- lean geometric multigrid
+// Section 5.3 (Lean Geometric Multigrid): the periodic Poisson problem on an
+// s x s grid (s a power of two; unit weights; node (i, j) has id i + s j),
+// relaxed by Gauss-Seidel in red-black order, coarsened 1:2 in each dimension
+// at every level (2 x 2 aggregates: first-order transfers and the Galerkin
+// operator of each level), visited with index gamma at every level and
+// corrected by the flat energy correction mu = 2 (eq. galerkin2).
+void order_by(Level& L, const vector<i32>& c, int ncol) {
+  vector<i32> perm(L.A.n);
+  std::iota(perm.begin(), perm.end(), 0);
+  std::stable_sort(perm.begin(), perm.end(), [&](i32 a, i32 b) { return c[a] < c[b]; });
+  L.ncol = ncol;
+  L.cptr.assign(ncol + 1, 0);
+  for (i32 x : c) L.cptr[x + 1]++;
+  for (int k = 0; k < ncol; ++k) L.cptr[k + 1] += L.cptr[k];
+  L.A = permute(L.A, perm);
+  L.perm = perm;
+}
+vector<i32> red_black(i64 s) {
+  vector<i32> c(s * s);
+  for (i64 j = 0; j < s; ++j)
+    for (i64 i = 0; i < s; ++i) c[i + s * j] = (i32)((i + j) & 1);
+  return c;
+}
+int setup_lgm(Hier& H, i64 s) {
+  if (s < 2 || (s & (s - 1)) || s > 32768) return 1;
+  const i64 n = s * s;
+  vector<i32> eu, ev;
+  vector<double> w;
+  for (i64 j = 0; j < s; ++j)
+    for (i64 i = 0; i < s; ++i) {
+      eu.push_back((i32)(i + s * j)); ev.push_back((i32)((i + 1) % s + s * j)); w.push_back(1.0);
+      eu.push_back((i32)(i + s * j)); ev.push_back((i32)(i + s * ((j + 1) % s))); w.push_back(1.0);
+    }
+  Level L1;
+  int rc = build_laplacian(n, (i64)eu.size(), eu.data(), ev.data(), w.data(), L1.A);
+  if (rc) return rc;
+  L1.type = L_FINEST;
+  order_by(L1, red_black(s), s > 1 ? 2 : 1);
+  H.perm1 = L1.perm;
+  H.lv.push_back(std::move(L1));
+  i64 side = s;
+  while (H.lv.back().A.n >= H.o.coarsest_max_n && side >= 4 && (int)H.lv.size() < H.o.max_levels) {
+    Level& F = H.lv.back();
+    const i64 sc = side / 2;
+    // aggregate of fine node (i, j): coarse node (i / 2, j / 2)
+    vector<i32> ag(F.A.n);
+    for (i64 u = 0; u < F.A.n; ++u) {
+      const i64 v = F.perm[u], i = v % side, j = v / side;
+      ag[u] = (i32)(i / 2 + sc * (j / 2));
+    }
+    Level C;
+    C.A = galerkin(F.A, ag, sc * sc);
+    C.type = L_AGG;
+    order_by(C, red_black(sc), 2);
+    vector<i32> inv(C.A.n);
+    for (i64 i = 0; i < C.A.n; ++i) inv[C.perm[i]] = (i32)i;
+    C.agg.resize(F.A.n);
+    for (i64 u = 0; u < F.A.n; ++u) C.agg[u] = inv[ag[u]];
+    H.lv.push_back(std::move(C));
+    side = sc;
+  }
+  for (size_t l = 0; l + 1 < H.lv.size(); ++l) H.lv[l].gamma_next = H.o.gamma;
+  H.o.ec = 1;
+  H.o.mu = 2.0;
+  for (auto& L : H.lv) {
+    L.val32.assign(L.A.val.begin(), L.A.val.end());
+    L.diag32.assign(L.A.diag.begin(), L.A.diag.end());
+  }
+  if (H.lv.back().A.n > H.o.dense_max) H.coarsest_relax = true;
+  if (!H.coarsest_relax) coarsest_factor(H);
+  else H.nL = H.lv.back().A.n;
+  return 0;
+}
+
 // ------------------------------------------------------------------- cycle
 // Section 4.2 cycle with pre/post relaxation (1,2), flat energy correction
 // (eq. galerkin2) or iterate recombination (eq. recomb), fractional cycle
@@ -1105,6 +1180,15 @@ void* ora_setup(i64 n, i64 m, const i32* eu, const i32* ev, const double* w, con
   Hier* H = new Hier;
   H->o = to_opts(o);
   int rc = setup(*H, n, m, eu, ev, w);
+  if (status) *status = rc;
+  if (rc) { delete H; return nullptr; }
+  return H;
+}
+// Lean geometric multigrid hierarchy of the s x s periodic Poisson grid.
+void* ora_setup_lgm(i64 s, const ora_opts* o, int* status) {
+  Hier* H = new Hier;
+  H->o = to_opts(o);
+  int rc = setup_lgm(*H, s);
   if (status) *status = rc;
   if (rc) { delete H; return nullptr; }
   return H;

@@ -71,6 +71,7 @@ def lib():
             "ora_schur": (vp, [i64, i64p, i32p, dp, dp, u8p, i32p]),
             "ora_galerkin": (vp, [i64, i64p, i32p, dp, dp, i32p, i64]),
             "ora_setup": (vp, [i64, i64, i32p, i32p, dp, C.POINTER(Opts), C.POINTER(C.c_int)]),
+            "ora_setup_lgm": (vp, [i64, C.POINTER(Opts), C.POINTER(C.c_int)]),
             "ora_free": (None, [vp]),
             "ora_num_levels": (C.c_int, [vp]),
             "ora_level_dims": (None, [vp, C.c_int, i64p]),
@@ -265,6 +266,21 @@ class Hierarchy:
         if st.value:
             raise ValueError(f"oracle setup status {st.value}")
         self.n = n
+
+    @classmethod
+    def lgm(cls, side, **opts):
+        """Lean geometric multigrid hierarchy of the side x side periodic
+        Poisson grid (Section 5.3): red-black GS, 2 x 2 aggregation at every
+        level, gamma at every level, flat mu = 2."""
+        self = cls.__new__(cls)
+        self.opts = default_opts(**opts)
+        st = C.c_int(0)
+        self.h = lib().ora_setup_lgm(side, C.byref(self.opts), C.byref(st))
+        self.status = st.value
+        if st.value:
+            raise ValueError(f"oracle LGM setup status {st.value}")
+        self.n = side * side
+        return self
 
     def __del__(self):
         h = getattr(self, "h", None)
