@@ -33,7 +33,7 @@ def parse():
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--workload", default="chung_lu_2p20",
-                   choices=["chung_lu_2p20", "grid2d_64", "rgg_2p20", "grid3d_128_k32", "graph_batch_256"])
+                   choices=["chung_lu_2p20", "grid2d_64", "rgg_2p20", "grid3d_128_k32", "graph_batch_256", "lgm_1024"])
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU reference baseline")
     p.add_argument("--no-fp32", action="store_true")
     p.add_argument("--copy-bytes", type=int, default=0,
@@ -436,7 +436,7 @@ def cpu_baseline(name):
         g, _ = W.config(name)
         seed, what, cap = 0, "full workload", 4096
     t0 = time.perf_counter()
-    H = O.Hierarchy(g.n, g.eu, g.ev, g.w)
+    H = O.Hierarchy.lgm(1024) if name == "lgm_1024" else O.Hierarchy(g.n, g.eu, g.ev, g.w)
     setup_s = time.perf_counter() - t0
     dt, cyc, k, dig = _oracle_rhs_loop(H, g, lambda j: W.rhs_normal(g.n, 1, seed + 7919 * j), cap)
     # the oracle's finest-level matrix-vector product (its residual), the paper's work unit
@@ -452,6 +452,28 @@ def cpu_baseline(name):
             "cycles": cyc, "solves": k, "solve_s": dt, "edges": g.m, "host": host_cpu(),
             "setup_s": setup_s, "mvm_ms": mvm_s * 1e3, "setup_mvm": setup_s / mvm_s,
             "solve_mvm_per_digit": dt / k / mvm_s / dig}
+
+
+def cycle_work_units(ns, gammas, nu):
+    """Relaxation work of one cycle in finest-level sweeps: nu sweeps per body
+    of every level above the coarsest, times its visits (the fractional
+    cycle index of each level: body c of level l visits level l+1
+    ceil((c+1) gamma_l) - ceil(c gamma_l) times), scaled by n_l / n_0."""
+    L = len(ns)
+    count, visits = [0] * L, [0] * L
+
+    def body(l):
+        visits[l] += 1
+        if l == L - 1:
+            return
+        c = count[l]
+        count[l] += 1
+        th = math.ceil((c + 1) * gammas[l]) - math.ceil(c * gammas[l])
+        for _ in range(th if l + 1 < L - 1 else 1):
+            body(l + 1)
+
+    body(0)
+    return sum(nu * visits[l] * ns[l] / ns[0] for l in range(L - 1))
 
 
 def main():
@@ -477,7 +499,10 @@ def main():
     print(f"[bench] setup n={g.n} m={g.m}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    H = lamg.Hierarchy(g.n, g.eu, g.ev, g.w)
+    if a.workload == "lgm_1024":
+        H = lamg.Hierarchy.lgm(1024)  # geometric hierarchy of the same periodic grid
+    else:
+        H = lamg.Hierarchy(g.n, g.eu, g.ev, g.w)
     torch.cuda.synchronize()
     setup_ms = (time.perf_counter() - t0) * 1e3
     levels = [H.dims(l) for l in range(H.num_levels)]
@@ -536,6 +561,13 @@ def main():
                 "ms_per_step": rv["seconds"] * 1e3 / a.steps, "cycles_per_solve": rv["cycles"] / a.steps,
                 "acf": rv["acf"], "rel_residual": rv["rel_residual"]}
         Hv.close()
+    lgm = None
+    if a.workload == "lgm_1024":
+        # convergence factor per unit of work (one finest relaxation sweep)
+        W = cycle_work_units([d["n"] for d in levels], [d["gamma"] for d in levels],
+                             H.opts.nu_pre + H.opts.nu_post)
+        lgm = {"work_units_per_cycle": W, "acf": r64["acf"], "factor_per_work_unit": r64["acf"] ** (1.0 / W),
+               "paper_factor_per_work_unit": 0.5}
     adj = None
     if a.workload == "rgg_2p20":
         adj = adjoint_step(g, b, a.steps, a.warmup)
@@ -569,6 +601,7 @@ def main():
         "v_cycle": vcyc,
         "fp32_refine": out32,
         "adjoint": adj,
+        "lgm": lgm,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -111,6 +111,22 @@ void lamg_options_default(lamg_options* o);
 lamg_status lamg_setup(int64_t n, int64_t m, const int32_t* eu, const int32_t* ev, const double* w,
                        const lamg_options* o, lamg_handle* out);
 
+/* Lean geometric multigrid (Section 5.3): the hierarchy of the periodic
+ * Poisson problem on a side x side grid (unit weights; node (i, j) has id
+ * i + side j, so b and x of lamg_solve are in that order).  Every level is
+ * the Galerkin operator of 1:2 coarsening in each dimension (aggregate
+ * (i/2, j/2) of the finer grid, first-order transfers) and is relaxed by
+ * Gauss-Seidel in red-black order; the cycle index is o->gamma at every
+ * level and the correction is the flat energy correction with mu = 2
+ * (eq. galerkin2), which this call sets in place of o->ec and o->mu (they
+ * stay changeable by lamg_set_solve_options).  Coarsening stops below
+ * o->coarsest_max_n nodes.
+ *   side  a power of two, 4 <= side <= LAMG_LGM_MAX_SIDE, else
+ *         LAMG_E_INVALID_ARG
+ *   o, out as for lamg_setup. */
+#define LAMG_LGM_MAX_SIDE 16384
+lamg_status lamg_setup_lgm(int32_t side, const lamg_options* o, lamg_handle* out);
+
 /* Solve A x = b - mean(b) (Section 4.2 cycles, mean removed each cycle).
  *   b     DEVICE double[n]; not modified
  *   x     DEVICE double[n]; the zero-mean solution (warm_start: initial guess on entry)

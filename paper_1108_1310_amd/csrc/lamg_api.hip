@@ -318,40 +318,36 @@ static bool opts_ok(const lamg_options& o) {
          (o.alloc == nullptr) == (o.dealloc == nullptr);
 }
 
-lamg_status lamg_setup(int64_t n, int64_t m, const int32_t* eu, const int32_t* ev, const double* w,
-                       const lamg_options* o, lamg_handle* out) {
-  if (!out) return LAMG_E_INVALID_ARG;
-  *out = nullptr;
-  if (n < 1 || m < 0 || n > (int64_t)0x7fffffff / 2 || m > (int64_t)0x3fffffff) return LAMG_E_INVALID_ARG;
-  if (m > 0 && (!eu || !ev || !w)) return LAMG_E_INVALID_ARG;
+}  // extern "C"
+
+// Setup frame shared by the entry points: options, handle, allocator scope,
+// the level construction `levels` (returns a status), finishing and errors.
+template <class Levels>
+static lamg_status run_setup(int64_t n, int64_t m, const lamg_options* o, lamg_handle* out, Levels levels,
+                             bool gamma_every_level = false, int ec = -1, double mu = 0) {
   lamg_options opt;
   lamg_options_default(&opt);
   if (o) {
     if (o->struct_size != sizeof(lamg_options)) return LAMG_E_INVALID_ARG;
     opt = *o;
   }
+  if (ec >= 0) {
+    opt.ec = (lamg_energy_correction)ec;
+    opt.mu = mu;
+  }
   if (!opts_ok(opt)) return LAMG_E_INVALID_ARG;
   lamg_hierarchy* h = new lamg_hierarchy;
   Hierarchy* H = &h->H;
   H->o = opt;
   H->s = (hipStream_t)opt.stream;
+  H->gamma_every_level = gamma_every_level;
   AllocScope scope(&H->o);  // setup temporaries through the same allocator
   H->n = (int)n;
   H->m = m;
   auto t0 = std::chrono::steady_clock::now();
   try {
-    lamg_status st = build_finest(H, n, m, eu, ev, w);
+    lamg_status st = levels(H);
     if (st != LAMG_OK) { lamg_free(h); return st; }
-    colour_and_order(H, H->lv[0], 0, nullptr);
-    int nagg = 0;
-    while (H->lv.back().n >= opt.coarsest_max_n && (int)H->lv.size() < 60) {
-      const int l = (int)H->lv.size() - 1;
-      if (try_eliminate(H, l)) continue;
-      const int r = aggregate(H, l, nagg);
-      if (r == 2) { H->coarsest_relax = true; break; }
-      if (r == 0) break;
-      ++nagg;
-    }
     finish_levels(H);
     H->bsave = H->lv[0].v64.b;
     H->x64 = H->lv[0].v64.x;
@@ -368,6 +364,48 @@ lamg_status lamg_setup(int64_t n, int64_t m, const int32_t* eu, const int32_t* e
   H->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   *out = h;
   return LAMG_OK;
+}
+
+extern "C" {
+
+lamg_status lamg_setup(int64_t n, int64_t m, const int32_t* eu, const int32_t* ev, const double* w,
+                       const lamg_options* o, lamg_handle* out) {
+  if (!out) return LAMG_E_INVALID_ARG;
+  *out = nullptr;
+  if (n < 1 || m < 0 || n > (int64_t)0x7fffffff / 2 || m > (int64_t)0x3fffffff) return LAMG_E_INVALID_ARG;
+  if (m > 0 && (!eu || !ev || !w)) return LAMG_E_INVALID_ARG;
+  return run_setup(n, m, o, out, [&](Hierarchy* H) {
+    lamg_status st = build_finest(H, n, m, eu, ev, w);
+    if (st != LAMG_OK) return st;
+    colour_and_order(H, H->lv[0], 0, nullptr);
+    int nagg = 0;
+    while (H->lv.back().n >= H->o.coarsest_max_n && (int)H->lv.size() < 60) {
+      const int l = (int)H->lv.size() - 1;
+      if (try_eliminate(H, l)) continue;
+      const int r = aggregate(H, l, nagg);
+      if (r == 2) { H->coarsest_relax = true; break; }
+      if (r == 0) break;
+      ++nagg;
+    }
+    return (lamg_status)LAMG_OK;
+  });
+}
+
+lamg_status lamg_setup_lgm(int32_t side, const lamg_options* o, lamg_handle* out) {
+  if (!out) return LAMG_E_INVALID_ARG;
+  *out = nullptr;
+  if (side < 4 || side > LAMG_LGM_MAX_SIDE || (side & (side - 1))) return LAMG_E_INVALID_ARG;
+  const int64_t n = (int64_t)side * side;
+  return run_setup(n, 2 * n, o, out, [&](Hierarchy* H) {
+    lamg_status st = build_lgm_finest(H, side);
+    if (st != LAMG_OK) return st;
+    int sd = side;
+    while (H->lv.back().n >= H->o.coarsest_max_n && sd >= 4 && (int)H->lv.size() < 60) {
+      lgm_coarsen(H, (int)H->lv.size() - 1, sd);
+      sd /= 2;
+    }
+    return (lamg_status)LAMG_OK;
+  }, true, LAMG_EC_FLAT_MU, 2.0);
 }
 
 lamg_status lamg_set_solve_options(lamg_handle h, const lamg_options* o) {

@@ -209,6 +209,7 @@ struct Hierarchy {
   // set while a cycle is recorded whose finest residual is already known:
   // FP64, in r64 (the stopping test's); FP32, equal to b (x starts at 0)
   bool top_res_known = false;
+  bool gamma_every_level = false;  // cycle index o.gamma at every level (geometric)
   std::vector<TailLevel> tail_host;  // host copy of the descriptors
   MVWork mv;
   // whole-hierarchy op program (every level, from level 0) for the
@@ -304,6 +305,10 @@ bool try_eliminate(Hierarchy* H, int l);
 int aggregate(Hierarchy* H, int l, int agg_index);
 void finish_levels(Hierarchy* H);
 void build_hub(Hierarchy* H, Level& L);
+// lean geometric multigrid (Section 5.3): the periodic side x side grid as
+// the finest level, red-black ordered; one 2 x 2 coarsening of level l
+lamg_status build_lgm_finest(Hierarchy* H, int side);
+void lgm_coarsen(Hierarchy* H, int l, int side);
 
 // solve
 int64_t cycle_bytes(const Hierarchy* H, int prec);

@@ -464,6 +464,11 @@ __global__ void k_max_i(int n, const int* __restrict__ a, int* __restrict__ out)
   for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o, 64));
   if ((threadIdx.x & 63) == 0) atomicMax(out, m);
 }
+// red-black colour of node i + side j of a side x side grid
+__global__ void k_red_black(int n, int side, int* __restrict__ col) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u < n) col[u] = ((u % side) + (u / side)) & 1;
+}
 __global__ void k_inverse(int n, const int* __restrict__ perm, int* __restrict__ inv) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) inv[perm[i]] = i;
@@ -543,11 +548,19 @@ int colour_greedy(hipStream_t s, int n, const int* rp, const int* ci, uint64_t s
   return to_host(s, ctr + 1) + 1;
 }
 
-static int* colour_order_impl(Hierarchy* H, Tmp& tmp, Level& L, int level) {
+// rb_side > 0: the level is an rb_side x rb_side grid in natural order and
+// takes the red-black colouring (i + j) mod 2 instead of the greedy one.
+static int* colour_order_impl(Hierarchy* H, Tmp& tmp, Level& L, int level, int rb_side = 0) {
   hipStream_t s = H->s;
   const int n = L.n;
   int* col = tmp.get<int>(n);
-  const int ncol = colour_greedy(s, n, L.rp, L.ci, (uint64_t)H->o.seed, level, col);
+  int ncol = 0;
+  if (rb_side > 0) {
+    hipLaunchKernelGGL(k_red_black, grid1(n), dim3(256), 0, s, n, rb_side, col);
+    ncol = n > 1 ? 2 : 1;
+  } else {
+    ncol = colour_greedy(s, n, L.rp, L.ci, (uint64_t)H->o.seed, level, col);
+  }
   // permutation: stable sort of ids by colour
   int* ids = tmp.get<int>(n);
   int* cs = tmp.get<int>(n);
@@ -1103,6 +1116,8 @@ static std::vector<double> tv_energies(Hierarchy* H, Tmp& tmp, const Level& F, i
   return to_host_vec(s, out, (size_t)K);
 }
 
+static int galerkin_level(Hierarchy* H, Tmp& tmp, int l, const int* aggn, int nc, int rb_side);
+
 int aggregate(Hierarchy* H, int l, int agg_index) {
   hipStream_t s = H->s;
   Tmp tmp;
@@ -1210,6 +1225,16 @@ int aggregate(Hierarchy* H, int l, int agg_index) {
   if (nc >= n) return 0;  // no coarsening possible
   int* aggn = tmp.get<int>(n);
   hipLaunchKernelGGL(k_number, grid1(n), dim3(256), 0, s, n, st, seedof, id, dmin, aggn);
+  return galerkin_level(H, tmp, l, aggn, nc, 0);
+}
+
+// The coarse level of aggregation aggn (fine node in level l's order ->
+// aggregate 0..nc-1): Galerkin operator, colouring and order (red-black of
+// an rb_side grid if rb_side > 0), transfer maps.  Returns 1.
+static int galerkin_level(Hierarchy* H, Tmp& tmp, int l, const int* aggn, int nc, int rb_side) {
+  hipStream_t s = H->s;
+  const Level& F = H->lv[l];
+  const int n = F.n;
   // Galerkin coarse operator
   int* gcnt = tmp.get<int>(n + 1);
   int* goff = tmp.get<int>(n + 1);
@@ -1222,7 +1247,7 @@ int aggregate(Hierarchy* H, int l, int agg_index) {
   Level C;
   C.type = LT_AGG;
   merge_triples(H, tmp, C, nc, key, v, nt);
-  int* cinv = colour_order_impl(H, tmp, C, l + 1);
+  int* cinv = colour_order_impl(H, tmp, C, l + 1, rb_side);
   C.agg = dnew<int>(H, n);
   hipLaunchKernelGGL(k_map, grid1(n), dim3(256), 0, s, n, aggn, cinv, C.agg);
   // P^T as CSR: members of each aggregate in ascending fine id
@@ -1239,6 +1264,52 @@ int aggregate(Hierarchy* H, int l, int agg_index) {
   LAMG_HIP(hipStreamSynchronize(s));
   H->lv.push_back(C);
   return 1;
+}
+
+// ------------------------------------------------ lean geometric multigrid
+// Section 5.3: the periodic Poisson problem on a side x side grid (unit
+// weights, node (i, j) = i + side j), coarsened 1:2 in each dimension at
+// every level: fine node (i, j) joins aggregate (i / 2, j / 2), numbered
+// i / 2 + (side / 2)(j / 2), and every level is coloured red-black.
+namespace {
+__global__ void k_lgm_edges(int side, int32_t* __restrict__ eu, int32_t* __restrict__ ev, double* __restrict__ w) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = (int64_t)side * side;
+  if (k >= 2 * n) return;
+  const int u = (int)(k >> 1), i = u % side, j = u / side;
+  eu[k] = u;
+  ev[k] = (k & 1) ? i + side * ((j + 1) % side) : (i + 1) % side + side * j;  // up : right
+  w[k] = 1.0;
+}
+__global__ void k_lgm_agg(int n, int side, const int* __restrict__ perm, int* __restrict__ agg) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= n) return;
+  const int v = perm[u];
+  agg[u] = (v % side) / 2 + (side / 2) * ((v / side) / 2);
+}
+}  // namespace
+
+lamg_status build_lgm_finest(Hierarchy* H, int side) {
+  Tmp tmp;
+  const int64_t n = (int64_t)side * side, m = 2 * n;
+  int32_t* eu = tmp.get<int32_t>(m);
+  int32_t* ev = tmp.get<int32_t>(m);
+  double* w = tmp.get<double>(m);
+  hipLaunchKernelGGL(k_lgm_edges, grid1(m), dim3(256), 0, H->s, side, eu, ev, w);
+  LAMG_HIP(hipGetLastError());
+  const lamg_status st = build_finest(H, n, m, eu, ev, w);
+  if (st != LAMG_OK) return st;
+  colour_order_impl(H, tmp, H->lv[0], 0, side);
+  return LAMG_OK;
+}
+
+void lgm_coarsen(Hierarchy* H, int l, int side) {
+  Tmp tmp;
+  const int n = H->lv[l].n;
+  int* agg = tmp.get<int>(n);
+  hipLaunchKernelGGL(k_lgm_agg, grid1(n), dim3(256), 0, H->s, n, side, (const int*)H->lv[l].perm, agg);
+  LAMG_HIP(hipGetLastError());
+  galerkin_level(H, tmp, l, agg, (side / 2) * (side / 2), side / 2);
 }
 
 // Cycle indices (Section 4.2, eq. cycle_index with gamma^l >= 1), FP32 level
@@ -1403,6 +1474,7 @@ void finish_levels(Hierarchy* H) {
     Level& F = H->lv[l];
     const Level& C = H->lv[l + 1];
     if (C.type == LT_ELIM) { F.gamma_next = 1.0; continue; }
+    if (H->gamma_every_level) { F.gamma_next = H->o.gamma; continue; }
     const double El = (double)F.nnz, Ec = (double)C.nnz;
     if (El > 0.1 * E1) F.gamma_next = H->o.gamma;
     else if (Ec <= 0) F.gamma_next = 1.0;

@@ -69,6 +69,7 @@ def lib():
         sig = {
             "lamg_options_default": (None, [C.POINTER(Options)]),
             "lamg_setup": (C.c_int, [i64, i64, vp, vp, vp, C.POINTER(Options), C.POINTER(vp)]),
+            "lamg_setup_lgm": (C.c_int, [i32, C.POINTER(Options), C.POINTER(vp)]),
             "lamg_solve": (C.c_int, [vp, vp, vp, C.POINTER(Info)]),
             "lamg_solve_batch": (C.c_int, [i32, C.POINTER(vp), C.POINTER(i32), C.POINTER(vp), C.POINTER(vp),
                                            C.POINTER(Info)]),
@@ -190,6 +191,26 @@ class Hierarchy:
         self.h = h
         self.n = int(n)
         self.m = int(eu.numel())
+
+    @classmethod
+    def lgm(cls, side: int, allocator: "TorchAllocator" = None, **opts):
+        """Lean geometric multigrid (Section 5.3) for the periodic Poisson
+        problem on a side x side grid (node (i, j) = i + side j): red-black
+        GS, 2 x 2 coarsening at every level, gamma at every level, flat
+        mu = 2."""
+        self = cls.__new__(cls)
+        self.opts = options(stream=_stream(), **opts)
+        self.opts.ec, self.opts.mu = EC_FLAT_MU, 2.0  # what the setup sets
+        self._allocator = allocator
+        if allocator is not None:
+            self.opts.alloc = allocator.c_alloc
+            self.opts.dealloc = allocator.c_dealloc
+        h = C.c_void_p()
+        _check(lib().lamg_setup_lgm(int(side), C.byref(self.opts), C.byref(h)), "lamg_setup_lgm")
+        self.h = h
+        self.n = int(side) * int(side)
+        self.m = 2 * self.n
+        return self
 
     def close(self):
         if getattr(self, "h", None):

@@ -17,6 +17,8 @@ Workloads (one per benchmark configuration):
   random geometric), sizes log-uniform in [1e3, 2e5], weights U[0.1, 1].
 * ``rgg``      -- random geometric graph in the unit square, radius
   ``sqrt(12/(pi n))``, weights ``exp(-d^2/r^2)``, largest component kept.
+* ``grid2d_periodic`` -- the periodic 5-point Poisson grid of the geometric
+  multigrid experiment, ids ``i + side*j``, unit weights.
 
 Every draw comes from ``numpy.random.default_rng(seed)`` with a fixed seed per
 workload and stream, so the same call gives byte-identical arrays everywhere.
@@ -32,7 +34,7 @@ import math
 import numpy as np
 
 SEEDS = {"grid2d": 101, "chung_lu": 102, "grid3d_aniso": 103,
-         "graph_batch": 104, "rgg": 105}
+         "graph_batch": 104, "rgg": 105, "lgm": 106}
 # independent random streams per workload
 _S_GRAPH, _S_WEIGHT, _S_RHS, _S_LABEL = 0, 1, 2, 4
 
@@ -88,6 +90,16 @@ def grid2d(nx: int = 64, ny: int | None = None, seed: int = SEEDS["grid2d"],
     else:
         w = _rng(seed, _S_WEIGHT).uniform(0.1, 1.0, eu.shape[0])
     return Graph(f"grid2d_{nx}x{ny}", nx * ny, eu, ev, w)
+
+
+def grid2d_periodic(side: int = 1024) -> Graph:
+    """Periodic side x side 5-point grid, unit weights: edges (i, j)-(i+1, j)
+    and (i, j)-(i, j+1), indices mod side."""
+    u = np.arange(side * side, dtype=np.int64)
+    i, j = u % side, u // side
+    eu = np.concatenate([u, u]).astype(np.int32)
+    ev = np.concatenate([(i + 1) % side + side * j, i + side * ((j + 1) % side)]).astype(np.int32)
+    return Graph(f"grid2d_periodic_{side}", side * side, eu, ev, np.ones(eu.shape[0]))
 
 
 def grid3d_aniso(nside: int = 128, seed: int = SEEDS["grid3d_aniso"]) -> Graph:
@@ -247,6 +259,9 @@ def config(name: str):
     if name == "grid3d_128_k32":
         g = grid3d_aniso(128)
         return g, rhs_normal(g.n, 32, SEEDS["grid3d_aniso"])
+    if name == "lgm_1024":
+        g = grid2d_periodic(1024)
+        return g, rhs_normal(g.n, 1, SEEDS["lgm"])
     if name == "rgg_2p20":
         g = rgg()
         lab, _ = label_split(g.n)
