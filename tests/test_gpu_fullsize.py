@@ -68,6 +68,30 @@ def test_chung_lu_full(ora, lg):
         assert np.linalg.norm(x - xo) <= 1e-6 * np.linalg.norm(xo)
 
 
+def test_grid_1024_published_acf(ora, lg):
+    """The 1024 x 1024 5-point grid of the paper's grid table (case (a),
+    ACF 0.216): the GPU hierarchy equals the oracle's bit for bit and the
+    GPU solve has the oracle's cycle count and ACF."""
+    _case("grid2d 1024 full size")
+    g = W.grid2d(1024)
+    Ho = ora.Hierarchy(g.n, g.eu, g.ev, g.w)
+    Hg = lg.Hierarchy(g.n, g.eu, g.ev, g.w)
+    assert Hg.num_levels == Ho.num_levels
+    for l in range(Ho.num_levels):
+        Lo, Lgl = Ho.level(l), Hg.level(l)
+        assert np.array_equal(Lo.A.col, Lgl["ci"]) and np.array_equal(Lo.A.val, Lgl["val"]), l
+        assert np.array_equal(Lo.perm, Lgl["perm"]), l
+        if l > 0:
+            assert np.array_equal(Lo.transfer, Lgl["transfer"]), l
+    b = W.rhs_normal(g.n, 1, 1)
+    xo, io, _ = Ho.solve(b)
+    x, info = Hg.solve(torch.tensor(b, device="cuda"))
+    assert info["status"] == 0 and abs(info["cycles"] - io["cycles"]) <= 1
+    assert abs(info["acf"] - io["acf"]) <= 0.02 * io["acf"]
+    assert 0.18 <= info["acf"] <= 0.25
+    assert rel_residual(laplacian(g), b, x.cpu().numpy()) <= 1.0000001e-8
+
+
 def test_grid3d_multivector_full(lg):
     """128^3 anisotropic grid, 32 right-hand sides, FP32 + FP64 refinement as
     one multi-vector batch: every column at 1e-8 (scipy residual), zero mean,
