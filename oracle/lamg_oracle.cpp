@@ -118,6 +118,7 @@ struct Opts {  // mirrors the library options, defaults from Section 4
   double relax_fast_ratio = 0.1; // stop coarsening when the last test-vector sweep cuts energy at least this much
   int coarsest_sweeps = 3;       // relaxation sweeps of a coarsest level that relaxation solves
   int dense_max = 8192;          // largest coarsest level factored densely
+  int allow_negative = 0;        // Section 5.2: accept negative weights (|w| in the aggregation tests)
 };
 
 struct AggDiag {  // aggregation-level setup quantities, kept for parity tests
@@ -161,11 +162,13 @@ struct Hier {
 // ---------------------------------------------------------------- Laplacian
 // COO -> Laplacian (Section 1, eq. lap; Section 5.1 preprocessing: duplicate
 // entries of an undirected pair are summed in input order).
-int build_laplacian(i64 n, i64 m, const i32* eu, const i32* ev, const double* w, Csr& A) {
+// allow_negative (Section 5.2): weights may be negative (not zero); the caller
+// vouches that the Laplacian is positive semi-definite.
+int build_laplacian(i64 n, i64 m, const i32* eu, const i32* ev, const double* w, Csr& A, bool allow_negative = false) {
   if (n < 1 || m < 0) return 1;
   for (i64 e = 0; e < m; ++e) {
     if (eu[e] < 0 || eu[e] >= n || ev[e] < 0 || ev[e] >= n || eu[e] == ev[e]) return 1;
-    if (!std::isfinite(w[e]) || !(w[e] > 0)) return 2;
+    if (!std::isfinite(w[e]) || (allow_negative ? w[e] == 0 : !(w[e] > 0))) return 2;
   }
   vector<i64> idx(m);
   std::iota(idx.begin(), idx.end(), 0);
@@ -471,6 +474,20 @@ AggResult aggregate(const Level& L, const Opts& o, int agg_index, int level, Agg
     R.fast = true;
     return R;
   }
+  // Section 5.2: with negative weights the hub, affinity and energy tests
+  // use |w|, i.e. run on the Laplacian of the absolute weights (diagonal
+  // sum |w| in the fixed row order); a level without negative weights uses
+  // its own matrix
+  bool neg = false;
+  for (double v : A.val) neg = neg || v < 0;
+  Csr Aabs;
+  if (neg) {
+    Aabs = A;
+    for (auto& v : Aabs.val) v = std::fabs(v);
+    for (i64 u = 0; u < n; ++u)
+      Aabs.diag[u] = row_reduce<double>(Aabs.deg(u), [&](i64 t) { return Aabs.val[Aabs.ptr[u] + t]; });
+  }
+  const Csr& Ad = neg ? Aabs : A;
   // node quantities
   vector<double> nrm(n), ystar((size_t)n * K), emin((size_t)n * K), sw(n), swd(n), maxw(n, 0.0);
   for (i64 u = 0; u < n; ++u) {
@@ -479,18 +496,18 @@ AggResult aggregate(const Level& L, const Opts& o, int agg_index, int level, Agg
     nrm[u] = s;
     i64 p0 = A.ptr[u];
     for (int k = 0; k < K; ++k) {
-      double B = row_reduce<double>(A.deg(u), [&](i64 t) { return A.val[p0 + t] * X[(i64)A.col[p0 + t] * K + k]; });
-      double y = B / A.diag[u];
+      double B = row_reduce<double>(A.deg(u), [&](i64 t) { return Ad.val[p0 + t] * X[(i64)A.col[p0 + t] * K + k]; });
+      double y = B / Ad.diag[u];
       double S2 = row_reduce<double>(A.deg(u), [&](i64 t) {
         double d = X[(i64)A.col[p0 + t] * K + k] - y;
-        return A.val[p0 + t] * (d * d);
+        return Ad.val[p0 + t] * (d * d);
       });
       ystar[u * K + k] = y;
       emin[u * K + k] = 0.5 * S2;  // min_y E_u(x; y)
     }
-    sw[u] = row_reduce<double>(A.deg(u), [&](i64 t) { return A.val[p0 + t]; });
-    swd[u] = row_reduce<double>(A.deg(u), [&](i64 t) { return A.val[p0 + t] * (double)A.deg(A.col[p0 + t]); });
-    for (i64 t = p0; t < A.ptr[u + 1]; ++t) maxw[u] = std::max(maxw[u], A.val[t]);
+    sw[u] = row_reduce<double>(A.deg(u), [&](i64 t) { return Ad.val[p0 + t]; });
+    swd[u] = row_reduce<double>(A.deg(u), [&](i64 t) { return Ad.val[p0 + t] * (double)A.deg(A.col[p0 + t]); });
+    for (i64 t = p0; t < A.ptr[u + 1]; ++t) maxw[u] = std::max(maxw[u], Ad.val[t]);
   }
   // per directed edge: affinity, admissibility, weak flag
   const i64 E2 = A.nnz();
@@ -512,10 +529,10 @@ AggResult aggregate(const Level& L, const Opts& o, int agg_index, int level, Agg
       bool ok = true;
       for (int k = 0; k < K && ok; ++k) {
         double d = X[s * K + k] - ystar[u * K + k];
-        ok = (A.diag[u] * (d * d)) <= (qfac * emin[u * K + k]);
+        ok = (Ad.diag[u] * (d * d)) <= (qfac * emin[u * K + k]);
       }
       D.ok[t] = ok;
-      D.weak[t] = A.val[t] < o.weak_edge_ratio * std::max(maxw[u], maxw[s]);
+      D.weak[t] = Ad.val[t] < o.weak_edge_ratio * std::max(maxw[u], maxw[s]);
     }
   }
   // initial states: hubs are seeds; nodes with only weak edges go to the dummy aggregate
@@ -646,7 +663,7 @@ void coarsest_solve(const Hier& H, const double* b, double* x) {
 // until fewer than coarsest_max_n nodes remain.
 int setup(Hier& H, i64 n, i64 m, const i32* eu, const i32* ev, const double* w) {
   Level L1;
-  int rc = build_laplacian(n, m, eu, ev, w, L1.A);
+  int rc = build_laplacian(n, m, eu, ev, w, L1.A, H.o.allow_negative != 0);
   if (rc) return rc;
   if (!connected(L1.A)) return 3;
   L1.type = L_FINEST;
@@ -1043,6 +1060,7 @@ typedef struct ora_opts {
   int ec; double tol; int max_cycles; uint64_t seed;
   double stage1_quantile, relax_fast_ratio;
   int coarsest_sweeps, dense_max;
+  int allow_negative;
 } ora_opts;
 
 void ora_opts_default(ora_opts* o) {
@@ -1057,6 +1075,7 @@ void ora_opts_default(ora_opts* o) {
   o->relax_fast_ratio = d.relax_fast_ratio;
   o->coarsest_sweeps = d.coarsest_sweeps;
   o->dense_max = d.dense_max;
+  o->allow_negative = d.allow_negative;
 }
 
 static Opts to_opts(const ora_opts* o) {
@@ -1072,6 +1091,7 @@ static Opts to_opts(const ora_opts* o) {
   d.relax_fast_ratio = o->relax_fast_ratio;
   d.coarsest_sweeps = o->coarsest_sweeps;
   d.dense_max = o->dense_max;
+  d.allow_negative = o->allow_negative;
   return d;
 }
 

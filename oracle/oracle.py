@@ -36,7 +36,7 @@ class Opts(C.Structure):
                 ("weak_edge_ratio", C.c_double), ("elim_stop_frac", C.c_double),
                 ("ec", C.c_int), ("tol", C.c_double), ("max_cycles", C.c_int),
                 ("seed", C.c_uint64), ("stage1_quantile", C.c_double), ("relax_fast_ratio", C.c_double),
-                ("coarsest_sweeps", C.c_int), ("dense_max", C.c_int)]
+                ("coarsest_sweeps", C.c_int), ("dense_max", C.c_int), ("allow_negative", C.c_int)]
 
 
 _lib = None

@@ -102,6 +102,36 @@ def grid2d_periodic(side: int = 1024) -> Graph:
     return Graph(f"grid2d_periodic_{side}", side * side, eu, ev, np.ones(eu.shape[0]))
 
 
+# Grid Laplacians with negative weights (the grid table of the paper's
+# numerical results, cases a-d): off-diagonal stencil entries as printed
+# (normalised), w = -entry, for the neighbour offsets (dx, dy) with dx >= 0
+# listed once; Neumann boundaries, i.e. the graph Laplacian of these weights.
+STENCILS = {
+    "a": [(1, 0, 1.0), (0, 1, 1.0)],                                   # 5-point
+    "b": [(1, 0, 16.0), (0, 1, 16.0), (2, 0, -1.0), (0, 2, -1.0)],     # fourth order
+    "c": [(1, 0, 0.2525), (0, 1, 0.2525), (1, 1, -0.12375), (1, -1, 0.12375)],  # rotated, agnostic U_xy
+    "d": [(1, 0, 0.5), (0, 1, 0.5), (1, 1, -0.2475)],                  # rotated, NE-SW U_xy
+}
+
+
+def grid_stencil(side: int = 1024, case: str = "b") -> Graph:
+    """side x side grid, id = i + side*j, one edge per in-grid neighbour
+    offset of the case's stencil with its (possibly negative) weight."""
+    idx = np.arange(side * side, dtype=np.int64).reshape(side, side)  # [j, i]
+    eu, ev, w = [], [], []
+    for dx, dy, wt in STENCILS[case]:
+        j0, j1 = max(0, -dy), side - max(0, dy)
+        i1 = side - dx
+        a = idx[j0:j1, 0:i1].ravel()
+        b = idx[j0 + dy:j1 + dy, dx:i1 + dx].ravel()
+        eu.append(a)
+        ev.append(b)
+        w.append(np.full(a.shape[0], wt))
+    eu = np.concatenate(eu).astype(np.int32)
+    ev = np.concatenate(ev).astype(np.int32)
+    return Graph(f"grid_stencil_{case}_{side}", side * side, eu, ev, np.concatenate(w))
+
+
 def grid3d_aniso(nside: int = 128, seed: int = SEEDS["grid3d_aniso"]) -> Graph:
     n = nside ** 3
     idx = np.arange(n, dtype=np.int64).reshape(nside, nside, nside)  # [z,y,x]
