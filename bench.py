@@ -33,7 +33,8 @@ def parse():
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--workload", default="chung_lu_2p20",
-                   choices=["chung_lu_2p20", "grid2d_64", "rgg_2p20", "grid3d_128_k32", "graph_batch_256", "lgm_1024"])
+                   choices=["chung_lu_2p20", "grid2d_64", "rgg_2p20", "grid3d_128_k32", "graph_batch_256", "lgm_1024",
+                            "negative_grid_1024"])
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU reference baseline")
     p.add_argument("--no-fp32", action="store_true")
     p.add_argument("--copy-bytes", type=int, default=0,
@@ -436,7 +437,10 @@ def cpu_baseline(name):
         g, _ = W.config(name)
         seed, what, cap = 0, "full workload", 4096
     t0 = time.perf_counter()
-    H = O.Hierarchy.lgm(1024) if name == "lgm_1024" else O.Hierarchy(g.n, g.eu, g.ev, g.w)
+    if name == "lgm_1024":
+        H = O.Hierarchy.lgm(1024)
+    else:
+        H = O.Hierarchy(g.n, g.eu, g.ev, g.w, allow_negative=1 if name == "negative_grid_1024" else 0)
     setup_s = time.perf_counter() - t0
     dt, cyc, k, dig = _oracle_rhs_loop(H, g, lambda j: W.rhs_normal(g.n, 1, seed + 7919 * j), cap)
     # the oracle's finest-level matrix-vector product (its residual), the paper's work unit
@@ -452,6 +456,33 @@ def cpu_baseline(name):
             "cycles": cyc, "solves": k, "solve_s": dt, "edges": g.m, "host": host_cpu(),
             "setup_s": setup_s, "mvm_ms": mvm_s * 1e3, "setup_mvm": setup_s / mvm_s,
             "solve_mvm_per_digit": dt / k / mvm_s / dig}
+
+
+def negative_grid_table(lamg):
+    """The four 1024 x 1024 grid Laplacians of the paper's negative-weight
+    table (ACF 0.216, 0.262, 0.816, 0.870 there): one untimed solve each with
+    the default cycle, and for (c), (d) also with the flat correction."""
+    import torch
+    from paper_1108_1310_amd import workloads as W
+    out = {}
+    for case in "abcd":
+        g = W.grid_stencil(1024, case)
+        b = torch.tensor(W.rhs_normal(g.n, 1, W.SEEDS["negative"]), device="cuda")
+        row = {"m": g.m}
+        for tag, kw in (("default", {}), ("flat_mu", dict(ec=lamg.EC_FLAT_MU, max_cycles=400))):
+            if tag == "flat_mu" and case in "ab":
+                continue
+            H = lamg.Hierarchy(g.n, g.eu, g.ev, g.w, allow_negative_weights=1, **kw)
+            t0 = time.perf_counter()
+            x, info = H.solve(b, check=False)
+            torch.cuda.synchronize()
+            row[tag] = {"levels": H.num_levels, "cycles": info["cycles"], "acf": info["acf"],
+                        "rel_residual": info["rel_residual"], "status": info["status"],
+                        "ms": 1e3 * (time.perf_counter() - t0)}
+            H.close()
+        out[case] = row
+        print(f"[bench] table case {case}: {row}", file=sys.stderr, flush=True)
+    return out
 
 
 def cycle_work_units(ns, gammas, nu):
@@ -502,7 +533,8 @@ def main():
     if a.workload == "lgm_1024":
         H = lamg.Hierarchy.lgm(1024)  # geometric hierarchy of the same periodic grid
     else:
-        H = lamg.Hierarchy(g.n, g.eu, g.ev, g.w)
+        H = lamg.Hierarchy(g.n, g.eu, g.ev, g.w,
+                           allow_negative_weights=1 if a.workload == "negative_grid_1024" else 0)
     torch.cuda.synchronize()
     setup_ms = (time.perf_counter() - t0) * 1e3
     levels = [H.dims(l) for l in range(H.num_levels)]
@@ -568,6 +600,9 @@ def main():
                              H.opts.nu_pre + H.opts.nu_post)
         lgm = {"work_units_per_cycle": W, "acf": r64["acf"], "factor_per_work_unit": r64["acf"] ** (1.0 / W),
                "paper_factor_per_work_unit": 0.5}
+    table = None
+    if a.workload == "negative_grid_1024":
+        table = negative_grid_table(lamg)
     adj = None
     if a.workload == "rgg_2p20":
         adj = adjoint_step(g, b, a.steps, a.warmup)
@@ -602,6 +637,7 @@ def main():
         "fp32_refine": out32,
         "adjoint": adj,
         "lgm": lgm,
+        "negative_grid_table": table,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

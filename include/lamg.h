@@ -83,6 +83,11 @@ typedef struct lamg_options {
   void* (*alloc)(size_t bytes, void* ctx);
   void (*dealloc)(void* ptr, void* ctx);
   void* alloc_ctx;
+  /* 1: accept negative (non-zero, finite) edge weights, Section 5.2; the
+   * caller vouches that the Laplacian is positive semi-definite.  The hub,
+   * affinity and energy-ratio tests of a level with a negative weight then
+   * use |w|.  0 (default): weights must be > 0 (LAMG_E_BAD_WEIGHT). */
+  int allow_negative_weights;
 } lamg_options;
 
 typedef struct lamg_info {
@@ -103,7 +108,8 @@ void lamg_options_default(lamg_options* o);
  *   m       number of edge entries, >= 0
  *   eu, ev  DEVICE int32[m] endpoints in [0, n), eu[e] != ev[e]; entries of the
  *           same unordered pair are summed (Section 5.1 preprocessing)
- *   w       DEVICE double[m] weights, finite and > 0
+ *   w       DEVICE double[m] weights, finite and > 0 (finite and non-zero with
+ *           o->allow_negative_weights; else LAMG_E_BAD_WEIGHT)
  *   o       HOST options (NULL = defaults)
  *   out     HOST; receives the handle, or NULL on error.
  * The inputs are copied; the caller may free them on return.  The handle owns

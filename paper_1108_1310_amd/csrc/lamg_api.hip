@@ -292,6 +292,7 @@ void lamg_options_default(lamg_options* o) {
   o->alloc = nullptr;
   o->dealloc = nullptr;
   o->alloc_ctx = nullptr;
+  o->allow_negative_weights = 0;
 }
 
 const char* lamg_last_error(void) { return g_last_error; }
@@ -315,7 +316,8 @@ static bool opts_ok(const lamg_options& o) {
          o.tv_k_max >= o.tv_k_min && o.tv_k_max <= 10 && o.tv_sweeps >= 0 && o.q_max > 1.0 && o.coarsest_max_n >= 2 &&
          o.elim_max_degree >= 0 && o.stage1_quantile >= 0.0 && o.stage1_quantile <= 1.0 && o.tol >= 0 &&
          o.max_cycles >= 0 && o.coarsest_sweeps >= 1 && o.dense_max >= 1 && o.dense_max <= 8192 && o.tail_max_n >= 0 &&
-         (o.alloc == nullptr) == (o.dealloc == nullptr);
+         (o.alloc == nullptr) == (o.dealloc == nullptr) &&
+         (o.allow_negative_weights == 0 || o.allow_negative_weights == 1);
 }
 
 }  // extern "C"

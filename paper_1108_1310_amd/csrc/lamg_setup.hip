@@ -216,13 +216,21 @@ void merge_triples(Hierarchy* H, Tmp& tmp, Level& C, int nrows, uint64_t* keys, 
 
 // ------------------------------------------------------------ finest level
 __global__ void k_validate(int64_t m, int64_t n, const int32_t* __restrict__ eu, const int32_t* __restrict__ ev,
-                           const double* __restrict__ w, int* flags) {
+                           const double* __restrict__ w, int allow_negative, int* flags) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= m) return;
   const int a = eu[e], b = ev[e];
   if (a < 0 || a >= n || b < 0 || b >= n || a == b) atomicOr(&flags[0], 1);
   const double x = w[e];
-  if (!(x > 0) || !isfinite(x)) atomicOr(&flags[0], 2);
+  if (!isfinite(x) || (allow_negative ? x == 0 : !(x > 0))) atomicOr(&flags[0], 2);
+}
+__global__ void k_count_negative(int64_t m, const double* __restrict__ v, int* cnt) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < m && v[e] < 0) atomicAdd(cnt, 1);
+}
+__global__ void k_abs(int64_t m, const double* __restrict__ v, double* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < m) out[e] = fabs(v[e]);
 }
 __global__ void k_edge_keys(int64_t m, int64_t n, const int32_t* __restrict__ eu, const int32_t* __restrict__ ev,
                             uint64_t* __restrict__ key) {
@@ -272,7 +280,8 @@ lamg_status build_finest(Hierarchy* H, int64_t n, int64_t m, const int32_t* eu, 
   Tmp tmp;
   int* flags = tmp.get<int>(4);
   LAMG_HIP(hipMemsetAsync(flags, 0, 4 * sizeof(int), s));
-  if (m > 0) hipLaunchKernelGGL(k_validate, grid1(m), dim3(256), 0, s, m, n, eu, ev, w, flags);
+  if (m > 0)
+    hipLaunchKernelGGL(k_validate, grid1(m), dim3(256), 0, s, m, n, eu, ev, w, H->o.allow_negative_weights, flags);
   const int f = to_host(s, flags);
   if (f & 1) return LAMG_E_INVALID_ARG;
   if (f & 2) return LAMG_E_BAD_WEIGHT;
@@ -1149,10 +1158,28 @@ int aggregate(Hierarchy* H, int l, int agg_index) {
   o.sw = tmp.get<double>(n);
   o.swd = tmp.get<double>(n);
   o.maxw = tmp.get<double>(n);
-  hipLaunchKernelGGL(k_node_short, grid1(n), dim3(256), 0, s, n, K, F.rp, F.ci, F.val, F.diag, deg, F.tv, o);
+  // Section 5.2: on a level with a negative weight the hub, affinity and
+  // energy tests use |w| (the Laplacian of the absolute weights, diagonal in
+  // the fixed row order); other levels use their own matrix
+  const double* tval = F.val;
+  const double* tdiag = F.diag;
+  if (H->o.allow_negative_weights && F.nnz > 0) {
+    int* nneg = tmp.get<int>(1);
+    LAMG_HIP(hipMemsetAsync(nneg, 0, sizeof(int), s));
+    hipLaunchKernelGGL(k_count_negative, grid1(F.nnz), dim3(256), 0, s, (int64_t)F.nnz, (const double*)F.val, nneg);
+    if (to_host(s, nneg) > 0) {
+      double* av = tmp.get<double>(F.nnz);
+      double* ad = tmp.get<double>(n);
+      hipLaunchKernelGGL(k_abs, grid1(F.nnz), dim3(256), 0, s, (int64_t)F.nnz, (const double*)F.val, av);
+      row_sums(s, tmp, n, F.rp, av, ad);
+      tval = av;
+      tdiag = ad;
+    }
+  }
+  hipLaunchKernelGGL(k_node_short, grid1(n), dim3(256), 0, s, n, K, F.rp, F.ci, tval, tdiag, deg, F.tv, o);
   if (F.all.nlong)
     hipLaunchKernelGGL(k_node_long, grid1((int64_t)F.all.nlong * 64), dim3(256), 0, s, F.all.longrows, F.all.nlong, K,
-                       F.rp, F.ci, F.val, F.diag, deg, F.tv, o);
+                       F.rp, F.ci, tval, tdiag, deg, F.tv, o);
   const int64_t E2 = F.nnz;
   F.aff = dnew<double>(H, E2);
   F.ok = dnew<uint8_t>(H, E2);
@@ -1160,7 +1187,7 @@ int aggregate(Hierarchy* H, int l, int agg_index) {
   F.hub = dnew<uint8_t>(H, n);
   F.state = dnew<int>(H, n);
   const double qfac = 2.0 * (H->o.q_max - 1.0);
-  hipLaunchKernelGGL(k_edges, grid1(n), dim3(256), 0, s, n, K, F.rp, F.ci, F.val, F.diag, F.tv, o, qfac,
+  hipLaunchKernelGGL(k_edges, grid1(n), dim3(256), 0, s, n, K, F.rp, F.ci, tval, tdiag, F.tv, o, qfac,
                      H->o.weak_edge_ratio, F.aff, F.ok, F.weak);
   int* st = F.state;
   int* seedof = tmp.get<int>(n);

@@ -37,7 +37,8 @@ class Options(C.Structure):
                 ("tail_max_n", C.c_int),
                 ("ec", C.c_int), ("precision", C.c_int), ("tol", C.c_double), ("max_cycles", C.c_int),
                 ("warm_start", C.c_int), ("seed", C.c_uint64), ("stream", C.c_void_p),
-                ("alloc", ALLOC_FN), ("dealloc", DEALLOC_FN), ("alloc_ctx", C.c_void_p)]
+                ("alloc", ALLOC_FN), ("dealloc", DEALLOC_FN), ("alloc_ctx", C.c_void_p),
+                ("allow_negative_weights", C.c_int)]
 
 
 class Info(C.Structure):

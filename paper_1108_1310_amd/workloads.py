@@ -34,7 +34,7 @@ import math
 import numpy as np
 
 SEEDS = {"grid2d": 101, "chung_lu": 102, "grid3d_aniso": 103,
-         "graph_batch": 104, "rgg": 105, "lgm": 106}
+         "graph_batch": 104, "rgg": 105, "lgm": 106, "negative": 107}
 # independent random streams per workload
 _S_GRAPH, _S_WEIGHT, _S_RHS, _S_LABEL = 0, 1, 2, 4
 
@@ -289,6 +289,9 @@ def config(name: str):
     if name == "grid3d_128_k32":
         g = grid3d_aniso(128)
         return g, rhs_normal(g.n, 32, SEEDS["grid3d_aniso"])
+    if name == "negative_grid_1024":
+        g = grid_stencil(1024, "b")
+        return g, rhs_normal(g.n, 1, SEEDS["negative"])
     if name == "lgm_1024":
         g = grid2d_periodic(1024)
         return g, rhs_normal(g.n, 1, SEEDS["lgm"])
