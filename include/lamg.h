@@ -178,6 +178,27 @@ lamg_status lamg_solve_batch(int32_t count, const lamg_handle* hs, const int32_t
 lamg_status lamg_edge_gradient(int64_t m, const int32_t* eu, const int32_t* ev, const double* x,
                                const double* lam, double* grad_w, void* stream);
 
+/* Lowest eigenpairs (Section 6.4, the eigensolver: the LAMG solver inside a
+ * block Rayleigh-quotient iteration, the alternative that section names to
+ * FAS).  Computes the k smallest eigenvalues of A on the zero-sum subspace
+ * (the non-zero part of the spectrum of a connected graph's Laplacian) and
+ * their eigenvectors by LOBPCG preconditioned with `cycles` LAMG cycles of
+ * this hierarchy (its solve options: precision, energy correction).
+ *   X      DEVICE double[n * k] row-major (eigenvector index fastest), in:
+ *          the initial block (e.g. seeded random; projected to zero-sum
+ *          here; its columns must be linearly independent after that),
+ *          out: orthonormal eigenvectors in ascending eigenvalue order.
+ *   evals  HOST double[k] out, ascending.
+ *   tol    stop when ||A x_j - lambda_j x_j||_2 <= tol * lambda_j for all j.
+ *   max_iter  LOBPCG iterations at most; cycles >= 1 per preconditioner call.
+ *   iters  HOST int32 out (nullable): iterations taken.
+ *   resid  HOST double[k] out (nullable): ||A x_j - lambda_j x_j|| / lambda_j.
+ * 1 <= k <= 8 and 4k <= n, else LAMG_E_INVALID_ARG.  LAMG_E_NOT_CONVERGED
+ * still writes the last iterate; LAMG_E_BREAKDOWN when the search space
+ * loses rank.  Runs on the hierarchy's stream and returns after it. */
+lamg_status lamg_eigs(lamg_handle h, int32_t k, double* X, double* evals, double tol, int32_t max_iter,
+                      int32_t cycles, int32_t* iters, double* resid);
+
 /* Change solve-phase options of an existing hierarchy (precision, ec, tol,
  * max_cycles, warm_start, stream); setup-phase fields are ignored. */
 lamg_status lamg_set_solve_options(lamg_handle h, const lamg_options* o);

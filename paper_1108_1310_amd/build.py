@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpaper_lamg.so")
-SOURCES = ["lamg_solve_kernels.hip", "lamg_setup.hip", "lamg_tail.hip", "lamg_mv.hip", "lamg_api.hip", "lamg_test_api.hip"]
+SOURCES = ["lamg_solve_kernels.hip", "lamg_setup.hip", "lamg_tail.hip", "lamg_mv.hip", "lamg_api.hip", "lamg_test_api.hip",
+           "lamg_eigs.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

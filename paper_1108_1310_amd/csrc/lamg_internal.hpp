@@ -338,6 +338,9 @@ void tail_run_next_mv(Hierarchy* H);
 void mv_release(Hierarchy* H);
 void mv_drop_graphs(Hierarchy* H);
 lamg_status solve_multi(Hierarchy* H, int k, const double* B, double* X, lamg_info* info);
+void mv_neg_apply(Hierarchy* H, int k, const double* Xp, double* Yp);
+void mv_precondition(Hierarchy* H, int k, const double* Bp, double* Xp, int cycles);
+void mv_project(Hierarchy* H, int k, double* Xp);
 
 }  // namespace lamg
 

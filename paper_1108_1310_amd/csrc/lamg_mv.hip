@@ -766,6 +766,61 @@ lamg_status solve_multi(Hierarchy* H, int k, const double* B, double* X, lamg_in
   return LAMG_OK;
 }
 
+// Y = -A X for an n x k block of level 0 in colour order (the residual kernel
+// with b = 0).
+void mv_neg_apply(Hierarchy* H, int k, const double* Xp, double* Yp) {
+  mv_alloc(H, k);
+  residual_mv<double>(H->s, H->lv[0], k, nullptr, Xp, Yp);
+}
+
+// Xp <- `cycles` cycles of the correction-form outer loop on A x = Bp - mean(Bp)
+// from x = 0, every column iterating (colour order, level 0).  The inner
+// cycle runs in the handle's precision.  Xp leaves zero-mean.
+void mv_precondition(Hierarchy* H, int k, const double* Bp, double* Xp, int cycles) {
+  mv_alloc(H, k);
+  MVWork& W = H->mv;
+  Level& L = H->lv[0];
+  hipStream_t s = H->s;
+  const int n = L.n;
+  const int64_t nk = (int64_t)n * k;
+  for (int c = 0; c < k; ++c) W.hmask[c] = 1;
+  LAMG_HIP(hipMemcpyAsync(W.mask, W.hmask, (size_t)k * sizeof(int), hipMemcpyHostToDevice, s));
+  fill_mv<double>(s, Xp, nk);
+  hipLaunchKernelGGL(k_copy_mv<double>, gridn(nk), dim3(MVT), 0, s, nk, Bp, W.R);
+  const bool fp32 = H->o.precision == LAMG_FP32_REFINE;
+  for (int it = 0; it < cycles; ++it) {
+    if (it > 0) residual_mv<double>(s, L, k, Bp, Xp, W.R);
+    col_reduce<double>(s, H, W.R, n, 0, RS_RMEAN, (double)n);
+    const double* rm = W.res + RS_RMEAN * k;
+    if (!fp32) {
+      Vecs<double>& v = W.v64[0];
+      hipLaunchKernelGGL(k_mv_rhs<double>, gridn(nk), dim3(MVT), 0, s, nk, k, (const double*)W.R, rm, v.b);
+      fill_mv<double>(s, v.x, nk);
+      cycle_graph_mv<double>(H);
+      hipLaunchKernelGGL(k_mv_add<double>, gridn(nk), dim3(MVT), 0, s, nk, k, (const double*)v.x,
+                         (const int*)W.mask, Xp);
+    } else {
+      Vecs<float>& v = W.v32[0];
+      hipLaunchKernelGGL(k_mv_rhs<float>, gridn(nk), dim3(MVT), 0, s, nk, k, (const double*)W.R, rm, v.b);
+      fill_mv<float>(s, v.x, nk);
+      cycle_graph_mv<float>(H);
+      hipLaunchKernelGGL(k_mv_add<float>, gridn(nk), dim3(MVT), 0, s, nk, k, (const float*)v.x, (const int*)W.mask,
+                         Xp);
+    }
+    subtract_mean_mv<double>(s, H, Xp, n, W.mask);
+  }
+  LAMG_HIP(hipGetLastError());
+}
+
+// Zero-mean columns of an n x k block of level 0.
+void mv_project(Hierarchy* H, int k, double* Xp) {
+  mv_alloc(H, k);
+  MVWork& W = H->mv;
+  for (int c = 0; c < k; ++c) W.hmask[c] = 1;
+  LAMG_HIP(hipMemcpyAsync(W.mask, W.hmask, (size_t)k * sizeof(int), hipMemcpyHostToDevice, H->s));
+  subtract_mean_mv<double>(H->s, H, Xp, H->lv[0].n, W.mask);
+}
+
 }  // namespace lamg
 
 using namespace lamg;

@@ -76,6 +76,7 @@ def lib():
                                            C.POINTER(Info)]),
             "lamg_set_solve_options": (C.c_int, [vp, C.POINTER(Options)]),
             "lamg_edge_gradient": (C.c_int, [i64, vp, vp, vp, vp, vp, vp]),
+            "lamg_eigs": (C.c_int, [vp, i32, vp, vp, d, i32, i32, C.POINTER(i32), vp]),
             "lamg_free": (None, [vp]),
             "lamg_status_str": (C.c_char_p, [C.c_int]),
             "lamg_last_error": (C.c_char_p, []),
@@ -251,6 +252,24 @@ class Hierarchy:
         d = info.as_dict()
         d["status"] = rc
         return x, d
+
+    def eigs(self, k: int, x0, tol: float = 1e-8, max_iter: int = 200, cycles: int = 1, check: bool = True):
+        """The k lowest eigenpairs of A on the zero-sum subspace (Section 6.4:
+        LOBPCG preconditioned by LAMG cycles of this hierarchy).  ``x0``:
+        [n, k] initial block (seeded random).  Returns (evals [k] float64
+        host, X [n, k] on the GPU, info dict with iters, resid, status)."""
+        X = _dev(x0, torch.float64).clone().contiguous()
+        if X.dim() != 2 or X.shape[0] != self.n or X.shape[1] != k:
+            raise ValueError("x0 must be [n, k]")
+        ev = np.zeros(k, np.float64)
+        rs = np.zeros(k, np.float64)
+        it = C.c_int32(0)
+        self.set_solve_options()  # the current stream
+        rc = lib().lamg_eigs(self.h, int(k), _ptr(X), C.c_void_p(ev.ctypes.data), float(tol), int(max_iter),
+                             int(cycles), C.byref(it), C.c_void_p(rs.ctypes.data))
+        if check and rc not in (OK, E_NOT_CONVERGED):
+            _check(rc, "lamg_eigs")
+        return ev, X, {"iters": int(it.value), "resid": rs, "status": rc}
 
     # ------------------------------------------------------ inspection (tests)
     @property

@@ -1,0 +1,120 @@
+"""LAMG eigensolver (Section 6.4: the LAMG solver inside a block
+Rayleigh-quotient iteration, LOBPCG) through the C-ABI, against the dense
+eigenpair oracle and closed-form grid spectra."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import eigs as E
+from paper_1108_1310_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-8  # ||A x - lambda x|| <= TOL * lambda per pair
+
+
+def _case(name):
+    print(f"[case] {name}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def lg():
+    from paper_1108_1310_amd import lamg
+    lamg.lib()
+    return lamg
+
+
+def _check_against(evals, X, lam_ref, vec_ref, nxt, a=None):
+    """Eigenvalues to 1e-9 relative; each eigenvector inside the span of the
+    oracle's eigenvectors of (numerically) the same eigenvalue: the
+    component outside the reference subspace is bounded by the residual over
+    the gap to the rest of the spectrum."""
+    k = lam_ref.size
+    assert np.allclose(evals, lam_ref, rtol=1e-9, atol=0), (evals, lam_ref)
+    x = X.cpu().numpy()
+    assert np.allclose(x.T @ x, np.eye(k), atol=1e-10)
+    assert np.allclose(x.sum(axis=0), 0, atol=1e-9 * math.sqrt(x.shape[0]))
+    full = np.concatenate([lam_ref, [nxt]])
+    for j in range(k):
+        near = np.abs(lam_ref - lam_ref[j]) <= 1e-9 * lam_ref[j]
+        U = vec_ref[:, near]
+        out = x[:, j] - U @ (U.T @ x[:, j])
+        others = full[np.abs(full - lam_ref[j]) > 1e-9 * lam_ref[j]]
+        gap = np.min(np.abs(others - lam_ref[j]))
+        assert np.linalg.norm(out) <= 10 * TOL * lam_ref[j] / gap + 1e-10, (j, np.linalg.norm(out))
+    if a is not None:
+        r = a @ x - x * evals[None, :]
+        assert np.all(np.linalg.norm(r, axis=0) <= 1.01 * TOL * evals)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_grid_closed_form(lg, prec):
+    """40 x 24 unit grid: the spectrum is the sums of the two paths' spectra."""
+    _case(f"eigs grid 40x24 prec={prec}")
+    g = W.grid2d(40, 24)
+    k = 5
+    H = lg.Hierarchy(g.n, g.eu, g.ev, g.w, precision=prec)
+    x0 = W.rhs_normal(g.n, k, seed=11)
+    ev, X, info = H.eigs(k, x0, tol=TOL, max_iter=200, cycles=1)
+    assert info["status"] == lg.OK, info
+    pa = np.array([2 - 2 * math.cos(math.pi * j / 40) for j in range(40)])
+    pb = np.array([2 - 2 * math.cos(math.pi * j / 24) for j in range(24)])
+    spec = np.sort((pa[:, None] + pb[None, :]).ravel())
+    assert np.allclose(ev, spec[1:k + 1], rtol=1e-9)
+    a = E.dense_laplacian(g.n, g.eu, g.ev, g.w)
+    lam, vec, nxt = E.lowest_eigenpairs(a, k)
+    _check_against(ev, X, lam, vec, nxt, a)
+    assert np.all(info["resid"] <= TOL)
+
+
+@pytest.mark.parametrize("name,k,cycles", [("er", 6, 1), ("chung_lu", 4, 2), ("rgg", 8, 1)])
+def test_random_graphs_against_dense(lg, name, k, cycles):
+    _case(f"eigs {name} k={k} cycles={cycles}")
+    if name == "er":
+        g = W.erdos_renyi(2500, 8.0, 5)
+    elif name == "chung_lu":
+        g = W.chung_lu(1 << 11)
+    else:
+        g = W.rgg(1 << 11)
+    H = lg.Hierarchy(g.n, g.eu, g.ev, g.w)
+    ev, X, info = H.eigs(k, W.rhs_normal(g.n, k, seed=3), tol=TOL, max_iter=300, cycles=cycles)
+    assert info["status"] == lg.OK, info
+    a = E.dense_laplacian(g.n, g.eu, g.ev, g.w)
+    lam, vec, nxt = E.lowest_eigenpairs(a, k)
+    _check_against(ev, X, lam, vec, nxt, a)
+
+
+def test_large_rgg_residuals(lg):
+    """2^16-point geometric graph: residual, orthonormality and zero mean of
+    every pair from the edge list (the dense oracle is out of reach here)."""
+    _case("eigs rgg 2^16 k=4")
+    g = W.rgg(1 << 16)
+    k = 4
+    H = lg.Hierarchy(g.n, g.eu, g.ev, g.w)
+    ev, X, info = H.eigs(k, W.rhs_normal(g.n, k, seed=7), tol=TOL, max_iter=300)
+    assert info["status"] == lg.OK, info
+    x = X.cpu().numpy()
+    ax = np.zeros_like(x)
+    d = (x[g.eu] - x[g.ev]) * g.w[:, None]
+    np.add.at(ax, g.eu, d)
+    np.add.at(ax, g.ev, -d)
+    r = np.linalg.norm(ax - x * ev[None, :], axis=0)
+    assert np.all(r <= 1.01 * TOL * ev), (r, ev)
+    assert np.allclose(x.T @ x, np.eye(k), atol=1e-10)
+    assert np.all(np.diff(ev) >= 0) and ev[0] > 0
+
+
+def test_invalid_and_unconverged(lg):
+    _case("eigs argument checks")
+    g = W.grid2d(8, 8)
+    H = lg.Hierarchy(g.n, g.eu, g.ev, g.w)
+    x0 = W.rhs_normal(g.n, 9, seed=1)
+    ev, X, info = H.eigs(9, x0, check=False)
+    assert info["status"] == lg.E_INVALID_ARG  # k > 8
+    ev, X, info = H.eigs(2, x0[:, :2], max_iter=0, check=False)
+    assert info["status"] == lg.E_NOT_CONVERGED and info["iters"] == 0
+    # the Rayleigh-Ritz values of the initial block bound the true ones from above
+    lam, _, _ = E.lowest_eigenpairs(E.dense_laplacian(g.n, g.eu, g.ev, g.w), 2)
+    assert np.all(ev >= lam * (1 - 1e-12))
