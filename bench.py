@@ -37,6 +37,8 @@ def parse():
                             "negative_grid_1024"])
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU reference baseline")
     p.add_argument("--no-fp32", action="store_true")
+    p.add_argument("--eigs", type=int, default=4,
+                   help="lowest eigenpairs timed beside the solve on the same hierarchy (0: skip)")
     p.add_argument("--copy-bytes", type=int, default=0,
                    help="only run a plain device copy of this many bytes (HBM counter calibration) and exit")
     return p.parse_args()
@@ -484,6 +486,29 @@ def negative_grid_table(lamg):
     return out
 
 
+def eigs_step(H, g, k, lamg, precision):
+    """The eigensolver (LOBPCG preconditioned by one LAMG cycle, run in
+    `precision`) on the workload's hierarchy: one untimed call, then one
+    timed call from the same seeded block.  No CPU leg: the dense
+    eigen-decomposition the oracle uses does not fit graphs of this size."""
+    import torch
+    from paper_1108_1310_amd import workloads as W
+    x0 = torch.tensor(W.rhs_normal(g.n, k, seed=101), device="cuda")
+    prec = H.opts.precision
+    H.set_solve_options(precision=precision)
+    H.eigs(k, x0, tol=1e-8, max_iter=500, cycles=1, check=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev, X, info = H.eigs(k, x0, tol=1e-8, max_iter=500, cycles=1, check=False)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    H.set_solve_options(precision=prec)
+    return {"k": k, "tol": 1e-8, "cycle": "fp64" if precision == lamg.FP64 else "fp32+refine", "status": lamg.lib().lamg_status_str(info["status"]).decode(),
+            "iterations": info["iters"], "ms": ms,
+            "ms_per_iteration": ms / max(1, info["iters"]), "eigenvalues": [float(v) for v in ev],
+            "rel_residuals": [float(v) for v in info["resid"]]}
+
+
 def cycle_work_units(ns, gammas, nu):
     """Relaxation work of one cycle in finest-level sweeps: nu sweeps per body
     of every level above the coarsest, times its visits (the fractional
@@ -610,6 +635,14 @@ def main():
     if a.workload == "rgg_2p20":
         adj = adjoint_step(g, b, a.steps, a.warmup)
         print(f"[bench] gradient {adj['ms_per_gradient']:.1f} ms", file=sys.stderr, flush=True)
+    eig = None
+    if a.eigs > 0 and a.workload not in ("lgm_1024", "negative_grid_1024"):
+        eig = {}
+        for prec, key in ((lamg.FP64, "fp64_cycle"), (lamg.FP32_REFINE, "fp32_cycle")):
+            e = eigs_step(H, g, a.eigs, lamg, prec)
+            e["mvm_units"] = 1e3 * e["ms"] / mvm_us
+            eig[key] = e
+            print(f"[bench] eigs ({key}) {e['ms']:.1f} ms, {e['iterations']} iterations", file=sys.stderr, flush=True)
     cpu = None
     if not a.no_cpu:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
@@ -642,6 +675,7 @@ def main():
         "adjoint": adj,
         "lgm": lgm,
         "negative_grid_table": table,
+        "eigs": eig,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -32,8 +32,8 @@ namespace lamg {
 namespace {
 
 constexpr int ET = 256;          // threads per block of the eigensolver kernels
-constexpr int GRAM_ROWS = 64;    // rows of S and T staged in LDS per tile
-constexpr int GRAM_BLOCKS = 512; // fixed grid of the Gram kernel (fixes the sum order)
+constexpr int GRAM_ROWS = 32;    // rows of S and T staged in LDS per tile
+constexpr int GRAM_BLOCKS = 1024; // fixed grid of the Gram kernel (fixes the sum order)
 constexpr int EIG_MAX_K = 8;    // eigenpairs asked for
 constexpr int EIG_MAX_KB = 16;  // iterated block: the asked pairs plus guard vectors
 constexpr int QMAX = 3 * EIG_MAX_KB;
@@ -42,7 +42,7 @@ struct Blocks3 {
   const double* p[3];
 };
 
-// part[b][i * q + j] = sum over the rows of block b's tiles of S[r, i] T[r, j],
+// part[i * q + j][b] = sum over the rows of block b's tiles of S[r, i] T[r, j],
 // where column i of S is column i % k of block p[i / k] (likewise T); tiles
 // are taken by blocks round-robin, rows in order inside a tile.
 __global__ __launch_bounds__(ET) void k_gram(int n, int k, int nb, Blocks3 S, Blocks3 T, double* __restrict__ part) {
@@ -78,32 +78,51 @@ __global__ __launch_bounds__(ET) void k_gram(int n, int k, int nb, Blocks3 S, Bl
 #pragma unroll
   for (int t = 0; t < (QMAX * QMAX + ET - 1) / ET; ++t) {
     const int pij = threadIdx.x + t * ET;
-    if (pij < qq) part[(size_t)blockIdx.x * qq + pij] = acc[t];
+    if (pij < qq) part[(size_t)pij * gridDim.x + blockIdx.x] = acc[t];
   }
 }
 
-// g[p] = sum over blocks b = 0, 1, ... of part[b][p]
-__global__ void k_gram_finish(int qq, int nblk, const double* __restrict__ part, double* __restrict__ g) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= qq) return;
+// g[p] = sum over blocks b of part[p][b]: one workgroup per entry, each
+// thread sums a strided slice in order, then a fixed pairwise tree in LDS
+__global__ __launch_bounds__(ET) void k_gram_finish(int nblk, const double* __restrict__ part, double* __restrict__ g) {
+  __shared__ double red[ET];
+  const int p = blockIdx.x;
+  const double* row = part + (size_t)p * nblk;
   double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += part[(size_t)b * qq + p];
-  g[p] = s;
+  for (int b = threadIdx.x; b < nblk; b += ET) s += row[b];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = ET / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) g[p] = red[0];
 }
 
 // out[r, c] = sum_{i < nb k} Src[r, i] C[i, c]  (C is q x k row-major; the
-// sum runs over the source columns in order)
+// sum runs over the source columns in order).  One thread per row: the row
+// is read once, C at wave-uniform addresses.
 __global__ __launch_bounds__(ET) void k_combine(int n, int k, int nb, Blocks3 S, const double* __restrict__ Cm,
                                                 double* __restrict__ out) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= (int64_t)n * k) return;
-  const int r = (int)(g / k), c = (int)(g % k);
-  double s = 0.0;
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  double acc[EIG_MAX_KB];
+#pragma unroll
+  for (int c = 0; c < EIG_MAX_KB; ++c) acc[c] = 0.0;
   for (int blk = 0; blk < nb; ++blk) {
     const double* row = S.p[blk] + (size_t)r * k;
-    for (int i = 0; i < k; ++i) s += row[i] * Cm[(blk * k + i) * k + c];
+    for (int i = 0; i < k; ++i) {
+      const double v = row[i];
+      const double* crow = Cm + (blk * k + i) * k;
+#pragma unroll
+      for (int c = 0; c < EIG_MAX_KB; ++c)
+        if (c < k) acc[c] += v * crow[c];
+    }
   }
-  out[g] = s;
+  double* o = out + (size_t)r * k;
+#pragma unroll
+  for (int c = 0; c < EIG_MAX_KB; ++c)
+    if (c < k) o[c] = acc[c];
 }
 
 // splitmix64 (Vigna): a counter-based generator, mapped to [-1, 1)
@@ -270,8 +289,7 @@ struct EigWork {
     const int q = nb * k, qq = q * q;
     hipStream_t s = H->s;
     hipLaunchKernelGGL(k_gram, dim3(GRAM_BLOCKS), dim3(ET), 0, s, n, k, nb, S, T, part);
-    hipLaunchKernelGGL(k_gram_finish, dim3((qq + ET - 1) / ET), dim3(ET), 0, s, qq, GRAM_BLOCKS,
-                       (const double*)part, g);
+    hipLaunchKernelGGL(k_gram_finish, dim3(qq), dim3(ET), 0, s, GRAM_BLOCKS, (const double*)part, g);
     LAMG_HIP(hipMemcpyAsync(hg, g, (size_t)qq * sizeof(double), hipMemcpyDeviceToHost, s));
     LAMG_HIP(hipStreamSynchronize(s));
     return std::vector<double>(hg, hg + qq);
@@ -281,7 +299,7 @@ struct EigWork {
     hipStream_t s = H->s;
     LAMG_HIP(hipMemcpyAsync(cm + 0, C.data() + (size_t)row0 * k, (size_t)nb * k * k * sizeof(double),
                             hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_combine, grid_nk((int64_t)n * k), dim3(ET), 0, s, n, k, nb, S, (const double*)cm, out);
+    hipLaunchKernelGGL(k_combine, grid_nk(n), dim3(ET), 0, s, n, k, nb, S, (const double*)cm, out);
     // the coefficient buffer is reused by the next combine: wait for this one
     LAMG_HIP(hipStreamSynchronize(s));
   }
