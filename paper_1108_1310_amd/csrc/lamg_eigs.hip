@@ -44,42 +44,89 @@ struct Blocks3 {
 
 // part[i * q + j][b] = sum over the rows of block b's tiles of S[r, i] T[r, j],
 // where column i of S is column i % k of block p[i / k] (likewise T); tiles
-// are taken by blocks round-robin, rows in order inside a tile.
+// are taken by blocks round-robin, rows in order inside a tile.  A thread's
+// staging slots (LDS index e = r q + col) are fixed, so their source offsets
+// are computed once, and the next tile is loaded into registers while the
+// current one is reduced.
+constexpr int GRAM_LPT = (GRAM_ROWS * QMAX + ET - 1) / ET;  // staging slots per thread
+__device__ inline const double* pick(const Blocks3& B, int blk) {
+  return blk == 0 ? B.p[0] : (blk == 1 ? B.p[1] : B.p[2]);
+}
 __global__ __launch_bounds__(ET) void k_gram(int n, int k, int nb, Blocks3 S, Blocks3 T, double* __restrict__ part) {
   __shared__ double sS[GRAM_ROWS * QMAX];
   __shared__ double sT[GRAM_ROWS * QMAX];
   const int q = nb * k, qq = q * q;
-  double acc[(QMAX * QMAX + ET - 1) / ET];
+  const double* sp[GRAM_LPT];
+  const double* tp[GRAM_LPT];
+  int off[GRAM_LPT];
 #pragma unroll
-  for (int t = 0; t < (QMAX * QMAX + ET - 1) / ET; ++t) acc[t] = 0.0;
+  for (int t = 0; t < GRAM_LPT; ++t) {
+    const int e = threadIdx.x + t * ET;
+    const int r = e / q, col = e % q, blk = min(col / k, nb - 1), c = col % k;
+    off[t] = r * k + c;
+    sp[t] = pick(S, blk);
+    tp[t] = pick(T, blk);
+  }
+  // running sums, one slot per (i, j), each owned by one thread
+  __shared__ double sAcc[QMAX * QMAX];
+  for (int pij = threadIdx.x; pij < qq; pij += ET) sAcc[pij] = 0.0;
   const int ntiles = (n + GRAM_ROWS - 1) / GRAM_ROWS;
-  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const int r0 = tile * GRAM_ROWS;
-    const int rows = min(GRAM_ROWS, n - r0);
-    for (int e = threadIdx.x; e < rows * q; e += ET) {
-      const int r = e / q, col = e % q, blk = col / k, c = col % k;
-      const size_t o = (size_t)(r0 + r) * k + c;
-      sS[r * q + col] = S.p[blk][o];
-      sT[r * q + col] = T.p[blk][o];
-    }
-    __syncthreads();
+  double ps[GRAM_LPT], pt[GRAM_LPT];
+  int tile = blockIdx.x;
+  if (tile < ntiles) {
+    const int r0 = tile * GRAM_ROWS, lim = min(GRAM_ROWS, n - r0) * q;
+    const size_t base = (size_t)r0 * k;
 #pragma unroll
-    for (int t = 0; t < (QMAX * QMAX + ET - 1) / ET; ++t) {
-      const int pij = threadIdx.x + t * ET;
-      if (pij < qq) {
-        const int i = pij / q, j = pij % q;
-        double a = acc[t];
-        for (int r = 0; r < rows; ++r) a += sS[r * q + i] * sT[r * q + j];
-        acc[t] = a;
+    for (int t = 0; t < GRAM_LPT; ++t)
+      if ((int)threadIdx.x + t * ET < lim) {
+        ps[t] = sp[t][base + off[t]];
+        pt[t] = tp[t][base + off[t]];
+      }
+  }
+  for (; tile < ntiles; tile += gridDim.x) {
+    const int rows = min(GRAM_ROWS, n - tile * GRAM_ROWS);
+#pragma unroll
+    for (int t = 0; t < GRAM_LPT; ++t) {
+      const int e = threadIdx.x + t * ET;
+      if (e < rows * q) {
+        sS[e] = ps[t];
+        sT[e] = pt[t];
       }
     }
     __syncthreads();
-  }
+    const int nt = tile + gridDim.x;
+    if (nt < ntiles) {
+      const int r0 = nt * GRAM_ROWS, lim = min(GRAM_ROWS, n - r0) * q;
+      const size_t base = (size_t)r0 * k;
 #pragma unroll
-  for (int t = 0; t < (QMAX * QMAX + ET - 1) / ET; ++t) {
-    const int pij = threadIdx.x + t * ET;
-    if (pij < qq) part[(size_t)pij * gridDim.x + blockIdx.x] = acc[t];
+      for (int t = 0; t < GRAM_LPT; ++t)
+        if ((int)threadIdx.x + t * ET < lim) {
+          ps[t] = sp[t][base + off[t]];
+          pt[t] = tp[t][base + off[t]];
+        }
+    }
+#pragma unroll 1
+    for (int pij = threadIdx.x; pij < qq; pij += ET) {
+      const int i = pij / q, j = pij % q;
+      double a = sAcc[pij];
+      int r = 0;
+      // eight rows' operands in flight, then their products in row order
+      for (; r + 8 <= rows; r += 8) {
+        double xv[8], yv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          xv[u] = sS[(r + u) * q + i];
+          yv[u] = sT[(r + u) * q + j];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a += xv[u] * yv[u];
+      }
+      for (; r < rows; ++r) a += sS[r * q + i] * sT[r * q + j];
+      sAcc[pij] = a;
+    }
+    __syncthreads();
   }
+  for (int pij = threadIdx.x; pij < qq; pij += ET) part[(size_t)pij * gridDim.x + blockIdx.x] = sAcc[pij];
 }
 
 // g[p] = sum over blocks b of part[p][b]: one workgroup per entry, each
