@@ -37,6 +37,7 @@ constexpr int GRAM_BLOCKS = 1024; // fixed grid of the Gram kernel (fixes the su
 constexpr int EIG_MAX_K = 8;    // eigenpairs asked for
 constexpr int EIG_MAX_KB = 16;  // iterated block: the asked pairs plus guard vectors
 constexpr int QMAX = 3 * EIG_MAX_KB;
+constexpr int CM_SLOTS = 8;     // coefficient slots of the combinations between synchronisations
 
 struct Blocks3 {
   const double* p[3];
@@ -320,16 +321,20 @@ struct EigWork {
   std::vector<void*> owned;
   double* part = nullptr;
   double* g = nullptr;   // device q*q
-  double* cm = nullptr;  // device QMAX * k
-  double* hg = nullptr;  // pinned host mirror of g
+  double* cm = nullptr;   // device CM_SLOTS x (QMAX * k) coefficient slots
+  double* hcm = nullptr;  // pinned host staging of the same slots
+  double* hg = nullptr;   // pinned host mirror of g
+  int slot = 0;           // next free coefficient slot; all are free after a synchronisation
   double* blk(size_t nk) {
     void* p = dev_alloc(H->o, nk * sizeof(double) + 16);
     owned.push_back(p);
     return (double*)p;
   }
   ~EigWork() {
+    (void)hipStreamSynchronize(H->s);  // combinations may still be in flight on an early return
     for (void* p : owned) dev_free(H->o, p);
     if (hg) (void)hipHostFree(hg);
+    if (hcm) (void)hipHostFree(hcm);
   }
   // host q x q matrix S^T T
   std::vector<double> gram(int nb, Blocks3 S, Blocks3 T) {
@@ -339,16 +344,24 @@ struct EigWork {
     hipLaunchKernelGGL(k_gram_finish, dim3(qq), dim3(ET), 0, s, GRAM_BLOCKS, (const double*)part, g);
     LAMG_HIP(hipMemcpyAsync(hg, g, (size_t)qq * sizeof(double), hipMemcpyDeviceToHost, s));
     LAMG_HIP(hipStreamSynchronize(s));
+    slot = 0;
     return std::vector<double>(hg, hg + qq);
   }
   void combine(int nb, Blocks3 S, const std::vector<double>& C, int row0, double* out) {
     // rows row0 .. row0 + nb k of C (q_total x k) as the coefficient matrix
+    // Each combination takes its own coefficient slot, so none waits for the
+    // previous one; the slots are recycled after a synchronisation.
     hipStream_t s = H->s;
-    LAMG_HIP(hipMemcpyAsync(cm + 0, C.data() + (size_t)row0 * k, (size_t)nb * k * k * sizeof(double),
-                            hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_combine, grid_nk(n), dim3(ET), 0, s, n, k, nb, S, (const double*)cm, out);
-    // the coefficient buffer is reused by the next combine: wait for this one
-    LAMG_HIP(hipStreamSynchronize(s));
+    if (slot == CM_SLOTS) {
+      LAMG_HIP(hipStreamSynchronize(s));
+      slot = 0;
+    }
+    const size_t cnt = (size_t)nb * k * k, o = (size_t)slot * QMAX * k;
+    std::copy(C.begin() + (size_t)row0 * k, C.begin() + (size_t)row0 * k + cnt, hcm + o);
+    LAMG_HIP(hipMemcpyAsync(cm + o, hcm + o, cnt * sizeof(double), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_combine, grid_nk(n), dim3(ET), 0, s, n, k, nb, S, (const double*)(cm + o), out);
+    LAMG_HIP(hipGetLastError());
+    ++slot;
   }
 };
 
@@ -370,7 +383,8 @@ lamg_status eigs(Hierarchy* H, int k, double* X, double* evals, double tol, int 
   E.k = kb;
   E.part = E.blk((size_t)GRAM_BLOCKS * QMAX * QMAX);
   E.g = E.blk((size_t)QMAX * QMAX);
-  E.cm = E.blk((size_t)QMAX * kb);
+  E.cm = E.blk((size_t)CM_SLOTS * QMAX * kb);
+  LAMG_HIP(hipHostMalloc((void**)&E.hcm, (size_t)CM_SLOTS * QMAX * kb * sizeof(double), hipHostMallocDefault));
   LAMG_HIP(hipHostMalloc((void**)&E.hg, (size_t)QMAX * QMAX * sizeof(double), hipHostMallocDefault));
   double *Xb = E.blk(nk), *NX = E.blk(nk), *Wb = E.blk(nk), *NW = E.blk(nk), *Pb = E.blk(nk), *NP = E.blk(nk);
   double *R = E.blk(nk), *Xn = E.blk(nk), *NXn = E.blk(nk), *Pn = E.blk(nk), *NPn = E.blk(nk);
