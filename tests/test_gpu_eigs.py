@@ -118,3 +118,35 @@ def test_invalid_and_unconverged(lg):
     # the Rayleigh-Ritz values of the initial block bound the true ones from above
     lam, _, _ = E.lowest_eigenpairs(E.dense_laplacian(g.n, g.eu, g.ev, g.w), 2)
     assert np.all(ev >= lam * (1 - 1e-12))
+
+
+def test_cycle_double_eigenvalues(lg):
+    """Cycle of 96 nodes: every non-zero eigenvalue 2 - 2 cos(2 pi j / n) is
+    double, so k = 4 covers two whole pairs; each returned vector must lie in
+    its pair's eigenspace (the basis inside a pair is not unique)."""
+    _case("eigs cycle 96 k=4 (double eigenvalues)")
+    n, k = 96, 4
+    eu = np.arange(n)
+    ev = (eu + 1) % n
+    w = np.ones(n)
+    H = lg.Hierarchy(n, eu, ev, w)
+    ev_, X, info = H.eigs(k, W.rhs_normal(n, k, seed=5), tol=TOL, max_iter=300)
+    assert info["status"] == lg.OK, info
+    ref = np.array([2 - 2 * math.cos(2 * math.pi * j / n) for j in (1, 1, 2, 2)])
+    assert np.allclose(ev_, ref, rtol=1e-9)
+    a = E.dense_laplacian(n, eu, ev, w)
+    lam, vec, nxt = E.lowest_eigenpairs(a, k)
+    _check_against(ev_, X, lam, vec, nxt, a)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_fiedler_pair(lg, prec):
+    """k = 1: the Fiedler value and vector (block of two columns)."""
+    _case(f"eigs fiedler er prec={prec}")
+    g = W.erdos_renyi(1500, 6.0, 9)
+    H = lg.Hierarchy(g.n, g.eu, g.ev, g.w, precision=prec)
+    ev, X, info = H.eigs(1, W.rhs_normal(g.n, 1, seed=2).reshape(-1, 1), tol=TOL, max_iter=300)
+    assert info["status"] == lg.OK, info
+    a = E.dense_laplacian(g.n, g.eu, g.ev, g.w)
+    lam, vec, nxt = E.lowest_eigenpairs(a, 1)
+    _check_against(ev, X, lam, vec, nxt, a)
