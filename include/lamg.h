@@ -195,7 +195,13 @@ lamg_status lamg_edge_gradient(int64_t m, const int32_t* eu, const int32_t* ev, 
  *   resid  HOST double[k] out (nullable): ||A x_j - lambda_j x_j|| / lambda_j.
  * 1 <= k <= 8 and 4k <= n, else LAMG_E_INVALID_ARG.  LAMG_E_NOT_CONVERGED
  * still writes the last iterate; LAMG_E_BREAKDOWN when the search space
- * loses rank.  Runs on the hierarchy's stream and returns after it. */
+ * loses rank.  Runs on the hierarchy's stream and returns after it.
+ * Internally the iterated block has kb = k + min(k, 4) columns (at most n/4);
+ * only the first k are tested and returned.  For the call it allocates, through
+ * the hierarchy's allocator: eleven n x kb FP64 blocks, about 19 MB of Gram
+ * partial sums and the multi-vector cycle workspace for kb columns (the last
+ * one is kept by the handle).  It also allocates a few KB of pinned host
+ * memory. */
 lamg_status lamg_eigs(lamg_handle h, int32_t k, double* X, double* evals, double tol, int32_t max_iter,
                       int32_t cycles, int32_t* iters, double* resid);
 
