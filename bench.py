@@ -509,6 +509,27 @@ def eigs_step(H, g, k, lamg, precision):
             "rel_residuals": [float(v) for v in info["resid"]]}
 
 
+def eigs_cpu_sample(k, lamg, n0=1 << 12):
+    """The eigenpair oracle (dense Laplacian, full symmetric eigendecomposition,
+    one BLAS thread) on a bounded sample: a Chung-Lu graph of the workload's
+    recipe at n0 = 2^12, beside the GPU eigensolver on the same graph."""
+    from threadpoolctl import threadpool_limits
+    from oracle import eigs as OE
+    from paper_1108_1310_amd import workloads as W
+    gs = W.chung_lu(n0)
+    t0 = time.perf_counter()
+    with threadpool_limits(limits=1):
+        lam, _, _ = OE.lowest_eigenpairs(OE.dense_laplacian(gs.n, gs.eu, gs.ev, gs.w), k)
+    cpu_ms = (time.perf_counter() - t0) * 1e3
+    Hs = lamg.Hierarchy(gs.n, gs.eu, gs.ev, gs.w)
+    e = eigs_step(Hs, gs, k, lamg, lamg.FP64)
+    Hs.close()
+    rel = max(abs(x - y) / y for x, y in zip(e["eigenvalues"], lam))
+    return {"kind": "oracle", "sample": f"Chung-Lu recipe at n0 = 2^12 (n = {gs.n}), dense eigh, k = {k}",
+            "cores": 1, "ms": cpu_ms, "gpu_ms_same_sample": e["ms"], "gpu_iterations": e["iterations"],
+            "max_rel_eigenvalue_diff": rel}
+
+
 def cycle_work_units(ns, gammas, nu):
     """Relaxation work of one cycle in finest-level sweeps: nu sweeps per body
     of every level above the coarsest, times its visits (the fractional
@@ -643,6 +664,9 @@ def main():
             e["mvm_units"] = 1e3 * e["ms"] / mvm_us
             eig[key] = e
             print(f"[bench] eigs ({key}) {e['ms']:.1f} ms, {e['iterations']} iterations", file=sys.stderr, flush=True)
+        if not a.no_cpu:
+            eig["cpu_baseline"] = eigs_cpu_sample(a.eigs, lamg)
+            print(f"[bench] eigs oracle sample {eig['cpu_baseline']}", file=sys.stderr, flush=True)
     cpu = None
     if not a.no_cpu:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
