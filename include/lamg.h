@@ -168,6 +168,33 @@ lamg_status lamg_solve(lamg_handle h, const double* b, double* x, lamg_info* inf
 lamg_status lamg_solve_batch(int32_t count, const lamg_handle* hs, const int32_t* nrhs,
                              const double* const* B, double* const* X, lamg_info* infos);
 
+/* Allocation-free form of the many-graph persistent solve of lamg_solve_batch
+ * (nrhs[i] == 1 for every entry), for callers that cannot allocate device
+ * memory during the call: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  The launch's own buffers (the graphs'
+ * descriptors, the queue orders and counter, the per-graph results) live in a
+ * static device array of the library, one copy per GPU held until the
+ * process ends, of LAMG_NOALLOC_MAX_GRAPHS graphs at most (about 1.3 MB);
+ * the call allocates no device or pinned host memory and does not autotune
+ * (it launches the configuration lamg_solve_batch tuned for the same batch
+ * shape, else the first one; results do not depend on it).
+ *   count  0 <= count <= LAMG_NOALLOC_MAX_GRAPHS, else LAMG_E_INVALID_ARG
+ *          with the reason in lamg_last_error()
+ *   hs     HOST[count] distinct handles of graphs with at most 2^18 nodes
+ *          (their whole-hierarchy program is made by lamg_setup and by
+ *          lamg_set_solve_options); else LAMG_E_INVALID_ARG
+ *   B, X   HOST[count] arrays of DEVICE double[n_i]: right-hand sides and
+ *          solutions in input node order, as in lamg_solve
+ *   infos  HOST[count], may be NULL.
+ * Solutions, statuses and infos equal those of lamg_solve_batch on the same
+ * handles and right-hand sides.  Every call on one GPU shares that GPU's
+ * scratch (the queue counter is cleared by a kernel before each launch), so
+ * calls that overlap on one GPU, from several threads or streams, race and
+ * must be serialised by the caller. */
+#define LAMG_NOALLOC_MAX_GRAPHS 4096
+lamg_status lamg_solve_batch_noalloc(int32_t count, const lamg_handle* hs, const double* const* B,
+                                     double* const* X, lamg_info* infos);
+
 /* Adjoint edge gradient of a solve x = A^+ b (spec differentiable form):
  * for a loss L with dL/dx = g, the caller solves A lam = g (lamg_solve on the
  * same hierarchy, since A is symmetric) and this kernel forms
@@ -216,7 +243,8 @@ void lamg_free(lamg_handle h);
 const char* lamg_status_str(lamg_status s);
 
 /* Text of the HIP error behind the last LAMG_E_DEVICE / LAMG_E_OUT_OF_MEMORY
- * returned on the calling thread ("" if none); valid until the next call. */
+ * returned on the calling thread (and the reason of a size refused by
+ * lamg_solve_batch_noalloc; "" if none); valid until the next call. */
 const char* lamg_last_error(void);
 
 #ifdef __cplusplus

@@ -191,6 +191,7 @@ thread_local char g_last_error[256] = "";
 void set_last_error(const char* where, hipError_t e) {
   std::snprintf(g_last_error, sizeof(g_last_error), "%s: %s (%d)", where, hipGetErrorString(e), (int)e);
 }
+void set_last_error_msg(const char* msg) { std::snprintf(g_last_error, sizeof(g_last_error), "%s", msg); }
 
 // Algorithmic bytes of one cycle on k right-hand sides: the matrix streams of
 // every pass once, its vector streams k times.
@@ -357,6 +358,7 @@ static lamg_status run_setup(int64_t n, int64_t m, const lamg_options* o, lamg_h
     H->colb = dnew<double>(H, n);
     H->colx = dnew<double>(H, n);
     H->bytes_per_cycle = cycle_bytes(H, LAMG_FP64);
+    if (H->lv[0].n <= BATCH_MAX_N) batch_prepare(H);  // the persistent many-graph program
     LAMG_HIP(hipStreamSynchronize(H->s));
   } catch (const DevError& e) {
     set_last_error("lamg_setup", e.e);
@@ -417,12 +419,14 @@ lamg_status lamg_set_solve_options(lamg_handle h, const lamg_options* o) {
     return LAMG_E_INVALID_ARG;
   Hierarchy* H = &h->H;
   // the captured cycles and the tail program depend on these options
-  if (o->ec != H->o.ec || o->mu != H->o.mu || o->nu_pre != H->o.nu_pre || o->nu_post != H->o.nu_post) {
+  if (o->nu_pre < 0 || o->nu_post < 0) return LAMG_E_INVALID_ARG;
+  const bool reprogram =
+      o->ec != H->o.ec || o->mu != H->o.mu || o->nu_pre != H->o.nu_pre || o->nu_post != H->o.nu_post;
+  if (reprogram) {
     drop_graphs(H);
     mv_drop_graphs(H);
     invalidate_programs(H);
   }
-  if (o->nu_pre < 0 || o->nu_post < 0) return LAMG_E_INVALID_ARG;
   H->o.precision = o->precision;
   H->o.ec = o->ec;
   H->o.mu = o->mu;
@@ -433,6 +437,14 @@ lamg_status lamg_set_solve_options(lamg_handle h, const lamg_options* o) {
   H->o.nu_pre = o->nu_pre;
   H->o.nu_post = o->nu_post;
   H->s = (hipStream_t)o->stream;
+  if (reprogram && H->lv[0].n <= BATCH_MAX_N) {
+    try {
+      batch_prepare(H);  // ready for the allocation-free batch entry
+    } catch (const DevError& e) {
+      set_last_error("lamg_set_solve_options", e.e);
+      return e.e == hipErrorOutOfMemory ? LAMG_E_OUT_OF_MEMORY : LAMG_E_DEVICE;
+    }
+  }
   return LAMG_OK;
 }
 
@@ -510,10 +522,6 @@ lamg_status lamg_solve(lamg_handle h, const double* b, double* x, lamg_info* inf
   }
 }
 
-// Graphs up to this size join the persistent launch of a many-graph batch;
-// larger ones are solved one after another with the multi-launch cycle.
-constexpr int BATCH_MAX_N = 1 << 18;
-
 lamg_status lamg_solve_batch(int32_t count, const lamg_handle* hs, const int32_t* nrhs, const double* const* B,
                              double* const* X, lamg_info* infos) {
   if (count < 0 || (count > 0 && (!hs || !nrhs || !B || !X))) return LAMG_E_INVALID_ARG;
@@ -556,6 +564,39 @@ lamg_status lamg_solve_batch(int32_t count, const lamg_handle* hs, const int32_t
     return e.e == hipErrorOutOfMemory ? LAMG_E_OUT_OF_MEMORY : LAMG_E_DEVICE;
   }
   return worst;
+}
+
+lamg_status lamg_solve_batch_noalloc(int32_t count, const lamg_handle* hs, const double* const* B,
+                                     double* const* X, lamg_info* infos) {
+  char msg[200];
+  if (count < 0 || (count > 0 && (!hs || !B || !X))) return LAMG_E_INVALID_ARG;
+  if (count > LAMG_NOALLOC_MAX_GRAPHS) {
+    std::snprintf(msg, sizeof(msg), "lamg_solve_batch_noalloc: %d graphs exceed the static scratch of %d graphs",
+                  (int)count, (int)LAMG_NOALLOC_MAX_GRAPHS);
+    set_last_error_msg(msg);
+    return LAMG_E_INVALID_ARG;
+  }
+  if (count == 0) return LAMG_OK;
+  std::vector<Hierarchy*> H(count);
+  for (int i = 0; i < count; ++i) {
+    if (!hs[i] || !B[i] || !X[i]) return LAMG_E_INVALID_ARG;
+    H[i] = &hs[i]->H;
+    if (H[i]->lv[0].n > BATCH_MAX_N) {
+      std::snprintf(msg, sizeof(msg), "lamg_solve_batch_noalloc: graph %d has %d nodes (at most %d)", i,
+                    H[i]->lv[0].n, BATCH_MAX_N);
+      set_last_error_msg(msg);
+      return LAMG_E_INVALID_ARG;
+    }
+  }
+  std::vector<Hierarchy*> sorted(H);
+  std::sort(sorted.begin(), sorted.end());
+  if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end()) return LAMG_E_INVALID_ARG;
+  try {
+    return solve_graphs(count, H.data(), B, X, infos, true);
+  } catch (const DevError& e) {
+    set_last_error("lamg_solve_batch_noalloc", e.e);
+    return e.e == hipErrorOutOfMemory ? LAMG_E_OUT_OF_MEMORY : LAMG_E_DEVICE;
+  }
 }
 
 namespace {

@@ -238,6 +238,7 @@ bool prof_on();
 void prof_flush();
 // Message of the last device error on this thread (lamg_last_error).
 void set_last_error(const char* where, hipError_t e);
+void set_last_error_msg(const char* msg);
 
 // ------------------------------------------------------------- allocation
 // Device memory through the options' allocator (hipMalloc / hipFree when
@@ -326,9 +327,19 @@ template <class T>
 void tail_run_next(Hierarchy* H);
 // Drop the op programs (they depend on nu, ec and mu).
 void invalidate_programs(Hierarchy* H);
+// Graphs up to this size join the persistent launch of a many-graph batch;
+// larger ones are solved one after another with the multi-launch cycle.
+constexpr int BATCH_MAX_N = 1 << 18;
 // Persistent many-graph solve: every graph's whole solve in one workgroup.
+// noalloc: the launch's buffers come from the library's static device
+// scratch (at most LAMG_NOALLOC_MAX_GRAPHS graphs, every hierarchy already
+// prepared, no tuning) instead of the first handle's allocator.
 lamg_status solve_graphs(int count, Hierarchy* const* hs, const double* const* B, double* const* X,
-                         lamg_info* infos);
+                         lamg_info* infos, bool noalloc = false);
+// The whole-hierarchy descriptors and op program of the persistent solve
+// (idempotent; made at setup for graphs of at most BATCH_MAX_N nodes and again
+// after a change of the options the program depends on).
+void batch_prepare(Hierarchy* H);
 // Multi-vector tail: one workgroup per column of the workspace blocks.
 void tail_prepare_mv(Hierarchy* H);
 template <class T>

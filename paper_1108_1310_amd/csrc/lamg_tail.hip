@@ -12,6 +12,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "lamg_device.hpp"
@@ -1008,7 +1009,12 @@ template void tail_run_next_mv<float>(Hierarchy*);
 
 void invalidate_programs(Hierarchy* H) {
   H->tail_lc = -1;
-  H->full_levels = nullptr;
+  // the whole-hierarchy descriptors do not depend on the options; its
+  // program does (released here: solves are synchronous, none is in flight)
+  if (H->full_prog) {
+    dev_free(H->o, H->full_prog);
+    H->owned.erase(std::find(H->owned.begin(), H->owned.end(), (void*)H->full_prog));
+  }
   H->full_prog = nullptr;
   H->full_nops = 0;
 }
@@ -1147,19 +1153,56 @@ struct TunerEntry {
 std::vector<TunerEntry> g_tuned;  // best configuration per batch signature (process lifetime)
 int g_batch_forced = -1;          // test hook: force a configuration
 
+}  // namespace
+
 void batch_prepare(Hierarchy* H) {
   if (H->full_prog) return;
-  std::vector<TailLevel> d = build_desc(H, 0);
-  TailLevel* dd = dnew<TailLevel>(H, d.size());
-  LAMG_HIP(hipMemcpy(dd, d.data(), d.size() * sizeof(TailLevel), hipMemcpyHostToDevice));
+  if (!H->full_levels) {
+    std::vector<TailLevel> d = build_desc(H, 0);
+    TailLevel* dd = dnew<TailLevel>(H, d.size());
+    LAMG_HIP(hipMemcpy(dd, d.data(), d.size() * sizeof(TailLevel), hipMemcpyHostToDevice));
+    H->full_levels = dd;
+  }
   std::vector<int4> prog;
   std::vector<int2> segs;
   build_prog(H, 0, prog, segs);
   int4* dp = dnew<int4>(H, std::max<size_t>(prog.size(), 1));
   LAMG_HIP(hipMemcpy(dp, prog.data(), prog.size() * sizeof(int4), hipMemcpyHostToDevice));
-  H->full_levels = dd;
   H->full_nops = (int)prog.size();
   H->full_prog = dp;
+}
+
+namespace {
+// Device block of one persistent launch: the graphs' descriptors (one copy
+// per LDS budget), the two queue orders, the queue counter and the results.
+constexpr size_t batch_buffer_bytes(size_t count) {
+  return 2 * count * sizeof(BatchGraph) + 2 * count * sizeof(int) + 256 + count * sizeof(BatchOut);
+}
+
+// Scratch of the allocation-free entry (lamg_solve_batch_noalloc): the block
+// above for up to LAMG_NOALLOC_MAX_GRAPHS graphs, one copy per device for the
+// life of the process.  Host code never passes this symbol to a kernel: its
+// device address comes from hipGetSymbolAddress, once per device.
+constexpr size_t kNoallocBytes = batch_buffer_bytes(LAMG_NOALLOC_MAX_GRAPHS);
+static __device__ __align__(256) char scratch[kNoallocBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's address of `scratch` (looked up on the first call on
+// that device, with the device current).
+char* noalloc_scratch() {
+  int dev = 0;
+  LAMG_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) throw DevError{hipErrorInvalidDevice};
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    LAMG_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) throw DevError{hipErrorInvalidSymbol};
+    g_scratch_ptr[dev] = (char*)p;
+  }
+  return g_scratch_ptr[dev];
 }
 
 }  // namespace
@@ -1171,7 +1214,7 @@ extern "C" lamg_status lamg_t_batch_config(int32_t config) {
 }
 
 lamg_status solve_graphs(int count, Hierarchy* const* hs, const double* const* B, double* const* X,
-                         lamg_info* infos) {
+                         lamg_info* infos, bool noalloc) {
   auto t0 = std::chrono::steady_clock::now();
   hipStream_t s = hs[0]->s;
   std::vector<BatchGraph> G(count);
@@ -1180,6 +1223,7 @@ lamg_status solve_graphs(int count, Hierarchy* const* hs, const double* const* B
   bool warm = false;
   for (int i = 0; i < count; ++i) {
     Hierarchy* H = hs[i];
+    if (noalloc && (!H->full_prog || !H->full_levels)) return LAMG_E_INVALID_ARG;  // (prepared at setup)
     batch_prepare(H);
     BatchGraph& g = G[i];
     std::memset(&g, 0, sizeof(g));
@@ -1222,16 +1266,20 @@ lamg_status solve_graphs(int count, Hierarchy* const* hs, const double* const* B
     LAMG_HIP(hipFuncSetAttribute((const void*)k_batch, hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024));
     attr = true;
   }
-  // device copies: graphs (one copy per LDS budget), orders, queue, results
+  // device copies: graphs (one copy per LDS budget), orders, queue, results;
+  // in the call's own block (through the first handle's allocator) or in
+  // the static scratch of the allocation-free entry
   const size_t gb = (size_t)count * sizeof(BatchGraph);
-  const size_t bytes = 2 * gb + 2 * (size_t)count * sizeof(int) + 256 + (size_t)count * sizeof(BatchOut);
-  const lamg_options& ao = hs[0]->o;  // the call's buffers through the first handle's allocator
-  char* buf = (char*)dev_alloc(ao, bytes);
+  const size_t bytes = batch_buffer_bytes((size_t)count);
+  const lamg_options& ao = hs[0]->o;
+  char* buf = noalloc ? noalloc_scratch() : (char*)dev_alloc(ao, bytes);
   struct Free {
     const lamg_options& o;
     char* p;
-    ~Free() { dev_free(o, p); }
-  } guard{ao, buf};
+    ~Free() {
+      if (p) dev_free(o, p);
+    }
+  } guard{ao, noalloc ? nullptr : buf};
   BatchGraph* dG[2] = {(BatchGraph*)buf, (BatchGraph*)(buf + gb)};
   int* dorder[2] = {(int*)(buf + 2 * gb), (int*)(buf + 2 * gb) + count};
   int* queue = (int*)(buf + 2 * gb + 2 * (size_t)count * sizeof(int));
@@ -1262,7 +1310,7 @@ lamg_status solve_graphs(int count, Hierarchy* const* hs, const double* const* B
     bool found = false;
     for (const TunerEntry& e : g_tuned)
       if (e.key == key) { best = e.best; found = true; }
-    if (!found && !warm) {
+    if (!found && !warm && !noalloc) {
       // time every configuration once on this batch (each run is a full,
       // identical solve) and keep the fastest for this batch signature
       hipEvent_t a, b;

@@ -74,6 +74,8 @@ def lib():
             "lamg_solve": (C.c_int, [vp, vp, vp, C.POINTER(Info)]),
             "lamg_solve_batch": (C.c_int, [i32, C.POINTER(vp), C.POINTER(i32), C.POINTER(vp), C.POINTER(vp),
                                            C.POINTER(Info)]),
+            "lamg_solve_batch_noalloc": (C.c_int, [i32, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp),
+                                                   C.POINTER(Info)]),
             "lamg_set_solve_options": (C.c_int, [vp, C.POINTER(Options)]),
             "lamg_edge_gradient": (C.c_int, [i64, vp, vp, vp, vp, vp, vp]),
             "lamg_eigs": (C.c_int, [vp, i32, vp, vp, d, i32, i32, C.POINTER(i32), vp]),
@@ -440,6 +442,32 @@ def solve_batch(hs: list[Hierarchy], Bs: list, Xs: list | None = None):
     rc = lib().lamg_solve_batch(cnt, hp, nrhs, bp, xp, infos)
     if rc not in (OK, E_NOT_CONVERGED):
         _check(rc, "lamg_solve_batch")
+    return Xd, [i.as_dict() for i in infos], rc
+
+
+NOALLOC_MAX_GRAPHS = 4096  # LAMG_NOALLOC_MAX_GRAPHS
+
+
+def solve_batch_noalloc(hs: list[Hierarchy], Bs: list, Xs: list | None = None):
+    """Many graphs, one right-hand side each, through the allocation-free
+    entry (lamg_solve_batch_noalloc): the same persistent launch as
+    solve_batch, its buffers in the library's static device scratch.  The
+    outputs are allocated here, before the call."""
+    cnt = len(hs)
+    Bd = [_dev(b, torch.float64) for b in Bs]
+    warm = Xs is not None
+    Xd = [_dev(x, torch.float64).clone() for x in Xs] if warm else [torch.empty_like(b) for b in Bd]
+    for h in hs:
+        if bool(h.opts.warm_start) != warm:
+            h.set_solve_options(warm_start=int(warm))
+    hp = (C.c_void_p * cnt)(*[h.h.value for h in hs])
+    bp = (C.c_void_p * cnt)(*[b.data_ptr() for b in Bd])
+    xp = (C.c_void_p * cnt)(*[x.data_ptr() for x in Xd])
+    infos = (Info * cnt)()
+    rc = lib().lamg_solve_batch_noalloc(cnt, hp, bp, xp, infos)
+    if rc not in (OK, E_NOT_CONVERGED):
+        msg = lib().lamg_last_error().decode()
+        raise LamgError(rc, f"lamg_solve_batch_noalloc {msg}".rstrip())
     return Xd, [i.as_dict() for i in infos], rc
 
 
