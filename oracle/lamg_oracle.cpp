@@ -62,9 +62,13 @@ inline double unit_pm1(uint64_t h) { return (double)(h >> 11) * (1.0 / 450359962
 // chunk's terms j, j+64, ..., j+448 left to right, the 64 partials are folded
 // by an xor butterfly (offsets 32..1), and the chunk sums are added left to
 // right.
+// Switch (ora_set_plain_rows) to sum every row left to right instead: the
+// paper fixes no order, so a decision that changed with it would hinge on
+// rounding alone (tested on the CPU).
+bool g_plain_rows = false;
 template <class T, class F>
 T row_reduce(i64 len, F term) {
-  if (len <= 64) {
+  if (len <= 64 || g_plain_rows) {
     T s = 0;
     for (i64 t = 0; t < len; ++t) s += term(t);
     return s;
@@ -119,6 +123,10 @@ struct Opts {  // mirrors the library options, defaults from Section 4
   int coarsest_sweeps = 3;       // relaxation sweeps of a coarsest level that relaxation solves
   int dense_max = 8192;          // largest coarsest level factored densely
   int allow_negative = 0;        // Section 5.2: accept negative weights (|w| in the aggregation tests)
+  int recomb_finest = 1;         // 1: iterate recombination also at the finest level (read from Section
+                                 // 3.4.5 as every level followed by an aggregation level); 0: only at
+                                 // levels entered from a finer one ("when the cycle switches from
+                                 // level l-1 to level l")
 };
 
 struct AggDiag {  // aggregation-level setup quantities, kept for parity tests
@@ -829,16 +837,17 @@ double dot(const vector<T>& a, const vector<T>& b) {
   return s;
 }
 
-// Residual-minimising combination y = x + sum_i alpha_i (x_i - x) (eq. recomb).
+// Residual-minimising combination y = x + sum_i alpha_i (x_i - x) (eq. recomb):
+// x is the final iterate with residual r, X[i] the saved iterates with
+// residuals R[i]; the residual of y is r + sum_i alpha_i (R[i] - r), so alpha
+// solves the th x th normal equations of that least-squares problem (FP64).
+// Writes y over x and alpha[0..th-1].
 template <class T>
-void recombine(const Hier& H, Work<T>& W, int l, int th) {
-  const Level& L = H.lv[l];
-  i64 n = L.A.n;
-  vector<T>& x = W.x[l];
-  vector<T>& r = W.r[l];
-  residual<T>(L.A, VAL<T>(L), DIAG<T>(L), W.b[l].data(), x.data(), r.data());
+void recombine_core(vector<T>& x, const vector<T>& r, const vector<vector<T>>& X, const vector<vector<T>>& R, int th,
+                    double* alpha_out) {
+  const i64 n = (i64)x.size();
   vector<vector<T>> d(th, vector<T>(n));
-  for (int i = 0; i < th; ++i) for (i64 u = 0; u < n; ++u) d[i][u] = W.R[l][i][u] - r[u];
+  for (int i = 0; i < th; ++i) for (i64 u = 0; u < n; ++u) d[i][u] = R[i][u] - r[u];
   double G[2][2] = {{0, 0}, {0, 0}}, g[2] = {0, 0}, rr = dot(r, r);
   for (int i = 0; i < th; ++i) {
     g[i] = dot(d[i], r);
@@ -860,9 +869,19 @@ void recombine(const Hier& H, Work<T>& W, int l, int th) {
   }
   for (i64 u = 0; u < n; ++u) {
     double y = (double)x[u];
-    for (int i = 0; i < th; ++i) y += alpha[i] * ((double)W.X[l][i][u] - (double)x[u]);
+    for (int i = 0; i < th; ++i) y += alpha[i] * ((double)X[i][u] - (double)x[u]);
     x[u] = (T)y;
   }
+  if (alpha_out) for (int i = 0; i < th; ++i) alpha_out[i] = alpha[i];
+}
+
+// Recombination at the end of a visit of level l: the final residual, then
+// the combination with the iterates saved after each sub-cycle's pre-relaxation.
+template <class T>
+void recombine(const Hier& H, Work<T>& W, int l, int th) {
+  const Level& L = H.lv[l];
+  residual<T>(L.A, VAL<T>(L), DIAG<T>(L), W.b[l].data(), W.x[l].data(), W.r[l].data());
+  recombine_core<T>(W.x[l], W.r[l], W.X[l], W.R[l], th, nullptr);
 }
 
 template <class T>
@@ -935,7 +954,7 @@ void visit(const Hier& H, Work<T>& W, int l, int th) {
   const int Lc = (int)H.lv.size() - 1;
   if (l == Lc) { body<T>(H, W, l, 0); return; }  // repeated exact solves are identical
   for (int i = 0; i < th; ++i) body<T>(H, W, l, i);
-  if (H.o.ec == 0 && H.lv[l + 1].type == L_AGG) recombine<T>(H, W, l, th);
+  if (H.o.ec == 0 && H.lv[l + 1].type == L_AGG && (l > 0 || H.o.recomb_finest)) recombine<T>(H, W, l, th);
 }
 
 template <class T>
@@ -1061,6 +1080,7 @@ typedef struct ora_opts {
   double stage1_quantile, relax_fast_ratio;
   int coarsest_sweeps, dense_max;
   int allow_negative;
+  int recomb_finest;
 } ora_opts;
 
 void ora_opts_default(ora_opts* o) {
@@ -1076,7 +1096,33 @@ void ora_opts_default(ora_opts* o) {
   o->coarsest_sweeps = d.coarsest_sweeps;
   o->dense_max = d.dense_max;
   o->allow_negative = d.allow_negative;
+  o->recomb_finest = d.recomb_finest;
 }
+
+// --- one iterate recombination (eq. recomb) on a raw CSR: x (final iterate)
+// and th <= 2 saved iterates Xs (n x th row-major, column i = iterate i);
+// residuals are formed here.  Writes y into y_out and alpha[0..th-1].
+void ora_recombine(i64 n, const i64* ptr, const i32* col, const double* val, const double* diag, const double* b,
+                   const double* x, const double* Xs, int th, double* y_out, double* alpha) {
+  Csr A;
+  A.n = n;
+  A.ptr.assign(ptr, ptr + n + 1);
+  A.col.assign(col, col + ptr[n]);
+  A.val.assign(val, val + ptr[n]);
+  A.diag.assign(diag, diag + n);
+  vector<double> xv(x, x + n), r(n);
+  residual<double>(A, A.val.data(), A.diag.data(), b, xv.data(), r.data());
+  vector<vector<double>> X(th, vector<double>(n)), R(th, vector<double>(n));
+  for (int i = 0; i < th; ++i) {
+    for (i64 u = 0; u < n; ++u) X[i][u] = Xs[u * th + i];
+    residual<double>(A, A.val.data(), A.diag.data(), b, X[i].data(), R[i].data());
+  }
+  recombine_core<double>(xv, r, X, R, th, alpha);
+  std::copy(xv.begin(), xv.end(), y_out);
+}
+
+// Row sums left to right (1) or in the fixed chunked order (0, default).
+void ora_set_plain_rows(int plain) { g_plain_rows = plain != 0; }
 
 static Opts to_opts(const ora_opts* o) {
   Opts d;
@@ -1092,6 +1138,7 @@ static Opts to_opts(const ora_opts* o) {
   d.coarsest_sweeps = o->coarsest_sweeps;
   d.dense_max = o->dense_max;
   d.allow_negative = o->allow_negative;
+  d.recomb_finest = o->recomb_finest;
   return d;
 }
 

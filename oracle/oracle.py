@@ -36,7 +36,8 @@ class Opts(C.Structure):
                 ("weak_edge_ratio", C.c_double), ("elim_stop_frac", C.c_double),
                 ("ec", C.c_int), ("tol", C.c_double), ("max_cycles", C.c_int),
                 ("seed", C.c_uint64), ("stage1_quantile", C.c_double), ("relax_fast_ratio", C.c_double),
-                ("coarsest_sweeps", C.c_int), ("dense_max", C.c_int), ("allow_negative", C.c_int)]
+                ("coarsest_sweeps", C.c_int), ("dense_max", C.c_int), ("allow_negative", C.c_int),
+                ("recomb_finest", C.c_int)]
 
 
 _lib = None
@@ -53,6 +54,8 @@ def lib():
                                             C.POINTER(C.c_float), C.POINTER(C.c_uint8))
         sig = {
             "ora_opts_default": (None, [C.POINTER(Opts)]),
+            "ora_set_plain_rows": (None, [C.c_int]),
+            "ora_recombine": (None, [i64, i64p, i32p, dp, dp, dp, dp, dp, C.c_int, dp, dp]),
             "ora_laplacian": (vp, [i64, i64, i32p, i32p, dp, C.POINTER(C.c_int)]),
             "ora_csr_nnz": (i64, [vp]), "ora_csr_n": (i64, [vp]),
             "ora_csr_export": (None, [vp, i64p, i32p, dp, dp]),
@@ -188,6 +191,25 @@ def hash5(seed, stream, a, b, c) -> int:
 
 def unit_pm1(h) -> float:
     return float(lib().ora_unit_pm1(h))
+
+
+def recombine(A: Csr, b, x, Xs):
+    """Iterate recombination (eq. recomb) of the final iterate x with the
+    saved iterates Xs ([n, th], th <= 2).  Returns (y, alpha)."""
+    Xs = np.ascontiguousarray(np.asarray(Xs, np.float64).reshape(A.n, -1))
+    th = Xs.shape[1]
+    y = np.zeros(A.n)
+    alpha = np.zeros(th)
+    lib().ora_recombine(A.n, _p(_i64(A.ptr), C.c_int64), _p(_i32(A.col), C.c_int32), _p(_f64(A.val), C.c_double),
+                        _p(_f64(A.diag), C.c_double), _p(_f64(b), C.c_double), _p(_f64(x), C.c_double),
+                        _p(Xs, C.c_double), th, _p(y, C.c_double), _p(alpha, C.c_double))
+    return y, alpha
+
+
+def set_plain_rows(plain: bool):
+    """Sum every row left to right (True) or in the fixed chunked order
+    (False, the default that the GPU path shares)."""
+    lib().ora_set_plain_rows(1 if plain else 0)
 
 
 def row_reduce(terms) -> float:
