@@ -186,10 +186,14 @@ void drop_graphs(Hierarchy* H) {
 }
 
 namespace {
-thread_local char g_last_error[256] = "";
+thread_local char g_last_error[512] = "";
+thread_local char g_error_detail[256] = "";
 }
+void set_error_detail(const char* msg) { std::snprintf(g_error_detail, sizeof(g_error_detail), "%s", msg); }
 void set_last_error(const char* where, hipError_t e) {
-  std::snprintf(g_last_error, sizeof(g_last_error), "%s: %s (%d)", where, hipGetErrorString(e), (int)e);
+  std::snprintf(g_last_error, sizeof(g_last_error), "%s: %s (%d)%s%s", where, hipGetErrorString(e), (int)e,
+                g_error_detail[0] ? ": " : "", g_error_detail);
+  g_error_detail[0] = 0;
 }
 void set_last_error_msg(const char* msg) { std::snprintf(g_last_error, sizeof(g_last_error), "%s", msg); }
 

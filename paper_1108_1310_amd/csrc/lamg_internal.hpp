@@ -195,6 +195,7 @@ struct Hierarchy {
   double* r64 = nullptr;   // level-1 outer residual
   double *colb = nullptr, *colx = nullptr;  // column staging of multi-RHS solves
   std::vector<void*> owned;  // every device allocation, freed with the handle
+  std::vector<size_t> owned_bytes;  // their sizes (same order)
   // captured cycles: [precision][2 alternating instances]
   hipStream_t cs = nullptr;  // capture stream
   hipGraphExec_t gexec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
@@ -217,6 +218,9 @@ struct Hierarchy {
   void* full_levels = nullptr;
   int4* full_prog = nullptr;
   int full_nops = 0;
+  std::vector<TailLevel> full_host;  // host copies of the descriptors and program
+  std::vector<int4> full_prog_host;
+  bool full_checked = false;         // validated against the allocations (program_check)
 };
 
 // -------------------------------------------------------- instrumentation
@@ -239,6 +243,8 @@ void prof_flush();
 // Message of the last device error on this thread (lamg_last_error).
 void set_last_error(const char* where, hipError_t e);
 void set_last_error_msg(const char* msg);
+// Detail appended to the next set_last_error on this thread (and cleared).
+void set_error_detail(const char* msg);
 
 // ------------------------------------------------------------- allocation
 // Device memory through the options' allocator (hipMalloc / hipFree when

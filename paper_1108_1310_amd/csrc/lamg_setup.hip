@@ -41,6 +41,7 @@ AllocScope::~AllocScope() { t_scope_alloc = prev; }
 void* dalloc(Hierarchy* H, size_t bytes) {
   void* p = dev_alloc(H->o, bytes);
   H->owned.push_back(p);
+  H->owned_bytes.push_back(std::max<size_t>(bytes, 16));
   return p;
 }
 

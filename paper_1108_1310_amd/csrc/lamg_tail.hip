@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstring>
 #include <mutex>
+#include <string>
 #include <vector>
 
 #include "lamg_device.hpp"
@@ -22,8 +23,12 @@ namespace lamg {
 
 namespace {
 
+// One workgroup size for every kernel of this file (k_tail, k_batch): the
+// wavefront-sum scratch sh[..][TAIL_WAVES] and every stride assume it, so a
+// launch of any other size would write past that scratch.
 constexpr int TAIL_THREADS = 1024;
 constexpr int TAIL_WAVES = TAIL_THREADS / 64;
+static_assert(TAIL_WAVES * 64 == TAIL_THREADS, "whole wavefronts");
 
 enum TailOp {
   OP_GS = 1,      // a = multicolour sweeps of level l (one staging for all)
@@ -165,7 +170,7 @@ __device__ __attribute__((always_inline)) inline void tail_gs(const TailLevel& L
 constexpr int TAIL_LDS = 152 * 1024;  // dynamic LDS of a tail workgroup (of 160 KB per CU)
 constexpr int TAIL_RES = 96 * 1024;   // of which at most this much holds resident levels
 template <class T>
-__device__ inline size_t tail_vec_bytes(const TailLevel& L) {
+__host__ __device__ inline size_t tail_vec_bytes(const TailLevel& L) {
   return (size_t)L.n * (3 * sizeof(T) + sizeof(int)) + 2 * sizeof(int) + (size_t)(2 * L.ncol + 2) * sizeof(int);
 }
 template <class T>
@@ -649,10 +654,10 @@ __device__ __attribute__((always_inline)) inline void run_ops(const TailParams& 
 // level are produced inside the program, so only the entry level's x and b are
 // loaded, and its x written back at the end.  Every thread computes the same
 // plan; one thread rewrites a descriptor after all threads have read it.
-__device__ inline size_t al16(size_t b) { return (b + 15) & ~(size_t)15; }
+__host__ __device__ inline size_t al16(size_t b) { return (b + 15) & ~(size_t)15; }
 
 template <class T>
-__device__ inline size_t res_footprint(const TailLevel& L) {
+__host__ __device__ inline size_t res_footprint(const TailLevel& L) {
   const size_t n = L.n, nz = L.nnz, nc = L.nc;
   size_t s = al16((n + 1) * 4) + al16(nz * 4) + al16(nz * sizeof(T)) + al16(n * sizeof(T)) +
              2 * al16((L.ncol + 1) * 4) + al16((size_t)(L.nlong > 0 ? L.nlong : 1) * 4);
@@ -698,6 +703,32 @@ template <> struct TSet<float> {
   }
 };
 
+// The residency plan: the first level of the largest suffix of levels that
+// joins LDS.  A level joins only while the LDS left over still stages the
+// vectors of every level above the resident ones that relaxes (a level
+// followed by an elimination level has no sweeps).  *bytes: their footprint.
+template <class T>
+__host__ __device__ inline int resident_from(const TailLevel* dl, int nlev, int lds_bytes, int res_bytes,
+                                             size_t* bytes) {
+  const size_t desc = al16((size_t)nlev * sizeof(TailLevel));
+  int rfrom = nlev;
+  size_t tot = 0;
+  if (desc < (size_t)lds_bytes) {
+    const size_t free0 = (size_t)lds_bytes - desc;
+    for (int i = nlev - 1; i >= 0; --i) {
+      const size_t b = res_footprint<T>(dl[i]);
+      size_t stage = 0;
+      for (int a = 0; a < i; ++a)
+        if (!dl[a].cidx) stage = stage > tail_vec_bytes<T>(dl[a]) + 64 ? stage : tail_vec_bytes<T>(dl[a]) + 64;
+      if (tot + b > (size_t)res_bytes || tot + b + stage > free0) break;
+      tot += b;
+      rfrom = i;
+    }
+  }
+  if (bytes) *bytes = tot;
+  return rfrom;
+}
+
 template <class T, bool MV>
 __device__ __attribute__((always_inline)) inline void run_resident(const TailParams& P, const int4* prog, int nops,
                                                                    char* lds, double (*sh)[TAIL_WAVES]) {
@@ -705,31 +736,12 @@ __device__ __attribute__((always_inline)) inline void run_resident(const TailPar
   const ColOf<MV> C{MV ? (int)blockIdx.x : 0, MV ? P.kc : 1};
   const int nlev = P.nlev;
   TailLevel* dl = (TailLevel*)lds;
-  {
-    const unsigned long long* src = (const unsigned long long*)P.L;
-    unsigned long long* dst = (unsigned long long*)dl;
-    const int words = nlev * (int)(sizeof(TailLevel) / 8);
-    for (int w = tid; w < words; w += TAIL_THREADS) dst[w] = src[w];
-  }
+  // one thread per descriptor, copied as the struct it is (no reinterpreting
+  // of its words through another type)
+  for (int i = tid; i < nlev; i += TAIL_THREADS) dl[i] = P.L[i];
   __syncthreads();
   char* cur = lds + al16((size_t)nlev * sizeof(TailLevel));
-  int rfrom = nlev;
-  {
-    // a level joins only while the LDS left over still stages the vectors
-    // of every level above the resident ones that relaxes (a level followed
-    // by an elimination level has no sweeps)
-    const size_t free0 = (size_t)P.lds_bytes - al16((size_t)nlev * sizeof(TailLevel));
-    size_t tot = 0;
-    for (int i = nlev - 1; i >= 0; --i) {
-      const size_t b = res_footprint<T>(dl[i]);
-      size_t stage = 0;
-      for (int a = 0; a < i; ++a)
-        if (!dl[a].cidx) stage = max(stage, tail_vec_bytes<T>(dl[a]) + 64);
-      if (tot + b > (size_t)P.res_bytes || tot + b + stage > free0) break;
-      tot += b;
-      rfrom = i;
-    }
-  }
+  const int rfrom = resident_from<T>(dl, nlev, P.lds_bytes, P.res_bytes, nullptr);
   T* x0 = nullptr;  // the entry level's x in global memory (written back at the end)
   for (int i = rfrom; i < nlev; ++i) {
     const TailLevel o = dl[i];
@@ -918,6 +930,107 @@ void build_prog(const Hierarchy* H, int lc, std::vector<int4>& prog, std::vector
   prog.swap(g.prog);
 }
 
+// Host-side check, before a program's first launch, of everything its ops
+// will touch: every descriptor pointer lies inside a live allocation of the
+// hierarchy with room for the extent the ops read or write (n, nnz, colour
+// and long-row lists, transfers, both precisions' matrices and work vectors),
+// every op's code, level and argument is in range and its level has the
+// transfer the op uses, and the LDS residency plan of both precisions fits
+// each LDS budget the program may run with.  Returns "" or the first problem.
+std::string program_check(const Hierarchy* H, const std::vector<TailLevel>& d, const std::vector<int4>& prog, int lc,
+                          const std::vector<int2>& budgets) {
+  char buf[200];
+  std::vector<std::pair<uintptr_t, size_t>> al(H->owned.size());
+  for (size_t i = 0; i < al.size(); ++i) al[i] = {(uintptr_t)H->owned[i], H->owned_bytes[i]};
+  std::sort(al.begin(), al.end());
+  auto inside = [&](const void* p, size_t bytes) {
+    const uintptr_t a = (uintptr_t)p;
+    auto it = std::upper_bound(al.begin(), al.end(), std::make_pair(a, ~(size_t)0));
+    if (it == al.begin()) return false;
+    --it;
+    return a >= it->first && a + bytes <= it->first + it->second;
+  };
+  const int nlev = (int)d.size();
+  for (int i = 0; i < nlev; ++i) {
+    const TailLevel& t = d[i];
+    const size_t n = t.n, nz = t.nnz, nc = t.nc, ne = t.nner;
+    if (t.n < 1 || t.nnz < 0 || t.ncol < 1 || t.vres != 0) {
+      std::snprintf(buf, sizeof(buf), "level %d: bad sizes", lc + i);
+      return buf;
+    }
+    struct Ext { const void* p; size_t bytes; const char* what; bool need; };
+    const Ext ex[] = {
+        {t.rp, (n + 1) * 4, "rp", true}, {t.ci, nz * 4, "ci", nz > 0}, {t.val64, nz * 8, "val64", nz > 0},
+        {t.val32, nz * 4, "val32", nz > 0}, {t.diag64, n * 8, "diag64", true}, {t.diag32, n * 4, "diag32", true},
+        {t.cptr, ((size_t)t.ncol + 1) * 4, "cptr", true}, {t.lptr, ((size_t)t.ncol + 1) * 4, "lptr", true},
+        {t.lrows, (size_t)(t.nlong > 0 ? t.nlong : 1) * 4, "lrows", true},
+        {t.agg, n * 4, "agg", t.agg != nullptr}, {t.agg_ptr, (nc + 1) * 4, "agg_ptr", t.agg != nullptr},
+        {t.members, n * 4, "members", t.agg != nullptr}, {t.cidx, n * 4, "cidx", t.cidx != nullptr},
+        {t.cfine, nc * 4, "cfine", t.cidx != nullptr}, {t.er_rp, (nc + 1) * 4, "er_rp", t.cidx != nullptr},
+        {t.er_ci, ne * 4, "er_ci", t.cidx != nullptr && ne > 0}, {t.er64, ne * 8, "er64", t.cidx != nullptr && ne > 0},
+        {t.er32, ne * 4, "er32", t.cidx != nullptr && ne > 0},
+        {t.x64, n * 8, "x64", true}, {t.b64, n * 8, "b64", true}, {t.r64, n * 8, "r64", true},
+        {t.X64[0], n * 8, "X64", true}, {t.X64[1], n * 8, "X64", true}, {t.R64[0], n * 8, "R64", true},
+        {t.R64[1], n * 8, "R64", true}, {t.x32, n * 4, "x32", true}, {t.b32, n * 4, "b32", true},
+        {t.r32, n * 4, "r32", true}, {t.X32[0], n * 4, "X32", true}, {t.X32[1], n * 4, "X32", true},
+        {t.R32[0], n * 4, "R32", true}, {t.R32[1], n * 4, "R32", true}};
+    for (const Ext& e : ex)
+      if (e.need && !inside(e.p, e.bytes)) {
+        std::snprintf(buf, sizeof(buf), "level %d: %s (%zu bytes) outside the hierarchy's allocations", lc + i,
+                      e.what, e.bytes);
+        return buf;
+      }
+    if ((t.agg != nullptr) + (t.cidx != nullptr) > 1 || (i + 1 < nlev) != (t.agg || t.cidx) ||
+        (i + 1 < nlev && (size_t)d[i + 1].n != nc)) {
+      std::snprintf(buf, sizeof(buf), "level %d: transfer does not match level %d", lc + i, lc + i + 1);
+      return buf;
+    }
+  }
+  for (size_t k = 0; k < prog.size(); ++k) {
+    const int4 op = prog[k];
+    const int li = op.y - lc;
+    bool ok = op.x >= OP_GS && op.x <= OP_RRAGG && li >= 0 && li < nlev;
+    if (ok) {
+      const TailLevel& t = d[li];
+      switch (op.x) {
+        case OP_GS: ok = op.z >= 0; break;
+        case OP_RES: ok = op.z >= 0 && op.z <= 2; break;
+        case OP_SAVEX: ok = op.z >= 0 && op.z <= 1; break;
+        case OP_RAGG: case OP_RRAGG: ok = t.agg != nullptr && op.z >= 0 && op.z <= 2; break;
+        case OP_IAGG: ok = t.agg != nullptr; break;
+        case OP_RELIM: case OP_IELIM: ok = t.cidx != nullptr; break;
+        case OP_ZERO: case OP_MEAN: break;
+        case OP_RECOMB: ok = op.z >= 1 && op.z <= 2 && t.agg != nullptr; break;
+        case OP_COARSE: ok = li == nlev - 1; break;
+        default: ok = false;
+      }
+    }
+    if (!ok) {
+      std::snprintf(buf, sizeof(buf), "op %zu (%d, %d, %d, %d) out of range", k, op.x, op.y, op.z, op.w);
+      return buf;
+    }
+  }
+  if (!H->coarsest_relax && !inside(H->cinv, (size_t)H->nL * H->nL * 8)) return "coarsest inverse outside the allocations";
+  for (const int2 b : budgets) {
+    const size_t desc = al16((size_t)nlev * sizeof(TailLevel));
+    size_t t64 = 0, t32 = 0;
+    resident_from<double>(d.data(), nlev, b.x, b.y, &t64);
+    resident_from<float>(d.data(), nlev, b.x, b.y, &t32);
+    if (desc >= (size_t)b.x || desc + t64 > (size_t)b.x || desc + t32 > (size_t)b.x || t64 > (size_t)b.y ||
+        t32 > (size_t)b.y) {
+      std::snprintf(buf, sizeof(buf), "LDS plan of %d levels exceeds a budget of %d bytes", nlev, b.x);
+      return buf;
+    }
+  }
+  return "";
+}
+
+void check_or_throw(const std::string& e) {
+  if (e.empty()) return;
+  set_error_detail(e.c_str());
+  throw DevError{hipErrorInvalidValue};
+}
+
 }  // namespace
 
 void tail_prepare(Hierarchy* H) {
@@ -935,6 +1048,7 @@ void tail_prepare(Hierarchy* H) {
   H->tail_host = d;
   std::vector<int4> prog;
   build_prog(H, lc, prog, H->tail_segs);
+  check_or_throw(program_check(H, d, prog, lc, {make_int2(TAIL_LDS, TAIL_RES)}));
   H->tail_prog = dnew<int4>(H, std::max<size_t>(prog.size(), 1));
   LAMG_HIP(hipMemcpy(H->tail_prog, prog.data(), prog.size() * sizeof(int4), hipMemcpyHostToDevice));
   H->tail_lc = lc;  // ready
@@ -1013,10 +1127,14 @@ void invalidate_programs(Hierarchy* H) {
   // program does (released here: solves are synchronous, none is in flight)
   if (H->full_prog) {
     dev_free(H->o, H->full_prog);
-    H->owned.erase(std::find(H->owned.begin(), H->owned.end(), (void*)H->full_prog));
+    const size_t i = std::find(H->owned.begin(), H->owned.end(), (void*)H->full_prog) - H->owned.begin();
+    H->owned.erase(H->owned.begin() + i);
+    H->owned_bytes.erase(H->owned_bytes.begin() + i);
   }
   H->full_prog = nullptr;
   H->full_nops = 0;
+  H->full_prog_host.clear();
+  H->full_checked = false;
 }
 
 // ============================================== persistent many-graph solve
@@ -1143,6 +1261,7 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_batch(const BatchGraph* __rest
 struct BatchConfig {
   int lds, per_cu, lpt;
 };
+constexpr int kBatchLds[2] = {128 * 1024, 64 * 1024};  // the two LDS budgets (one descriptor copy each)
 constexpr BatchConfig kBatchConfigs[] = {{128 * 1024, 1, 1}, {64 * 1024, 2, 1}, {64 * 1024, 1, 1}, {128 * 1024, 1, 0}};
 constexpr int kNumBatchConfigs = sizeof(kBatchConfigs) / sizeof(kBatchConfigs[0]);
 
@@ -1162,6 +1281,7 @@ void batch_prepare(Hierarchy* H) {
     TailLevel* dd = dnew<TailLevel>(H, d.size());
     LAMG_HIP(hipMemcpy(dd, d.data(), d.size() * sizeof(TailLevel), hipMemcpyHostToDevice));
     H->full_levels = dd;
+    H->full_host = d;
   }
   std::vector<int4> prog;
   std::vector<int2> segs;
@@ -1170,6 +1290,8 @@ void batch_prepare(Hierarchy* H) {
   LAMG_HIP(hipMemcpy(dp, prog.data(), prog.size() * sizeof(int4), hipMemcpyHostToDevice));
   H->full_nops = (int)prog.size();
   H->full_prog = dp;
+  H->full_prog_host = prog;
+  H->full_checked = false;
 }
 
 namespace {
@@ -1225,6 +1347,11 @@ lamg_status solve_graphs(int count, Hierarchy* const* hs, const double* const* B
     Hierarchy* H = hs[i];
     if (noalloc && (!H->full_prog || !H->full_levels)) return LAMG_E_INVALID_ARG;  // (prepared at setup)
     batch_prepare(H);
+    if (!H->full_checked) {
+      check_or_throw(program_check(H, H->full_host, H->full_prog_host, 0,
+                                   {make_int2(kBatchLds[0], kBatchLds[0] / 2), make_int2(kBatchLds[1], kBatchLds[1] / 2)}));
+      H->full_checked = true;
+    }
     BatchGraph& g = G[i];
     std::memset(&g, 0, sizeof(g));
     g.P.L = (const TailLevel*)H->full_levels;
@@ -1285,7 +1412,7 @@ lamg_status solve_graphs(int count, Hierarchy* const* hs, const double* const* B
   int* queue = (int*)(buf + 2 * gb + 2 * (size_t)count * sizeof(int));
   BatchOut* dout = (BatchOut*)(buf + 2 * gb + 2 * (size_t)count * sizeof(int) + 256);
   for (int v = 0; v < 2; ++v) {
-    const int lds = v == 0 ? 128 * 1024 : 64 * 1024;
+    const int lds = kBatchLds[v];
     for (BatchGraph& g : G) {
       g.P.lds_bytes = lds;
       g.P.res_bytes = lds / 2;

@@ -116,23 +116,37 @@ def test_grid3d_multivector_full(lg):
 
 
 def test_graph_batch_full(ora, lg):
-    """The 256-graph batch in one persistent launch (FP64): every graph at
-    1e-8 (scipy residual); the eight smallest graphs against the oracle."""
-    _case("graph_batch_256 full size")
+    """The 256-graph batch in one persistent launch, FP64 and then FP32 cycles
+    with FP64 refinement (each precision's first call tunes the launch
+    configuration, so every configuration runs): every graph at 1e-8 (scipy
+    residual); the eight smallest graphs against the oracle in both
+    precisions; the FP32 solutions against the FP64 ones."""
+    _case("graph_batch_256 full size, fp64")
     gs = W.graph_batch()
     bs = [W.rhs_normal(g.n, 1, 1000 + i) for i, g in enumerate(gs)]
+    bd = [torch.tensor(b, device="cuda") for b in bs]
     hs = [lg.Hierarchy(g.n, g.eu, g.ev, g.w) for g in gs]
-    X, infos, rc = lg.solve_batch(hs, [torch.tensor(b, device="cuda") for b in bs])
-    assert rc == 0
-    for i, (g, b) in enumerate(zip(gs, bs)):
-        x = X[i].cpu().numpy()
-        assert rel_residual(laplacian(g), b, x) <= 1.0000001e-8, i
-        assert infos[i]["rel_residual"] <= 1e-8, i
-    for i in np.argsort([g.n for g in gs])[:8]:
-        g = gs[i]
-        xo, io, _ = ora.Hierarchy(g.n, g.eu, g.ev, g.w).solve(bs[i])
-        assert abs(infos[i]["cycles"] - io["cycles"]) <= 1, i
-        assert np.linalg.norm(X[i].cpu().numpy() - xo) <= 1e-6 * np.linalg.norm(xo), i
+    small = np.argsort([g.n for g in gs])[:8]
+    X64 = None
+    for prec in (0, 1):
+        _case(f"graph_batch_256 full size, precision {prec}")
+        for h in hs:
+            h.set_solve_options(precision=prec)
+        X, infos, rc = lg.solve_batch(hs, bd)
+        assert rc == 0, prec
+        for i, (g, b) in enumerate(zip(gs, bs)):
+            x = X[i].cpu().numpy()
+            assert rel_residual(laplacian(g), b, x) <= 1.0000001e-8, (prec, i)
+            assert infos[i]["rel_residual"] <= 1e-8, (prec, i)
+            if X64 is not None:
+                assert np.linalg.norm(x - X64[i]) <= 1e-6 * np.linalg.norm(X64[i]), i
+        for i in small:
+            g = gs[i]
+            xo, io, _ = ora.Hierarchy(g.n, g.eu, g.ev, g.w).solve(bs[i], precision=prec)
+            assert abs(infos[i]["cycles"] - io["cycles"]) <= 1, (prec, i)
+            assert np.linalg.norm(X[i].cpu().numpy() - xo) <= 1e-6 * np.linalg.norm(xo), (prec, i)
+        if prec == 0:
+            X64 = [x.cpu().numpy() for x in X]
 
 
 def test_rgg_adjoint_full(lg):
