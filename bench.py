@@ -10,7 +10,11 @@ the same hierarchy and reported beside it.
 value = edges * cycles / second over the timed steps (edges = m of the input
 graph); GB/s = algorithmic bytes of the timed cycles / time.  The roofline
 object covers the dominant kernel (the multicolour Gauss-Seidel relaxation),
-timed live with HIP events around each of its launches on the solve stream.
+timed live with HIP events on the solve stream around each run of its
+back-to-back launches (one span per sweep's launched colours), in a second
+pass over the same solves that launches the cycle eagerly.  Beside the
+two-level headline, a multilevel graph (RGG 2^20) is solved with per-kernel
+spans; the CPU oracle runs on the headline's own graph and right-hand side.
 """
 from __future__ import annotations
 
@@ -37,6 +41,8 @@ def parse():
                             "negative_grid_1024"])
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU reference baseline")
     p.add_argument("--no-fp32", action="store_true")
+    p.add_argument("--no-multilevel", action="store_true",
+                   help="skip the multilevel (RGG 2^20) solve timed beside the Chung-Lu headline")
     p.add_argument("--eigs", type=int, default=4,
                    help="lowest eigenpairs timed beside the solve on the same hierarchy (0: skip)")
     p.add_argument("--copy-bytes", type=int, default=0,
@@ -405,10 +411,46 @@ def copy_ceiling_gbps():
     return gbps
 
 
-def cpu_baseline(name):
+def cpu_baseline_same_input(name, gpu_cycles=None):
+    """The CPU reference (serial C++) on the benchmark's own input: the same
+    graph and right-hand side, setup untimed, one FP64 solve to 1e-8 timed
+    (its cycle count is compared with the GPU's).  The half-size sample of
+    the same recipe (several right-hand sides) is reported beside it."""
+    from oracle import oracle as O
+    from paper_1108_1310_amd import workloads as W
+    g, b = W.config(name)
+    b = b.reshape(-1)
+    t0 = time.perf_counter()
+    H = O.Hierarchy(g.n, g.eu, g.ev, g.w)
+    setup_s = time.perf_counter() - t0
+    print(f"[bench] cpu oracle setup {setup_s:.1f} s", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    x, info, _ = H.solve(b)
+    dt = time.perf_counter() - t0
+    A0 = H.level(0).A
+    xr, br = W.rhs_normal(g.n, 1, 7), W.rhs_normal(g.n, 1, 8)
+    O.residual(A0, br, xr)
+    t1 = time.perf_counter()
+    for _ in range(3):
+        O.residual(A0, br, xr)
+    mvm_s = (time.perf_counter() - t1) / 3
+    digits = -math.log10(max(info["rel_residual"], 1e-300))
+    del H
+    half = cpu_baseline("chung_lu_2p19")
+    return {"value": g.m * info["cycles"] / dt, "unit": "edges*cycles/s", "cores": 1, "kind": "oracle",
+            "sample": "the benchmark's own graph and right-hand side, one FP64 solve to 1e-8, 1 thread "
+                      "(setup not timed)",
+            "cycles": info["cycles"], "gpu_cycles": gpu_cycles,
+            "cycles_match": gpu_cycles is None or int(round(gpu_cycles)) == info["cycles"],
+            "rel_residual": info["rel_residual"], "solve_s": dt, "edges": g.m, "host": host_cpu(),
+            "setup_s": setup_s, "mvm_ms": mvm_s * 1e3, "setup_mvm": setup_s / mvm_s,
+            "solve_mvm_per_digit": dt / mvm_s / digits, "half_size_sample": half}
+
+
+def cpu_baseline(name, gpu_cycles=None):
     """The CPU reference (serial C++) on a bounded sample of the same workload
     recipe: seeded right-hand sides solved one after another until about
-    CPU_MIN_S seconds of solve work."""
+    CPU_MIN_S seconds of solve work (the Chung-Lu headline: its own input)."""
     from oracle import oracle as O
     from paper_1108_1310_amd import workloads as W
     if name == "graph_batch_256":
@@ -427,6 +469,8 @@ def cpu_baseline(name):
         return {"value": ec / dt, "unit": "edges*cycles/s", "cores": 1, "kind": "oracle", "sample": sample,
                 "solve_s": dt, "host": host_cpu()}
     if name == "chung_lu_2p20":
+        return cpu_baseline_same_input(name, gpu_cycles)
+    if name == "chung_lu_2p19":
         g = W.chung_lu(1 << 19)
         seed, what, cap = W.SEEDS["chung_lu"], "Chung-Lu recipe at n0 = 2^19 (half the workload)", 64
     elif name == "rgg_2p20":
@@ -667,10 +711,13 @@ def main():
         if not a.no_cpu:
             eig["cpu_baseline"] = eigs_cpu_sample(a.eigs, lamg)
             print(f"[bench] eigs oracle sample {eig['cpu_baseline']}", file=sys.stderr, flush=True)
+    ml = None
+    if a.workload == "chung_lu_2p20" and not a.no_multilevel:
+        ml = multilevel_rgg(a, lamg)
     cpu = None
     if not a.no_cpu:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(a.workload)
+        cpu = cpu_baseline(a.workload, r64["cycles"] / a.steps)
     value = g.m * r64["cycles"] / r64["seconds"]
     rec = {
         "metric": "edges*cycles/s to 1e-8 rel. residual (FP64; FP32+refine beside)",
@@ -700,10 +747,54 @@ def main():
         "lgm": lgm,
         "negative_grid_table": table,
         "eigs": eig,
+        "multilevel_rgg_2p20": ml,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)
+
+
+def multilevel_rgg(a, lamg, steps_cap=5):
+    """A multilevel workload beside the two-level headline: the random
+    geometric graph of 2^20 points (20 levels: aggregation transfers, iterate
+    recombination and the single-workgroup tail all run), FP64 solves to 1e-8
+    timed as the headline is, then the same solves instrumented with HIP event
+    spans per kernel: GS, residual, aggregation restriction and interpolation
+    (time, launches, algorithmic bytes) and the tail launches (time only)."""
+    import torch
+    g, b = workload("rgg_2p20")
+    bd = torch.tensor(b.reshape(-1), device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    H = lamg.Hierarchy(g.n, g.eu, g.ev, g.w)
+    torch.cuda.synchronize()
+    setup_ms = (time.perf_counter() - t0) * 1e3
+    steps = max(1, min(a.steps, steps_cap))
+    r = timed_solves(H, bd, lamg.FP64, steps, 1, lamg)
+    print(f"[bench] multilevel rgg_2p20 fp64 {r['seconds']:.3f}s cycles={r['cycles']}", file=sys.stderr, flush=True)
+    lamg.prof_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        H.solve(bd)
+    torch.cuda.synchronize()
+    inst_ms = (time.perf_counter() - t0) * 1e3
+    kernels = {}
+    for name, kid in (("gs", 0), ("residual", 1), ("restrict_agg", 10), ("interp_agg", 12), ("tail", 14)):
+        p = lamg.prof_read(kid)
+        kernels[name] = {"ms_per_solve": p["ms"] / steps, "launches_per_solve": p["launches"] / steps,
+                         "avg_us": 1e3 * p["ms"] / max(1, p["launches"]), "share_of_step": p["ms"] / inst_ms,
+                         "gbps": p["bytes"] / (p["ms"] * 1e6) if p["ms"] > 0 and p["bytes"] > 0 else None,
+                         "bytes_per_launch": p["bytes"] / max(1, p["launches"]) if p["bytes"] > 0 else None}
+    lamg.prof_enable(False)
+    cyc = r["cycles"] / steps
+    kernels["tail"]["us_per_cycle"] = 1e3 * kernels["tail"]["ms_per_solve"] / max(cyc, 1)
+    out = {"workload": "rgg_2p20", "n": g.n, "m": g.m, "levels": H.num_levels, "setup_ms": setup_ms,
+           "value": g.m * r["cycles"] / r["seconds"], "unit": "edges*cycles/s",
+           "ms_per_solve": r["seconds"] * 1e3 / steps, "cycles_per_solve": cyc, "acf": r["acf"],
+           "rel_residual": r["rel_residual"], "gbps": r["bytes"] / r["seconds"] / 1e9,
+           "instrumented_ms_per_solve": inst_ms / steps, "kernels": kernels}
+    H.close()
+    return out
 
 
 if __name__ == "__main__":

@@ -42,6 +42,14 @@ typedef enum { LAMG_FP64 = 0, LAMG_FP32_REFINE = 1 } lamg_precision;
 /* Energy correction (Section 3.4.4-3.4.5): iterate recombination (eq. recomb)
  * or a flat factor mu on the restricted residual (eq. galerkin2). */
 typedef enum { LAMG_EC_RECOMBINE = 0, LAMG_EC_FLAT_MU = 1 } lamg_energy_correction;
+/* The norm iterate recombination minimises over its combinations: the
+ * residual 2-norm as eq. recomb prints it (default), or the energy norm of the
+ * error (y - x*)^T A (y - x*), computable as 1/2 y^T A y - b^T y.  The energy
+ * norm converges on smooth right-hand sides where the printed norm can stall
+ * (random geometric graphs, anisotropic grids) but is unreliable close to the
+ * rounding floor of large graphs (tolerances near 1e-10); the flat energy
+ * correction (LAMG_EC_FLAT_MU) converges in both regimes. */
+typedef enum { LAMG_RECOMB_RESIDUAL = 0, LAMG_RECOMB_ENERGY = 1 } lamg_recomb_norm;
 
 typedef struct lamg_options {
   uint32_t struct_size;     /* sizeof(lamg_options); set by lamg_options_default */
@@ -88,6 +96,9 @@ typedef struct lamg_options {
    * affinity and energy-ratio tests of a level with a negative weight then
    * use |w|.  0 (default): weights must be > 0 (LAMG_E_BAD_WEIGHT). */
   int allow_negative_weights;
+  /* lamg_recomb_norm of iterate recombination (solve phase; changeable by
+   * lamg_set_solve_options), LAMG_RECOMB_RESIDUAL by default. */
+  int recomb_norm;
 } lamg_options;
 
 typedef struct lamg_info {
@@ -232,8 +243,9 @@ lamg_status lamg_edge_gradient(int64_t m, const int32_t* eu, const int32_t* ev, 
 lamg_status lamg_eigs(lamg_handle h, int32_t k, double* X, double* evals, double tol, int32_t max_iter,
                       int32_t cycles, int32_t* iters, double* resid);
 
-/* Change solve-phase options of an existing hierarchy (precision, ec, tol,
- * max_cycles, warm_start, stream); setup-phase fields are ignored. */
+/* Change solve-phase options of an existing hierarchy (precision, ec, mu,
+ * nu_pre, nu_post, recomb_norm, tol, max_cycles, warm_start, stream);
+ * setup-phase fields are ignored. */
 lamg_status lamg_set_solve_options(lamg_handle h, const lamg_options* o);
 
 /* Release a hierarchy; NULL is a no-op. */

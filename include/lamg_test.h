@@ -114,7 +114,9 @@ lamg_status lamg_t_level_gs(lamg_handle h, int32_t l, int32_t precision, int32_t
  * every later launch with HIP events on the launch's stream; kernel ids:
  * 0 GS FP64, 1 residual FP64, 2 GS FP32, 3 residual FP32, 4..7 the same
  * four for the multi-vector kernels, 8 / 9 the hub sweep (FP64 / FP32; its
- * colours are not in 0 / 2).  lamg_t_prof_read waits for the recorded events and returns the summed kernel time (ms), the
+ * colours are not in 0 / 2), 10 / 11 the aggregation restriction, 12 / 13 the
+ * aggregation interpolation, 14 / 15 the single-workgroup tail launches
+ * (single-vector cycles; no bytes counted: latency-bound).  lamg_t_prof_read waits for the recorded events and returns the summed kernel time (ms), the
  * number of launches and their algorithmic bytes (HOST outputs). */
 void lamg_t_prof_enable(int on);
 lamg_status lamg_t_prof_read(int kernel, double* ms, int64_t* launches, int64_t* bytes);

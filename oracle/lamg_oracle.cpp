@@ -123,6 +123,8 @@ struct Opts {  // mirrors the library options, defaults from Section 4
   int coarsest_sweeps = 3;       // relaxation sweeps of a coarsest level that relaxation solves
   int dense_max = 8192;          // largest coarsest level factored densely
   int allow_negative = 0;        // Section 5.2: accept negative weights (|w| in the aggregation tests)
+  int recomb_norm = 0;           // the norm iterate recombination minimises: 0 the residual 2-norm as
+                                 // printed in eq. recomb (default), 1 the energy norm of the error
   int recomb_finest = 1;         // 1: iterate recombination also at the finest level (read from Section
                                  // 3.4.5 as every level followed by an aggregation level); 0: only at
                                  // levels entered from a finer one ("when the cycle switches from
@@ -837,24 +839,43 @@ double dot(const vector<T>& a, const vector<T>& b) {
   return s;
 }
 
-// Residual-minimising combination y = x + sum_i alpha_i (x_i - x) (eq. recomb):
-// x is the final iterate with residual r, X[i] the saved iterates with
-// residuals R[i]; the residual of y is r + sum_i alpha_i (R[i] - r), so alpha
-// solves the th x th normal equations of that least-squares problem (FP64).
+// Iterate recombination y = x + sum_i alpha_i (x_i - x) (eq. recomb): x is
+// the final iterate with residual r, X[i] the saved iterates with residuals
+// R[i].  With D_i = X[i] - x, the residual of y is r + sum_i alpha_i d_i with
+// d_i = R[i] - r = -A D_i.  alpha solves the th x th normal equations
+// G alpha = -g in FP64 of
+//   norm 0 (as printed): min ||b - A y||_2:  G_ij = d_i . d_j,  g_i = d_i . r;
+//   norm 1 (energy):     min (y - x*)^T A (y - x*), i.e. min 1/2 y^T A y - b^T y:
+//                        G_ij = D_i^T A D_j = -D_i . d_j (the two off-diagonal
+//                        products averaged),  g_i = -D_i . r.
+// A direction is dropped (alpha_i = 0) when its Gram entry is not above
+// 1e-28 r.r (norm 0) or 0 (norm 1), or the 2 x 2 system is near singular.
 // Writes y over x and alpha[0..th-1].
 template <class T>
 void recombine_core(vector<T>& x, const vector<T>& r, const vector<vector<T>>& X, const vector<vector<T>>& R, int th,
-                    double* alpha_out) {
+                    int norm, double* alpha_out) {
   const i64 n = (i64)x.size();
-  vector<vector<T>> d(th, vector<T>(n));
-  for (int i = 0; i < th; ++i) for (i64 u = 0; u < n; ++u) d[i][u] = R[i][u] - r[u];
+  vector<vector<T>> d(th, vector<T>(n)), D(th, vector<T>(n));
+  for (int i = 0; i < th; ++i)
+    for (i64 u = 0; u < n; ++u) {
+      d[i][u] = R[i][u] - r[u];
+      D[i][u] = X[i][u] - x[u];
+    }
   double G[2][2] = {{0, 0}, {0, 0}}, g[2] = {0, 0}, rr = dot(r, r);
-  for (int i = 0; i < th; ++i) {
-    g[i] = dot(d[i], r);
-    for (int j = 0; j < th; ++j) G[i][j] = dot(d[i], d[j]);
+  if (norm == 0) {
+    for (int i = 0; i < th; ++i) {
+      g[i] = dot(d[i], r);
+      for (int j = 0; j < th; ++j) G[i][j] = dot(d[i], d[j]);
+    }
+  } else {
+    for (int i = 0; i < th; ++i) {
+      g[i] = -dot(D[i], r);
+      G[i][i] = -dot(D[i], d[i]);
+    }
+    if (th > 1) G[0][1] = G[1][0] = 0.5 * (-dot(D[0], d[1]) - dot(D[1], d[0]));
   }
   double alpha[2] = {0, 0};
-  const double tiny = 1e-28 * rr;
+  const double tiny = norm == 0 ? 1e-28 * rr : 0.0;
   if (th == 1) {
     if (G[0][0] > tiny) alpha[0] = -g[0] / G[0][0];
   } else {
@@ -881,7 +902,7 @@ template <class T>
 void recombine(const Hier& H, Work<T>& W, int l, int th) {
   const Level& L = H.lv[l];
   residual<T>(L.A, VAL<T>(L), DIAG<T>(L), W.b[l].data(), W.x[l].data(), W.r[l].data());
-  recombine_core<T>(W.x[l], W.r[l], W.X[l], W.R[l], th, nullptr);
+  recombine_core<T>(W.x[l], W.r[l], W.X[l], W.R[l], th, H.o.recomb_norm, nullptr);
 }
 
 template <class T>
@@ -1081,6 +1102,7 @@ typedef struct ora_opts {
   int coarsest_sweeps, dense_max;
   int allow_negative;
   int recomb_finest;
+  int recomb_norm;
 } ora_opts;
 
 void ora_opts_default(ora_opts* o) {
@@ -1097,13 +1119,14 @@ void ora_opts_default(ora_opts* o) {
   o->dense_max = d.dense_max;
   o->allow_negative = d.allow_negative;
   o->recomb_finest = d.recomb_finest;
+  o->recomb_norm = d.recomb_norm;
 }
 
 // --- one iterate recombination (eq. recomb) on a raw CSR: x (final iterate)
 // and th <= 2 saved iterates Xs (n x th row-major, column i = iterate i);
 // residuals are formed here.  Writes y into y_out and alpha[0..th-1].
 void ora_recombine(i64 n, const i64* ptr, const i32* col, const double* val, const double* diag, const double* b,
-                   const double* x, const double* Xs, int th, double* y_out, double* alpha) {
+                   const double* x, const double* Xs, int th, int norm, double* y_out, double* alpha) {
   Csr A;
   A.n = n;
   A.ptr.assign(ptr, ptr + n + 1);
@@ -1117,7 +1140,7 @@ void ora_recombine(i64 n, const i64* ptr, const i32* col, const double* val, con
     for (i64 u = 0; u < n; ++u) X[i][u] = Xs[u * th + i];
     residual<double>(A, A.val.data(), A.diag.data(), b, X[i].data(), R[i].data());
   }
-  recombine_core<double>(xv, r, X, R, th, alpha);
+  recombine_core<double>(xv, r, X, R, th, norm, alpha);
   std::copy(xv.begin(), xv.end(), y_out);
 }
 
@@ -1139,6 +1162,7 @@ static Opts to_opts(const ora_opts* o) {
   d.dense_max = o->dense_max;
   d.allow_negative = o->allow_negative;
   d.recomb_finest = o->recomb_finest;
+  d.recomb_norm = o->recomb_norm;
   return d;
 }
 

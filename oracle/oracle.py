@@ -37,7 +37,7 @@ class Opts(C.Structure):
                 ("ec", C.c_int), ("tol", C.c_double), ("max_cycles", C.c_int),
                 ("seed", C.c_uint64), ("stage1_quantile", C.c_double), ("relax_fast_ratio", C.c_double),
                 ("coarsest_sweeps", C.c_int), ("dense_max", C.c_int), ("allow_negative", C.c_int),
-                ("recomb_finest", C.c_int)]
+                ("recomb_finest", C.c_int), ("recomb_norm", C.c_int)]
 
 
 _lib = None
@@ -55,7 +55,7 @@ def lib():
         sig = {
             "ora_opts_default": (None, [C.POINTER(Opts)]),
             "ora_set_plain_rows": (None, [C.c_int]),
-            "ora_recombine": (None, [i64, i64p, i32p, dp, dp, dp, dp, dp, C.c_int, dp, dp]),
+            "ora_recombine": (None, [i64, i64p, i32p, dp, dp, dp, dp, dp, C.c_int, C.c_int, dp, dp]),
             "ora_laplacian": (vp, [i64, i64, i32p, i32p, dp, C.POINTER(C.c_int)]),
             "ora_csr_nnz": (i64, [vp]), "ora_csr_n": (i64, [vp]),
             "ora_csr_export": (None, [vp, i64p, i32p, dp, dp]),
@@ -193,16 +193,18 @@ def unit_pm1(h) -> float:
     return float(lib().ora_unit_pm1(h))
 
 
-def recombine(A: Csr, b, x, Xs):
+def recombine(A: Csr, b, x, Xs, norm: int = 0):
     """Iterate recombination (eq. recomb) of the final iterate x with the
-    saved iterates Xs ([n, th], th <= 2).  Returns (y, alpha)."""
+    saved iterates Xs ([n, th], th <= 2), minimising the residual 2-norm
+    (norm 0, as printed) or the energy norm of the error (norm 1).
+    Returns (y, alpha)."""
     Xs = np.ascontiguousarray(np.asarray(Xs, np.float64).reshape(A.n, -1))
     th = Xs.shape[1]
     y = np.zeros(A.n)
     alpha = np.zeros(th)
     lib().ora_recombine(A.n, _p(_i64(A.ptr), C.c_int64), _p(_i32(A.col), C.c_int32), _p(_f64(A.val), C.c_double),
                         _p(_f64(A.diag), C.c_double), _p(_f64(b), C.c_double), _p(_f64(x), C.c_double),
-                        _p(Xs, C.c_double), th, _p(y, C.c_double), _p(alpha, C.c_double))
+                        _p(Xs, C.c_double), th, int(norm), _p(y, C.c_double), _p(alpha, C.c_double))
     return y, alpha
 
 

@@ -97,7 +97,7 @@ void body(Hierarchy* H, int l, int sub, std::vector<int64_t>& count) {
   residual<T>(s, L, val, dg, v.b, v.x, r);
   if (rec) hipLaunchKernelGGL(k_copy<T>, grid1(L.n), dim3(256), 0, s, L.n, (const T*)v.x, v.X[sub]);
   const T mu = rec ? T(1) : (T)H->o.mu;
-  restrict_agg<T>(s, C, r, vc.b, mu);
+  restrict_agg<T>(s, C, L.n, r, vc.b, mu);
   fill<T>(s, vc.x, T(0), C.n);
   const int64_t c = count[l]++;
   const double gl = L.gamma_next;
@@ -247,9 +247,11 @@ int64_t cycle_bytes_k(const Hierarchy* H, int prec, int k) {
     }
     tot += bodies[l] * body;
     if (H->o.ec == LAMG_EC_RECOMBINE && C.type == LT_AGG) {
-      // per visit: final residual, Gram (th+1 vectors), update (th+2 vectors)
+      // per visit: final residual, Gram (residuals: th+1 vectors; energy
+      // norm: iterates too, 2 (th+1)), update (th+2 vectors)
       const int64_t th = visits[l] ? (recth[l] + visits[l] - 1) / visits[l] : 1;
-      tot += visits[l] * ((M + 3 * n * sx) + (th + 1) * n * sx + (th + 2) * n * sx);
+      const int64_t gram = (H->o.recomb_norm == LAMG_RECOMB_ENERGY ? 2 : 1) * (th + 1);
+      tot += visits[l] * ((M + 3 * n * sx) + gram * n * sx + (th + 2) * n * sx);
     }
   }
   tot += 2 * (int64_t)H->lv[0].n * sx;  // mean removal
@@ -298,6 +300,7 @@ void lamg_options_default(lamg_options* o) {
   o->dealloc = nullptr;
   o->alloc_ctx = nullptr;
   o->allow_negative_weights = 0;
+  o->recomb_norm = LAMG_RECOMB_RESIDUAL;
 }
 
 const char* lamg_last_error(void) { return g_last_error; }
@@ -322,7 +325,8 @@ static bool opts_ok(const lamg_options& o) {
          o.elim_max_degree >= 0 && o.stage1_quantile >= 0.0 && o.stage1_quantile <= 1.0 && o.tol >= 0 &&
          o.max_cycles >= 0 && o.coarsest_sweeps >= 1 && o.dense_max >= 1 && o.dense_max <= 8192 && o.tail_max_n >= 0 &&
          (o.alloc == nullptr) == (o.dealloc == nullptr) &&
-         (o.allow_negative_weights == 0 || o.allow_negative_weights == 1);
+         (o.allow_negative_weights == 0 || o.allow_negative_weights == 1) &&
+         (o.recomb_norm == LAMG_RECOMB_RESIDUAL || o.recomb_norm == LAMG_RECOMB_ENERGY);
 }
 
 }  // extern "C"
@@ -419,13 +423,20 @@ lamg_status lamg_setup_lgm(int32_t side, const lamg_options* o, lamg_handle* out
 lamg_status lamg_set_solve_options(lamg_handle h, const lamg_options* o) {
   if (!h || !o || o->struct_size != sizeof(lamg_options)) return LAMG_E_INVALID_ARG;
   if (o->tol < 0 || o->max_cycles < 0 || (o->precision != LAMG_FP64 && o->precision != LAMG_FP32_REFINE) ||
-      (o->ec != LAMG_EC_RECOMBINE && o->ec != LAMG_EC_FLAT_MU))
+      (o->ec != LAMG_EC_RECOMBINE && o->ec != LAMG_EC_FLAT_MU) ||
+      (o->recomb_norm != LAMG_RECOMB_RESIDUAL && o->recomb_norm != LAMG_RECOMB_ENERGY))
     return LAMG_E_INVALID_ARG;
   Hierarchy* H = &h->H;
   // the captured cycles and the tail program depend on these options
   if (o->nu_pre < 0 || o->nu_post < 0) return LAMG_E_INVALID_ARG;
+  // captured cycles hold the options as kernel arguments; op programs hold ec, mu and nu
+  const bool regraph = o->recomb_norm != H->o.recomb_norm;
   const bool reprogram =
       o->ec != H->o.ec || o->mu != H->o.mu || o->nu_pre != H->o.nu_pre || o->nu_post != H->o.nu_post;
+  if (regraph && !reprogram) {
+    drop_graphs(H);
+    mv_drop_graphs(H);
+  }
   if (reprogram) {
     drop_graphs(H);
     mv_drop_graphs(H);
@@ -440,6 +451,7 @@ lamg_status lamg_set_solve_options(lamg_handle h, const lamg_options* o) {
   H->o.stream = o->stream;
   H->o.nu_pre = o->nu_pre;
   H->o.nu_post = o->nu_post;
+  H->o.recomb_norm = o->recomb_norm;
   H->s = (hipStream_t)o->stream;
   if (reprogram && H->lv[0].n <= BATCH_MAX_N) {
     try {

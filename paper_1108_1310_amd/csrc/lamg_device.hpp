@@ -63,5 +63,51 @@ __device__ inline T row_sum_wave(int len, int lane, F term) {
   return total;
 }
 
+// Iterate recombination (eq. recomb), y = x + sum_i alpha_i (X_i - x) over
+// th <= 2 saved iterates.  With D_i = X_i - x and d_i = R_i - r = -A D_i, the
+// six running sums of one element are, for
+//   norm 0 (the residual 2-norm, as printed): d0.d0, d0.d1, d1.d1, d0.r, d1.r, r.r
+//   norm 1 (the energy norm of the error):   -D0.d0, -D0.d1, -D1.d1, -D0.r, -D1.r, -D1.d0
+// so that in both cases alpha solves G alpha = -g with G from the first three
+// (norm 1: the off-diagonal averaged over its two products) and g from the
+// next two.
+template <class T>
+__device__ inline void recomb_terms(int norm, int th, T ru, T R0, T R1, T xu, T X0, T X1, double (&v)[6]) {
+  const double r = (double)ru;
+  const double d0 = (double)(R0 - ru);
+  const double d1 = th > 1 ? (double)(R1 - ru) : 0.0;
+  if (norm == 0) {
+    v[0] += d0 * d0; v[1] += d0 * d1; v[2] += d1 * d1; v[3] += d0 * r; v[4] += d1 * r; v[5] += r * r;
+  } else {
+    const double e0 = (double)(X0 - xu);
+    const double e1 = th > 1 ? (double)(X1 - xu) : 0.0;
+    v[0] += -(e0 * d0); v[1] += -(e0 * d1); v[2] += -(e1 * d1); v[3] += -(e0 * r); v[4] += -(e1 * r);
+    v[5] += -(e1 * d0);
+  }
+}
+// The th x th normal equations from the six totals; a direction is dropped
+// (alpha_i = 0) when its Gram entry is not above 1e-28 r.r (norm 0) or 0
+// (norm 1), or when the 2 x 2 determinant is at most 1e-12 G00 G11.
+__host__ __device__ inline void recomb_alpha(int norm, int th, const double (&t)[6], double* a0, double* a1) {
+  const double G00 = t[0], G11 = t[2], g0 = t[3], g1 = t[4];
+  const double G01 = norm == 0 ? t[1] : 0.5 * (t[1] + t[5]);
+  const double tiny = norm == 0 ? 1e-28 * t[5] : 0.0;
+  *a0 = 0;
+  *a1 = 0;
+  if (th == 1) {
+    if (G00 > tiny) *a0 = -g0 / G00;
+    return;
+  }
+  const double det = G00 * G11 - G01 * G01;
+  if (G00 > tiny && G11 > tiny && det > 1e-12 * G00 * G11) {
+    *a0 = (-g0 * G11 + g1 * G01) / det;
+    *a1 = (-g1 * G00 + g0 * G01) / det;
+  } else if (G00 >= G11) {
+    if (G00 > tiny) *a0 = -g0 / G00;
+  } else {
+    if (G11 > tiny) *a1 = -g1 / G11;
+  }
+}
+
 }  // namespace dev
 }  // namespace lamg

@@ -228,8 +228,10 @@ struct Hierarchy {
 // on its stream and its algorithmic bytes are accumulated per kernel:
 // 0 GS FP64, 1 residual FP64, 2 GS FP32, 3 residual FP32, 4..7 the same
 // four for the multi-vector kernels, 8 / 9 the hub sweep (FP64 / FP32: the
-// partial-sum launch and the single-workgroup sweep of each GS sweep).
-constexpr int PROF_KERNELS = 10;
+// partial-sum launch and the single-workgroup sweep of each GS sweep),
+// 10 / 11 aggregation restriction, 12 / 13 aggregation interpolation,
+// 14 / 15 the single-workgroup tail launches (FP64 / FP32).
+constexpr int PROF_KERNELS = 16;
 // Spans: prof_begin records the opening event of a run of launches of one
 // kernel, prof_count adds each launch (and its algorithmic bytes) of that
 // kernel to the open span, prof_end records the closing event.
@@ -280,7 +282,7 @@ void gs_multi_sweep(hipStream_t s, const Level& L, const double* b, double* X, i
 
 // transfers
 template <class T>
-void restrict_agg(hipStream_t s, const Level& C, const T* r, T* bc, T mu);
+void restrict_agg(hipStream_t s, const Level& C, int nfine, const T* r, T* bc, T mu);
 template <class T>
 void interp_agg(hipStream_t s, const Level& C, int nfine, const T* e, T* x);
 template <class T>

@@ -311,8 +311,10 @@ __global__ __launch_bounds__(MVT) void k_colsum(int n, int k, int rows, const T*
 }
 // Recombination dots per column with d_i = R_i - r: G00, G01, G11, g0, g1, r.r
 template <class T>
-__global__ __launch_bounds__(MVT) void k_coldots(int n, int k, int rows, int stride, int th, const T* __restrict__ r,
-                                                 const T* __restrict__ R0, const T* __restrict__ R1,
+__global__ __launch_bounds__(MVT) void k_coldots(int n, int k, int rows, int stride, int th, int norm,
+                                                 const T* __restrict__ r, const T* __restrict__ R0,
+                                                 const T* __restrict__ R1, const T* __restrict__ x,
+                                                 const T* __restrict__ X0, const T* __restrict__ X1,
                                                  double* __restrict__ part) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= k * rows) return;
@@ -320,15 +322,8 @@ __global__ __launch_bounds__(MVT) void k_coldots(int n, int k, int rows, int str
   double v[6] = {0, 0, 0, 0, 0, 0};
   for (int i = g / k; i < n; i += rows) {
     const size_t o = (size_t)i * k + c;
-    const double ru = (double)r[o];
-    const double d0 = (double)(R0[o] - r[o]);
-    const double d1 = th > 1 ? (double)(R1[o] - r[o]) : 0.0;
-    v[0] += d0 * d0;
-    v[1] += d0 * d1;
-    v[2] += d1 * d1;
-    v[3] += d0 * ru;
-    v[4] += d1 * ru;
-    v[5] += ru * ru;
+    dev::recomb_terms<T>(norm, th, r[o], R0[o], th > 1 ? R1[o] : T(0), norm ? x[o] : T(0), norm ? X0[o] : T(0),
+                         norm && th > 1 ? X1[o] : T(0), v);
   }
 #pragma unroll
   for (int q = 0; q < 6; ++q) part[(size_t)q * stride + g] = v[q];
@@ -356,30 +351,13 @@ __global__ __launch_bounds__(MVT) void k_colfinish(int k, int rows, const double
 }
 // Per column: the th x th normal equations of min || r + sum_i alpha_i d_i ||
 // (eq. recomb), with the drop rules of the single-vector kernel.
-__global__ __launch_bounds__(MVT) void k_colalpha(int k, int rows, int stride, int th, const double* __restrict__ part,
-                                                  double* __restrict__ alpha) {
+__global__ __launch_bounds__(MVT) void k_colalpha(int k, int rows, int stride, int th, int norm,
+                                                  const double* __restrict__ part, double* __restrict__ alpha) {
   const int c = blockIdx.x;
   double tot[6];
   for (int q = 0; q < 6; ++q) tot[q] = col_total(k, rows, part + (size_t)q * stride, c);
   if (threadIdx.x != 0) return;
-  const double G00 = tot[0], G01 = tot[1], G11 = tot[2], g0 = tot[3], g1 = tot[4], rr = tot[5];
-  const double tiny = 1e-28 * rr;
-  double a0 = 0, a1 = 0;
-  if (th == 1) {
-    if (G00 > tiny) a0 = -g0 / G00;
-  } else {
-    const double det = G00 * G11 - G01 * G01;
-    if (G00 > tiny && G11 > tiny && det > 1e-12 * G00 * G11) {
-      a0 = (-g0 * G11 + g1 * G01) / det;
-      a1 = (-g1 * G00 + g0 * G01) / det;
-    } else if (G00 >= G11) {
-      if (G00 > tiny) a0 = -g0 / G00;
-    } else {
-      if (G11 > tiny) a1 = -g1 / G11;
-    }
-  }
-  alpha[2 * c] = a0;
-  alpha[2 * c + 1] = a1;
+  dev::recomb_alpha(norm, th, tot, &alpha[2 * c], &alpha[2 * c + 1]);
 }
 template <class T>
 __global__ void k_colupdate(int n, int k, int th, const double* __restrict__ alpha, const T* __restrict__ X0,
@@ -431,10 +409,12 @@ void recombine_mv(hipStream_t s, Hierarchy* H, const Level& L, Vecs<T>& v, int t
   residual_mv<T>(s, L, k, v.b, v.x, v.r);
   const int rows = red_rows(W, n);
   const int stride = k * W.rows;
-  hipLaunchKernelGGL(k_coldots<T>, gridn((int64_t)k * rows), dim3(MVT), 0, s, n, k, rows, stride, th,
-                     (const T*)v.r, (const T*)v.R[0], (const T*)v.R[1], W.part);
+  const int norm = H->o.recomb_norm;
+  hipLaunchKernelGGL(k_coldots<T>, gridn((int64_t)k * rows), dim3(MVT), 0, s, n, k, rows, stride, th, norm,
+                     (const T*)v.r, (const T*)v.R[0], (const T*)v.R[1], (const T*)v.x, (const T*)v.X[0],
+                     (const T*)v.X[1], W.part);
   double* alpha = W.res + RS_ALPHA * k;
-  hipLaunchKernelGGL(k_colalpha, dim3(k), dim3(MVT), 0, s, k, rows, stride, th, (const double*)W.part, alpha);
+  hipLaunchKernelGGL(k_colalpha, dim3(k), dim3(MVT), 0, s, k, rows, stride, th, norm, (const double*)W.part, alpha);
   hipLaunchKernelGGL(k_colupdate<T>, gridn((int64_t)n * k), dim3(MVT), 0, s, n, k, th, (const double*)alpha,
                      (const T*)v.X[0], (const T*)v.X[1], v.x);
   LAMG_HIP(hipGetLastError());

@@ -434,12 +434,24 @@ __global__ void k_fill(T* p, T v, int n) {
 static inline dim3 g1(int n, int b = 256) { return dim3((unsigned)std::max(1, (n + b - 1) / b)); }
 
 template <class T>
-void restrict_agg(hipStream_t s, const Level& C, const T* r, T* bc, T mu) {
+void restrict_agg(hipStream_t s, const Level& C, int nfine, const T* r, T* bc, T mu) {
+  const int kid = sizeof(T) == 8 ? 10 : 11;
+  const int64_t sx = sizeof(T);
+  prof_begin(s, kid);
+  // members' indices and residuals, aggregate pointers and coarse values
+  if (prof_on()) prof_count(kid, (int64_t)nfine * (sx + 4) + (int64_t)C.n * (sx + 4));
   hipLaunchKernelGGL(k_restrict_agg<T>, g1(C.n), dim3(256), 0, s, C.n, C.agg_ptr, C.members, r, bc, mu);
+  prof_end(s);
 }
 template <class T>
 void interp_agg(hipStream_t s, const Level& C, int nfine, const T* e, T* x) {
+  const int kid = sizeof(T) == 8 ? 12 : 13;
+  const int64_t sx = sizeof(T);
+  prof_begin(s, kid);
+  // aggregate index, x read and written per fine node; coarse values
+  if (prof_on()) prof_count(kid, (int64_t)nfine * (4 + 2 * sx) + (int64_t)C.n * sx);
   hipLaunchKernelGGL(k_interp_agg<T>, g1(nfine), dim3(256), 0, s, nfine, C.agg, e, x);
+  prof_end(s);
 }
 // Elimination restriction on the precomputed C-side stencil, with the
 // relaxation kernel's tiling (hub rows of C nodes have many F neighbours).
@@ -461,7 +473,7 @@ void fill(hipStream_t s, T* p, T v, int n) {
   if (n > 0) hipLaunchKernelGGL(k_fill<T>, g1(n), dim3(256), 0, s, p, v, n);
 }
 #define INST(T)                                                                                         \
-  template void restrict_agg<T>(hipStream_t, const Level&, const T*, T*, T);                           \
+  template void restrict_agg<T>(hipStream_t, const Level&, int, const T*, T*, T);                      \
   template void interp_agg<T>(hipStream_t, const Level&, int, const T*, T*);                           \
   template void restrict_elim<T>(hipStream_t, const Level&, const T*, T*);                             \
   template void interp_elim<T>(hipStream_t, const Level&, const Level&, const T*, const T*, const T*, const T*, T*); \
@@ -495,23 +507,16 @@ __device__ inline void block_sum_store(double (&v)[NV], double* out) {
     for (int i = 0; i < NV; ++i) out[i] = sh[i][0];
 }
 
-// Recombination dot products with d_i = R_i - r: G00, G01, G11, g0, g1, r.r
+// Recombination sums of the chosen norm (dev::recomb_terms), six slots.
 template <class T>
-__global__ __launch_bounds__(k::RED_THREADS) void k_recomb_dots(int n, int th, const T* __restrict__ r,
+__global__ __launch_bounds__(k::RED_THREADS) void k_recomb_dots(int n, int th, int norm, const T* __restrict__ r,
                                                                 const T* __restrict__ R0, const T* __restrict__ R1,
-                                                                double* part) {
+                                                                const T* __restrict__ x, const T* __restrict__ X0,
+                                                                const T* __restrict__ X1, double* part) {
   double v[6] = {0, 0, 0, 0, 0, 0};
-  for (int u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += gridDim.x * blockDim.x) {
-    const double ru = (double)r[u];
-    const double d0 = (double)(R0[u] - r[u]);
-    const double d1 = th > 1 ? (double)(R1[u] - r[u]) : 0.0;
-    v[0] += d0 * d0;
-    v[1] += d0 * d1;
-    v[2] += d1 * d1;
-    v[3] += d0 * ru;
-    v[4] += d1 * ru;
-    v[5] += ru * ru;
-  }
+  for (int u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += gridDim.x * blockDim.x)
+    dev::recomb_terms<T>(norm, th, r[u], R0[u], th > 1 ? R1[u] : T(0), norm ? x[u] : T(0), norm ? X0[u] : T(0),
+                         norm && th > 1 ? X1[u] : T(0), v);
   block_sum_store<6>(v, part + blockIdx.x * NSLOT);
 }
 // Sum the block partials in a fixed order and solve the th x th normal
@@ -532,7 +537,7 @@ __device__ inline double finish_slot(int nblk, const double* part, int slot) {
   __syncthreads();
   return r;
 }
-__global__ __launch_bounds__(256) void k_recomb_alpha(int nblk, int th, const double* part, double* res) {
+__global__ __launch_bounds__(256) void k_recomb_alpha(int nblk, int th, int norm, const double* part, double* res) {
   __shared__ double tot[6];
   for (int q = 0; q < 6; ++q) {
     const double v = finish_slot(nblk, part, q);
@@ -540,24 +545,9 @@ __global__ __launch_bounds__(256) void k_recomb_alpha(int nblk, int th, const do
   }
   __syncthreads();
   if (threadIdx.x != 0) return;
-  const double G00 = tot[0], G01 = tot[1], G11 = tot[2], g0 = tot[3], g1 = tot[4], rr = tot[5];
-  const double tiny = 1e-28 * rr;
-  double a0 = 0, a1 = 0;
-  if (th == 1) {
-    if (G00 > tiny) a0 = -g0 / G00;
-  } else {
-    const double det = G00 * G11 - G01 * G01;
-    if (G00 > tiny && G11 > tiny && det > 1e-12 * G00 * G11) {
-      a0 = (-g0 * G11 + g1 * G01) / det;
-      a1 = (-g1 * G00 + g0 * G01) / det;
-    } else if (G00 >= G11) {
-      if (G00 > tiny) a0 = -g0 / G00;
-    } else {
-      if (G11 > tiny) a1 = -g1 / G11;
-    }
-  }
-  res[0] = a0;
-  res[1] = a1;
+  double t[6];
+  for (int q = 0; q < 6; ++q) t[q] = tot[q];
+  dev::recomb_alpha(norm, th, t, &res[0], &res[1]);
 }
 template <class T>
 __global__ void k_recomb_update(int n, int th, const double* __restrict__ res, const T* __restrict__ X0,
@@ -584,9 +574,11 @@ void recombine(hipStream_t s, Hierarchy* H, const Level& L, Vecs<T>& v, int th) 
   else { val = (const T*)L.val32; dg = (const T*)L.diag32; }
   residual<T>(s, L, val, dg, v.b, v.x, v.r);
   const int nb = red_grid(L.n);
-  hipLaunchKernelGGL(k_recomb_dots<T>, dim3(nb), dim3(k::RED_THREADS), 0, s, L.n, th, v.r, v.R[0], v.R[1],
+  const int norm = H->o.recomb_norm;
+  hipLaunchKernelGGL(k_recomb_dots<T>, dim3(nb), dim3(k::RED_THREADS), 0, s, L.n, th, norm, (const T*)v.r,
+                     (const T*)v.R[0], (const T*)v.R[1], (const T*)v.x, (const T*)v.X[0], (const T*)v.X[1],
                      red_part(H));
-  hipLaunchKernelGGL(k_recomb_alpha, dim3(1), dim3(256), 0, s, nb, th, red_part(H), red_res(H));
+  hipLaunchKernelGGL(k_recomb_alpha, dim3(1), dim3(256), 0, s, nb, th, norm, red_part(H), red_res(H));
   hipLaunchKernelGGL(k_recomb_update<T>, g1(L.n), dim3(256), 0, s, L.n, th, red_res(H), v.X[0], v.X[1], v.x);
   LAMG_HIP(hipGetLastError());
 }

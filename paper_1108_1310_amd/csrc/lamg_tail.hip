@@ -55,6 +55,7 @@ struct TailParams {
   int lds_bytes;  // dynamic LDS of the launch
   int res_bytes;  // of which at most this much holds LDS-resident levels
   int nlev;       // levels lc .. lc + nlev - 1 in the program
+  int rnorm;      // norm iterate recombination minimises (0 residual, 1 energy)
 };
 
 template <class T> struct TV;
@@ -558,33 +559,17 @@ __device__ __attribute__((always_inline)) inline void run_ops(const TailParams& 
         __syncthreads();
         auto R0 = C.v(L, TV<T>::R(L, 0));
         auto R1 = C.v(L, TV<T>::R(L, 1));
-        double v[6] = {0, 0, 0, 0, 0, 0};
-        for (int u = tid; u < L.n; u += TAIL_THREADS) {
-          const double ru = (double)r[u];
-          const double d0 = (double)(R0[u] - r[u]);
-          const double d1 = th > 1 ? (double)(R1[u] - r[u]) : 0.0;
-          v[0] += d0 * d0; v[1] += d0 * d1; v[2] += d1 * d1; v[3] += d0 * ru; v[4] += d1 * ru; v[5] += ru * ru;
-        }
-        block_sums<6>(v, sh);
-        const double G00 = v[0], G01 = v[1], G11 = v[2], g0 = v[3], g1 = v[4], rr = v[5];
-        const double tiny = 1e-28 * rr;
-        double a0 = 0, a1 = 0;
-        if (th == 1) {
-          if (G00 > tiny) a0 = -g0 / G00;
-        } else {
-          const double det = G00 * G11 - G01 * G01;
-          if (G00 > tiny && G11 > tiny && det > 1e-12 * G00 * G11) {
-            a0 = (-g0 * G11 + g1 * G01) / det;
-            a1 = (-g1 * G00 + g0 * G01) / det;
-          } else if (G00 >= G11) {
-            if (G00 > tiny) a0 = -g0 / G00;
-          } else {
-            if (G11 > tiny) a1 = -g1 / G11;
-          }
-        }
         auto x = C.v(L, TV<T>::x(L));
         auto X0 = C.v(L, TV<T>::X(L, 0));
         auto X1 = C.v(L, TV<T>::X(L, 1));
+        const int norm = PP.rnorm;
+        double v[6] = {0, 0, 0, 0, 0, 0};
+        for (int u = tid; u < L.n; u += TAIL_THREADS)
+          dev::recomb_terms<T>(norm, th, r[u], R0[u], th > 1 ? R1[u] : T(0), norm ? x[u] : T(0),
+                               norm ? X0[u] : T(0), norm && th > 1 ? X1[u] : T(0), v);
+        block_sums<6>(v, sh);
+        double a0 = 0, a1 = 0;
+        dev::recomb_alpha(norm, th, v, &a0, &a1);
         for (int u = tid; u < L.n; u += TAIL_THREADS) {
           const double xu = (double)x[u];
           double y = xu;
@@ -1072,13 +1057,18 @@ void launch_tail(Hierarchy* H, const void* levels, int kc) {
   P.lds_bytes = (int)lds;
   P.res_bytes = TAIL_RES;
   P.nlev = (int)H->lv.size() - H->tail_lc;
+  P.rnorm = H->o.recomb_norm;
   static bool attr_set = false;
   if (!attr_set) {
     LAMG_HIP(hipFuncSetAttribute((const void*)k_tail<T, MV>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     attr_set = true;
   }
+  const int kid = sizeof(T) == 8 ? 14 : 15;
+  if (!MV) prof_begin(H->s, kid);
+  if (!MV && prof_on()) prof_count(kid, 0);  // latency-bound: time and launches only
   hipLaunchKernelGGL((k_tail<T, MV>), dim3(MV ? kc : 1), dim3(TAIL_THREADS), lds, H->s, P,
                      (const int4*)(H->tail_prog + seg.x), seg.y);
+  if (!MV) prof_end(H->s);
   LAMG_HIP(hipGetLastError());
 }
 }  // namespace
@@ -1363,6 +1353,7 @@ lamg_status solve_graphs(int count, Hierarchy* const* hs, const double* const* B
     g.P.mu = H->o.mu;
     g.P.kc = 1;
     g.P.nlev = (int)H->lv.size();
+    g.P.rnorm = H->o.recomb_norm;
     g.prog = H->full_prog;
     g.nops = H->full_nops;
     g.n = H->lv[0].n;

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(HERE, "libpaper_lamg.so")
 OK, E_INVALID_ARG, E_BAD_WEIGHT, E_NOT_CONNECTED, E_NOT_CONVERGED, E_BREAKDOWN, E_OUT_OF_MEMORY, E_DEVICE = range(8)
 FP64, FP32_REFINE = 0, 1
 EC_RECOMBINE, EC_FLAT_MU = 0, 1
+RECOMB_RESIDUAL, RECOMB_ENERGY = 0, 1
 
 
 # Device allocator hooks of lamg_options (alloc(bytes, ctx) -> ptr, dealloc(ptr, ctx)).
@@ -38,7 +39,7 @@ class Options(C.Structure):
                 ("ec", C.c_int), ("precision", C.c_int), ("tol", C.c_double), ("max_cycles", C.c_int),
                 ("warm_start", C.c_int), ("seed", C.c_uint64), ("stream", C.c_void_p),
                 ("alloc", ALLOC_FN), ("dealloc", DEALLOC_FN), ("alloc_ctx", C.c_void_p),
-                ("allow_negative_weights", C.c_int)]
+                ("allow_negative_weights", C.c_int), ("recomb_norm", C.c_int)]
 
 
 class Info(C.Structure):
@@ -392,8 +393,10 @@ class LaplacianSolve(torch.autograd.Function):
     The hierarchy is built in forward and kept on the context.  The adjoint
     solve uses the energy correction `adjoint_ec` (default 1, the flat mu of
     eq. galerkin2): its right-hand side is typically smooth (a function of x
-    on a node subset), a regime in which residual-minimising recombination
-    can stall on large graphs while the flat correction converges.
+    on a node subset), a regime in which recombination in the printed
+    residual norm can stall on large graphs, and recombination in the energy
+    norm (recomb_norm=RECOMB_ENERGY) is unreliable near the rounding floor of
+    tight tolerances, while the flat correction converges.
     """
 
     @staticmethod
@@ -497,7 +500,8 @@ def colour(rp, ci, n, seed=0, level=0):
 
 KERNELS = {0: "gs_fp64", 1: "residual_fp64", 2: "gs_fp32", 3: "residual_fp32",
            4: "mv_gs_fp64", 5: "mv_residual_fp64", 6: "mv_gs_fp32", 7: "mv_residual_fp32",
-           8: "hub_sweep_fp64", 9: "hub_sweep_fp32"}
+           8: "hub_sweep_fp64", 9: "hub_sweep_fp32", 10: "restrict_agg_fp64", 11: "restrict_agg_fp32",
+           12: "interp_agg_fp64", 13: "interp_agg_fp32", 14: "tail_fp64", 15: "tail_fp32"}
 
 
 def prof_enable(on: bool = True):

@@ -168,6 +168,40 @@ def test_solve_matches_oracle(ora, lg, name, precision):
     assert np.linalg.norm(xg - xo) <= 1e-6 * np.linalg.norm(xo)
 
 
+@pytest.mark.parametrize("name", ["grid3d16", "rgg16k"])
+def test_energy_recombination_matches_oracle(ora, lg, name):
+    """Iterate recombination in the energy norm (recomb_norm = 1): one cycle
+    through the multi-launch path and through the single-workgroup tail
+    against the oracle's cycle, and solves in FP64, FP32 + refinement and the
+    persistent many-graph launch in the oracle's cycles."""
+    _print_case(f"energy recombination {name}")
+    n, eu, ev, w = graphs()[name]
+    Ho = ora.Hierarchy(n, eu, ev, w, recomb_norm=1)
+    b = W.rhs_normal(n, 1, 23)
+    xo = Ho.cycle(b, np.zeros(n))
+    tol = 1e-10 if name.startswith("grid3d") else 1e-12
+    for tail in (4096, 0):
+        Hg = lg.Hierarchy(n, eu, ev, w, recomb_norm=1, tail_max_n=tail)
+        xg = Hg.cycle(b, np.zeros(n)).cpu().numpy()
+        assert np.linalg.norm(xg - xo) <= tol * np.linalg.norm(xo), tail
+    Hg = lg.Hierarchy(n, eu, ev, w, recomb_norm=1)
+    for precision in (0, 1):
+        xs, io, _ = Ho.solve(b, precision=precision)
+        xg, ig = Hg.solve(torch.tensor(b, device="cuda"), precision=precision)
+        assert ig["status"] == 0 and io["status"] == 0
+        assert abs(ig["cycles"] - io["cycles"]) <= 1, (precision, ig["cycles"], io["cycles"])
+        assert np.linalg.norm(xg.cpu().numpy() - xs) <= 1e-6 * np.linalg.norm(xs)
+    # the same graph twice in one persistent launch (two handles), FP64
+    Hg.set_solve_options(precision=0)
+    H2 = lg.Hierarchy(n, eu, ev, w, recomb_norm=1)
+    X, infos, rc = lg.solve_batch([Hg, H2], [b, b])
+    assert rc == 0
+    xs, io, _ = Ho.solve(b)
+    for i in range(2):
+        assert abs(infos[i]["cycles"] - io["cycles"]) <= 1
+        assert np.linalg.norm(X[i].cpu().numpy() - xs) <= 1e-6 * np.linalg.norm(xs)
+
+
 def test_coarsest_solve_matches(ora, lg):
     _print_case("coarsest")
     n, eu, ev, w = graphs()["grid64"]

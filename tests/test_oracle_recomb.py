@@ -1,4 +1,6 @@
-"""Pins of the oracle's iterate recombination (Section 3.4.5, eq. recomb), of
+"""Pins of the oracle's iterate recombination (Section 3.4.5, eq. recomb) in
+both norms (the residual 2-norm printed there, the default, and the energy
+norm of the error, an option), of
 the cycle index and fractional visit schedule (Section 4.2, eq.
 cycle_index) against hand-evaluated values, and of the fixed row-sum order
 (a rounding choice only: the hierarchies and cycle counts do not depend on
@@ -34,12 +36,12 @@ def _case(ora, n=300, seed=3):
 
 @pytest.mark.parametrize("th", [1, 2])
 def test_recombination_is_the_least_squares_solution(ora, th):
-    """alpha minimises ||b - A(x + sum_i alpha_i (X_i - x))||_2: equal to
-    numpy's least-squares solution of [R_i - r] alpha = -r, and y is the
-    stated combination."""
+    """Residual norm (as printed): alpha minimises
+    ||b - A(x + sum_i alpha_i (X_i - x))||_2: equal to numpy's least-squares
+    solution of [R_i - r] alpha = -r, and y is the stated combination."""
     A, D, b, x, X0, X1 = _case(ora)
     Xs = np.stack([X0, X1][:th], axis=1)
-    y, alpha = ora.recombine(A, b, x, Xs)
+    y, alpha = ora.recombine(A, b, x, Xs, norm=0)
     r = b - D @ x
     M = np.stack([(b - D @ Xs[:, i]) - r for i in range(th)], axis=1)
     ref, *_ = np.linalg.lstsq(M, -r, rcond=None)
@@ -54,13 +56,39 @@ def test_recombination_is_the_least_squares_solution(ora, th):
 
 
 @pytest.mark.parametrize("th", [1, 2])
+def test_energy_recombination_minimises_the_error_energy(ora, th):
+    """Energy norm (the option): alpha minimises (y - x*)^T A (y - x*) over
+    the combinations, i.e. solves (D^T A D) alpha = D^T r with D = [X_i - x]
+    (numpy on the dense Laplacian); y has the smallest error energy of any
+    step along X_0 - x, and the error energy never exceeds that of x or of
+    any X_i."""
+    A, Dn, b, x, X0, X1 = _case(ora)
+    Xs = np.stack([X0, X1][:th], axis=1)
+    y, alpha = ora.recombine(A, b, x, Xs, norm=1)
+    Dm = Xs - x[:, None]
+    ref = np.linalg.solve(Dm.T @ Dn @ Dm, Dm.T @ (b - Dn @ x))
+    assert np.allclose(alpha, ref, rtol=1e-8, atol=1e-12), (alpha, ref)
+    assert np.allclose(y, x + Dm @ alpha, rtol=0, atol=1e-12 * np.abs(y).max())
+    xs = np.linalg.lstsq(Dn, b, rcond=None)[0]
+    err = lambda z: float((z - xs) @ Dn @ (z - xs))
+    ey = err(y)
+    for t in np.linspace(-2, 2, 9):
+        assert ey <= err(x + t * (Xs[:, 0] - x)) * (1 + 1e-9) + 1e-20
+    assert ey <= min([err(x)] + [err(Xs[:, i]) for i in range(th)]) * (1 + 1e-9)
+    # the residual-norm choice generally differs
+    _, a0 = ora.recombine(A, b, x, Xs, norm=0)
+    assert not np.allclose(a0, alpha)
+
+
+@pytest.mark.parametrize("th", [1, 2])
 def test_recombination_never_increases_the_residual(ora, th):
     """alpha = 0 (keep x) and alpha = e_i (take X_i) are feasible, so the
-    recombined residual is at most the smallest of those residuals."""
+    recombined residual (residual norm) is at most the smallest of those
+    residuals."""
     for seed in range(5):
         A, D, b, x, X0, X1 = _case(ora, 200, 10 + seed)
         Xs = np.stack([X0, X1][:th], axis=1)
-        y, _ = ora.recombine(A, b, x, Xs)
+        y, _ = ora.recombine(A, b, x, Xs, norm=0)
         ry = np.linalg.norm(b - D @ y)
         bound = min([np.linalg.norm(b - D @ x)] + [np.linalg.norm(b - D @ Xs[:, i]) for i in range(th)])
         assert ry <= bound * (1 + 1e-12), (seed, ry, bound)
@@ -71,12 +99,13 @@ def test_recombination_degenerate_directions(ora):
     (a zero direction): the dropped direction gets alpha = 0 and the
     residual still does not increase."""
     A, D, b, x, X0, X1 = _case(ora)
-    y, alpha = ora.recombine(A, b, x, np.stack([X0, X0], axis=1))
-    assert alpha[1] == 0.0 and alpha[0] != 0.0
-    r1, _ = ora.recombine(A, b, x, X0[:, None])
-    assert np.allclose(y, r1, rtol=0, atol=1e-13 * np.abs(y).max())
-    y, alpha = ora.recombine(A, b, x, x[:, None].copy())
-    assert alpha[0] == 0.0 and np.array_equal(y, x)
+    for norm in (0, 1):
+        y, alpha = ora.recombine(A, b, x, np.stack([X0, X0], axis=1), norm=norm)
+        assert alpha[1] == 0.0 and alpha[0] != 0.0
+        r1, _ = ora.recombine(A, b, x, X0[:, None], norm=norm)
+        assert np.allclose(y, r1, rtol=0, atol=1e-13 * np.abs(y).max())
+        y, alpha = ora.recombine(A, b, x, x[:, None].copy(), norm=norm)
+        assert alpha[0] == 0.0 and np.array_equal(y, x)
 
 
 def test_cycle_index_against_hand_values(ora):
