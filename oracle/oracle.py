@@ -13,19 +13,26 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "lamg_oracle.cpp")
-LIB = os.path.join(HERE, "liblamg_oracle.so")
+SAN_LIB = os.path.join(HERE, "liblamg_oracle_san.so")
+LIB = os.environ.get("LAMG_ORACLE_LIB") or os.path.join(HERE, "liblamg_oracle.so")
 
 L_FINEST, L_ELIM, L_AGG = 0, 1, 2
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle (serial, no FMA contraction, no fast-math)."""
-    if force or not os.path.exists(LIB):
-        tmp = LIB + ".tmp"
-        subprocess.check_call(["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math",
+def build(force: bool = True, sanitize: bool = False) -> str:
+    """Compile the oracle (serial, no FMA contraction, no fast-math).  With
+    sanitize, an AddressSanitizer + UndefinedBehaviorSanitizer build into its
+    own library (loaded by setting LAMG_ORACLE_LIB and preloading the ASan
+    runtime; tests/test_oracle_sanitize.py)."""
+    out = SAN_LIB if sanitize else LIB
+    if force or not os.path.exists(out):
+        tmp = out + ".tmp"
+        extra = (["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer", "-g"]
+                 if sanitize else [])
+        subprocess.check_call(["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math", *extra,
                                "-shared", "-fPIC", "-o", tmp, SRC])
-        os.replace(tmp, LIB)
-    return LIB
+        os.replace(tmp, out)
+    return out
 
 
 class Opts(C.Structure):

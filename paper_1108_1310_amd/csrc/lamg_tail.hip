@@ -241,13 +241,15 @@ __device__ __attribute__((always_inline)) inline void tail_gs_lds(const TailLeve
 // Sweeps of a small level (n <= R * TAIL_THREADS rows): thread t owns rows
 // t, t + TAIL_THREADS, ... for the whole op.  Each row's colour, first RMAX
 // weights and column indices, b and diagonal stay in registers and x lives
-// in LDS, so a colour phase is one round of LDS gathers before the barrier.
-// The sums run left to right as in every other relaxation path; entries past
-// RMAX come from global memory, long rows (> 64) from the wavefront path.
+// in LDS (with the colours' long-row bounds), so a colour phase is one round
+// of LDS gathers before the barrier.  The sums run left to right as in every
+// other relaxation path; entries past RMAX come from the level's arrays,
+// long rows (> 64) from the wavefront path.
 template <class T, bool MV, int R>
 __device__ __attribute__((always_inline)) inline void tail_gs_small(const TailLevel& L, ColOf<MV> C, char* lds,
                                                                     int sweeps) {
-  constexpr int RMAX = 8;
+  // entries held in registers per row: 16 for one row per thread, 8 for two
+  constexpr int RMAX = R == 1 ? 16 : 8;
   auto x = C.v(L, TV<T>::x(L));
   auto b = C.v(L, TV<T>::b(L));
   const T* dg = TV<T>::diag(L);
@@ -255,6 +257,10 @@ __device__ __attribute__((always_inline)) inline void tail_gs_small(const TailLe
   const int n = L.n, nc = L.ncol;
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
   LP<T> sx = (LP<T>)lds;
+  // the colours' long-row bounds, read every phase, staged beside x (the
+  // level's own list may sit in global memory)
+  LP<int> slp = (LP<int>)(sx + n);
+  for (int c = tid; c <= nc; c += TAIL_THREADS) slp[c] = L.lptr[c];
   int col[R], p0[R], len[R], cj[R][RMAX];
   T bu[R], du[R], wj[R][RMAX];
 #pragma unroll
@@ -298,7 +304,7 @@ __device__ __attribute__((always_inline)) inline void tail_gs_small(const TailLe
         for (int t = RMAX; t < len[k]; ++t) s += val[p0[k] + t] * sx[L.ci[p0[k] + t]];
         sx[tid + k * TAIL_THREADS] = (bu[k] + s) / du[k];
       }
-      for (int k = L.lptr[c] + wv; k < L.lptr[c + 1]; k += TAIL_WAVES) {
+      for (int k = slp[c] + wv; k < slp[c + 1]; k += TAIL_WAVES) {
         const int u = L.lrows[k];
         const int q0 = L.rp[u], ln = L.rp[u + 1] - q0;
         const T s = dev::row_sum_wave<T>(ln, lane, [&](int t) { return val[q0 + t] * sx[L.ci[q0 + t]]; });
@@ -316,9 +322,10 @@ __device__ __attribute__((always_inline)) inline void tail_gs_small(const TailLe
 template <class T, bool MV>
 __device__ __attribute__((always_inline)) inline void tail_sweeps(const TailLevel& L, ColOf<MV> C, char* lds,
                                                                   int budget, int sweeps) {
-  if (L.n <= TAIL_THREADS && (size_t)L.n * sizeof(T) <= (size_t)budget) {
+  const size_t small = (size_t)L.n * sizeof(T) + (size_t)(L.ncol + 1) * sizeof(int);
+  if (L.n <= TAIL_THREADS && small <= (size_t)budget) {
     tail_gs_small<T, MV, 1>(L, C, lds, sweeps);
-  } else if (L.n <= 2 * TAIL_THREADS && (size_t)L.n * sizeof(T) <= (size_t)budget) {
+  } else if (L.n <= 2 * TAIL_THREADS && small <= (size_t)budget) {
     tail_gs_small<T, MV, 2>(L, C, lds, sweeps);
   } else if (tail_fits<T>(L, budget)) {
     tail_gs_lds<T, MV>(L, C, lds, budget, sweeps);

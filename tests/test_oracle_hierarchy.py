@@ -5,6 +5,7 @@ import numpy as np
 import pytest
 
 from test_oracle_pins import random_graph
+from paper_1108_1310_amd import workloads as W
 
 SMALL = dict(coarsest_max_n=8)  # force several levels on tiny graphs
 NOFAST = dict(relax_fast_ratio=-1.0)  # keep coarsening even where relaxation is fast
@@ -307,3 +308,24 @@ def test_relaxation_fast_stops_coarsening(ora):
     assert not G.coarsest_relax and G.num_levels > 3
     for l in agg_levels(G):
         assert G.agg_diag(l)["rate"] > 0.3
+
+
+def _colouring_proper(ptr, col, cptr):
+    """Every edge joins two colour classes (class c = rows cptr[c]..cptr[c+1])."""
+    n = len(ptr) - 1
+    colour = np.repeat(np.arange(len(cptr) - 1), np.diff(cptr))
+    rows = np.repeat(np.arange(n), np.diff(ptr))
+    return len(colour) == n and not np.any(colour[rows] == colour[col])
+
+
+@pytest.mark.parametrize("name", ["grid2d_48", "rgg_2p12", "chung_lu_2p12", "grid3d_aniso_12", "er_3000"])
+def test_every_level_colouring_is_proper(ora, name):
+    """Each level's multicolour order is a proper colouring (no edge inside a
+    colour class), so a colour class can be relaxed simultaneously."""
+    g = {"grid2d_48": lambda: W.grid2d(48), "rgg_2p12": lambda: W.rgg(1 << 12),
+         "chung_lu_2p12": lambda: W.chung_lu(1 << 12), "grid3d_aniso_12": lambda: W.grid3d_aniso(12),
+         "er_3000": lambda: W.erdos_renyi(3000, 8.0, 4)}[name]()
+    H = ora.Hierarchy(g.n, g.eu, g.ev, g.w)
+    for l in range(H.num_levels):
+        L = H.level(l)
+        assert _colouring_proper(L.A.ptr, L.A.col, L.cptr), (name, l)
