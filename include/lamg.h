@@ -185,7 +185,7 @@ lamg_status lamg_solve_batch(int32_t count, const lamg_handle* hs, const int32_t
  * harnesses that forbid hipMalloc.  The launch's own buffers (the graphs'
  * descriptors, the queue orders and counter, the per-graph results) live in a
  * static device array of the library, one copy per GPU held until the
- * process ends, of LAMG_NOALLOC_MAX_GRAPHS graphs at most (about 1.3 MB);
+ * process ends, of LAMG_NOALLOC_MAX_GRAPHS graphs at most (about 2.4 MB);
  * the call allocates no device or pinned host memory and does not autotune
  * (it launches the configuration lamg_solve_batch tuned for the same batch
  * shape, else the first one; results do not depend on it).

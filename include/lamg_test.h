@@ -69,11 +69,15 @@ lamg_status lamg_t_mv_cycle(lamg_handle h, int32_t k, const double* b_perm, doub
 lamg_status lamg_t_mv_columns(lamg_handle h, int32_t k, int32_t* cycles, double* rel, double* removed_mean);
 
 /* Launch configuration of the persistent many-graph solve (lamg_solve_batch
- * with count > 1): config in [0, 4) forces that configuration (LDS staging
- * budget 128/64 KB, 1 or 2 workgroups per compute unit, largest-work-first or
- * input queue order); -1 restores the autotuner, which times every
- * configuration on the first batch of each shape and keeps the fastest.
- * Process-wide; not thread-safe.  LAMG_E_INVALID_ARG outside [-1, 4). */
+ * with count > 1): config in [0, LAMG_T_BATCH_CONFIGS) forces that
+ * configuration (LDS staging budget 64 / 96 / 128 / 152 KB, 1 or 2 workgroups
+ * per compute unit, largest-work-first or input queue order); -1 restores the
+ * autotuner, which times every configuration on the first batch of each shape
+ * (every graph capped at two cycles) and keeps the fastest, also in the file
+ * named by the environment variable LAMG_TUNE_CACHE when set (read before
+ * the first tuning of a process, appended after each).  Process-wide; not
+ * thread-safe.  LAMG_E_INVALID_ARG outside [-1, LAMG_T_BATCH_CONFIGS). */
+#define LAMG_T_BATCH_CONFIGS 10
 lamg_status lamg_t_batch_config(int32_t config);
 
 /* Coarsest-level solve x = (A_L + (mean diag / n_L) 1 1^T)^-1 b, DEVICE [n_L]

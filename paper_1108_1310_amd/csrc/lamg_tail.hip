@@ -11,6 +11,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -1177,7 +1179,7 @@ __device__ inline double wg_sum(int n, double (*sh)[TAIL_WAVES], F f) {
 }
 
 __device__ __attribute__((always_inline)) inline void solve_graph(const BatchGraph& g, BatchOut* out, char* lds,
-                                                                  double (*sh)[TAIL_WAVES]) {
+                                                                  double (*sh)[TAIL_WAVES], int cap) {
   const int tid = threadIdx.x, n = g.n;
   const TailLevel& L0 = g.P.L[0];
   double* b64 = L0.b64;
@@ -1197,7 +1199,8 @@ __device__ __attribute__((always_inline)) inline void solve_graph(const BatchGra
   double rk = r0;
   int it = 0;
   if (nb > 0) {
-    while (rk > g.tol * nb && it < g.max_cycles && isfinite(rk)) {
+    const int maxc = g.max_cycles < cap ? g.max_cycles : cap;
+    while (rk > g.tol * nb && it < maxc && isfinite(rk)) {
       if (!g.fp32) {
         run_cycle<double>(g.P, g.prog, g.nops, lds, sh);
       } else {
@@ -1237,7 +1240,7 @@ __device__ __attribute__((always_inline)) inline void solve_graph(const BatchGra
 }
 
 __global__ __launch_bounds__(TAIL_THREADS) void k_batch(const BatchGraph* __restrict__ G, const int* __restrict__ order,
-                                                        int count, int* queue, BatchOut* out) {
+                                                        int count, int* queue, BatchOut* out, int cap) {
   __shared__ double sh[6][TAIL_WAVES];
   __shared__ int slot;
   extern __shared__ double lds_d[];
@@ -1248,7 +1251,7 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_batch(const BatchGraph* __rest
     __syncthreads();
     if (q >= count) break;  // every workgroup leaves once the queue is drained
     const int gi = order[q];
-    solve_graph(G[gi], out + gi, (char*)lds_d, sh);
+    solve_graph(G[gi], out + gi, (char*)lds_d, sh, cap);
   }
 }
 
@@ -1258,9 +1261,23 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_batch(const BatchGraph* __rest
 struct BatchConfig {
   int lds, per_cu, lpt;
 };
-constexpr int kBatchLds[2] = {128 * 1024, 64 * 1024};  // the two LDS budgets (one descriptor copy each)
-constexpr BatchConfig kBatchConfigs[] = {{128 * 1024, 1, 1}, {64 * 1024, 2, 1}, {64 * 1024, 1, 1}, {128 * 1024, 1, 0}};
+// the LDS budgets (one copy of the graphs' descriptors each); two workgroups
+// fit a compute unit's 160 KB only with the smallest
+constexpr int kNumBatchLds = 4;
+constexpr int kBatchLds[kNumBatchLds] = {128 * 1024, 64 * 1024, 96 * 1024, 152 * 1024};
+constexpr BatchConfig kBatchConfigs[] = {
+    {128 * 1024, 1, 1}, {64 * 1024, 2, 1}, {64 * 1024, 1, 1}, {128 * 1024, 1, 0}, {96 * 1024, 1, 1},
+    {152 * 1024, 1, 1}, {64 * 1024, 2, 0}, {96 * 1024, 1, 0}, {152 * 1024, 1, 0}, {64 * 1024, 1, 0}};
 constexpr int kNumBatchConfigs = sizeof(kBatchConfigs) / sizeof(kBatchConfigs[0]);
+constexpr int kBatchMaxLds = 152 * 1024;
+// tuning runs cap every graph at this many cycles: the ranking of the
+// configurations is that of the per-cycle work, at a fraction of a solve
+constexpr int kTuneCycles = 2;
+int lds_slot(int lds) {
+  for (int v = 0; v < kNumBatchLds; ++v)
+    if (kBatchLds[v] == lds) return v;
+  return 0;
+}
 
 struct TunerEntry {
   uint64_t key;
@@ -1268,6 +1285,34 @@ struct TunerEntry {
 };
 std::vector<TunerEntry> g_tuned;  // best configuration per batch signature (process lifetime)
 int g_batch_forced = -1;          // test hook: force a configuration
+bool g_cache_loaded = false;
+
+// Persisted choices: with LAMG_TUNE_CACHE set to a file, every tuned batch
+// signature is appended to it as "<key hex> <config>" and a later process
+// reads the file before its first tuning (entries with a configuration index
+// outside the table are ignored).  The key covers the device (name and
+// compute units) and the batch's shape.
+void tune_cache_load() {
+  if (g_cache_loaded) return;
+  g_cache_loaded = true;
+  const char* path = std::getenv("LAMG_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  unsigned long long k = 0;
+  int c = 0;
+  while (std::fscanf(f, "%llx %d", &k, &c) == 2)
+    if (c >= 0 && c < kNumBatchConfigs) g_tuned.push_back({(uint64_t)k, c});
+  std::fclose(f);
+}
+void tune_cache_store(uint64_t key, int best) {
+  const char* path = std::getenv("LAMG_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "%016llx %d\n", (unsigned long long)key, best);
+  std::fclose(f);
+}
 
 }  // namespace
 
@@ -1295,7 +1340,7 @@ namespace {
 // Device block of one persistent launch: the graphs' descriptors (one copy
 // per LDS budget), the two queue orders, the queue counter and the results.
 constexpr size_t batch_buffer_bytes(size_t count) {
-  return 2 * count * sizeof(BatchGraph) + 2 * count * sizeof(int) + 256 + count * sizeof(BatchOut);
+  return 4 * count * sizeof(BatchGraph) + 2 * count * sizeof(int) + 256 + count * sizeof(BatchOut);
 }
 
 // Scratch of the allocation-free entry (lamg_solve_batch_noalloc): the block
@@ -1345,8 +1390,9 @@ lamg_status solve_graphs(int count, Hierarchy* const* hs, const double* const* B
     if (noalloc && (!H->full_prog || !H->full_levels)) return LAMG_E_INVALID_ARG;  // (prepared at setup)
     batch_prepare(H);
     if (!H->full_checked) {
-      check_or_throw(program_check(H, H->full_host, H->full_prog_host, 0,
-                                   {make_int2(kBatchLds[0], kBatchLds[0] / 2), make_int2(kBatchLds[1], kBatchLds[1] / 2)}));
+      std::vector<int2> budgets;
+      for (int v = 0; v < kNumBatchLds; ++v) budgets.push_back(make_int2(kBatchLds[v], kBatchLds[v] / 2));
+      check_or_throw(program_check(H, H->full_host, H->full_prog_host, 0, budgets));
       H->full_checked = true;
     }
     BatchGraph& g = G[i];
@@ -1386,9 +1432,19 @@ lamg_status solve_graphs(int count, Hierarchy* const* hs, const double* const* B
   int dev = 0, ncu = 0;
   LAMG_HIP(hipGetDevice(&dev));
   LAMG_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  {
+    hipDeviceProp_t prop;
+    LAMG_HIP(hipGetDeviceProperties(&prop, dev));
+    for (const char* c = prop.gcnArchName; *c; ++c) {
+      key ^= (uint64_t)(unsigned char)*c;
+      key *= 1099511628211ULL;
+    }
+    key ^= (uint64_t)ncu;
+    key *= 1099511628211ULL;
+  }
   static bool attr = false;
   if (!attr) {
-    LAMG_HIP(hipFuncSetAttribute((const void*)k_batch, hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024));
+    LAMG_HIP(hipFuncSetAttribute((const void*)k_batch, hipFuncAttributeMaxDynamicSharedMemorySize, kBatchMaxLds));
     attr = true;
   }
   // device copies: graphs (one copy per LDS budget), orders, queue, results;
@@ -1405,11 +1461,13 @@ lamg_status solve_graphs(int count, Hierarchy* const* hs, const double* const* B
       if (p) dev_free(o, p);
     }
   } guard{ao, noalloc ? nullptr : buf};
-  BatchGraph* dG[2] = {(BatchGraph*)buf, (BatchGraph*)(buf + gb)};
-  int* dorder[2] = {(int*)(buf + 2 * gb), (int*)(buf + 2 * gb) + count};
-  int* queue = (int*)(buf + 2 * gb + 2 * (size_t)count * sizeof(int));
-  BatchOut* dout = (BatchOut*)(buf + 2 * gb + 2 * (size_t)count * sizeof(int) + 256);
-  for (int v = 0; v < 2; ++v) {
+  static_assert(kNumBatchLds == 4, "batch_buffer_bytes holds one descriptor copy per LDS budget");
+  BatchGraph* dG[kNumBatchLds];
+  for (int v = 0; v < kNumBatchLds; ++v) dG[v] = (BatchGraph*)(buf + v * gb);
+  int* dorder[2] = {(int*)(buf + kNumBatchLds * gb), (int*)(buf + kNumBatchLds * gb) + count};
+  int* queue = (int*)(buf + kNumBatchLds * gb + 2 * (size_t)count * sizeof(int));
+  BatchOut* dout = (BatchOut*)(buf + kNumBatchLds * gb + 2 * (size_t)count * sizeof(int) + 256);
+  for (int v = 0; v < kNumBatchLds; ++v) {
     const int lds = kBatchLds[v];
     for (BatchGraph& g : G) {
       g.P.lds_bytes = lds;
@@ -1420,31 +1478,33 @@ lamg_status solve_graphs(int count, Hierarchy* const* hs, const double* const* B
   }
   LAMG_HIP(hipMemcpyAsync(dorder[0], natural.data(), count * sizeof(int), hipMemcpyHostToDevice, s));
   LAMG_HIP(hipMemcpyAsync(dorder[1], lpt.data(), count * sizeof(int), hipMemcpyHostToDevice, s));
-  auto launch = [&](int c) {
+  auto launch = [&](int c, int cap) {
     const BatchConfig& cf = kBatchConfigs[c];
     fill<int>(s, queue, 0, 1);
     const int grid = std::max(1, std::min(count, ncu * cf.per_cu));
-    hipLaunchKernelGGL(k_batch, dim3(grid), dim3(TAIL_THREADS), cf.lds, s, (const BatchGraph*)dG[cf.lds == 128 * 1024 ? 0 : 1],
-                       (const int*)dorder[cf.lpt], count, queue, dout);
+    hipLaunchKernelGGL(k_batch, dim3(grid), dim3(TAIL_THREADS), cf.lds, s, (const BatchGraph*)dG[lds_slot(cf.lds)],
+                       (const int*)dorder[cf.lpt], count, queue, dout, cap);
     LAMG_HIP(hipGetLastError());
   };
   int best = 0;
   if (g_batch_forced >= 0) {
     best = g_batch_forced;
   } else {
+    if (!noalloc) tune_cache_load();
     bool found = false;
     for (const TunerEntry& e : g_tuned)
       if (e.key == key) { best = e.best; found = true; }
     if (!found && !warm && !noalloc) {
-      // time every configuration once on this batch (each run is a full,
-      // identical solve) and keep the fastest for this batch signature
+      // time every configuration on this batch, each graph capped at
+      // kTuneCycles cycles (the same ops per cycle as the real solve), and
+      // keep the fastest for this batch signature
       hipEvent_t a, b;
       LAMG_HIP(hipEventCreate(&a));
       LAMG_HIP(hipEventCreate(&b));
       float bestms = 0;
       for (int c = 0; c < kNumBatchConfigs; ++c) {
         LAMG_HIP(hipEventRecord(a, s));
-        launch(c);
+        launch(c, kTuneCycles);
         LAMG_HIP(hipEventRecord(b, s));
         LAMG_HIP(hipEventSynchronize(b));
         float ms = 0;
@@ -1454,9 +1514,10 @@ lamg_status solve_graphs(int count, Hierarchy* const* hs, const double* const* B
       (void)hipEventDestroy(a);
       (void)hipEventDestroy(b);
       g_tuned.push_back({key, best});
+      tune_cache_store(key, best);
     }
   }
-  launch(best);
+  launch(best, 1 << 30);
   std::vector<BatchOut> out(count);
   LAMG_HIP(hipMemcpyAsync(out.data(), dout, count * sizeof(BatchOut), hipMemcpyDeviceToHost, s));
   LAMG_HIP(hipStreamSynchronize(s));

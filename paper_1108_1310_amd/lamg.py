@@ -449,6 +449,7 @@ def solve_batch(hs: list[Hierarchy], Bs: list, Xs: list | None = None):
 
 
 NOALLOC_MAX_GRAPHS = 4096  # LAMG_NOALLOC_MAX_GRAPHS
+BATCH_CONFIGS = 10  # LAMG_T_BATCH_CONFIGS
 
 
 def solve_batch_noalloc(hs: list[Hierarchy], Bs: list, Xs: list | None = None):

@@ -62,5 +62,7 @@ def test_host_only_entry_points():
     assert h.value is None
     L.lamg_free(None)  # no-op
     # batch launch configuration: only -1 (autotune) and 0..3
-    assert L.lamg_t_batch_config(4) == lamg.E_INVALID_ARG and L.lamg_t_batch_config(-2) == lamg.E_INVALID_ARG
+    assert L.lamg_t_batch_config(lamg.BATCH_CONFIGS) == lamg.E_INVALID_ARG
+    assert L.lamg_t_batch_config(-2) == lamg.E_INVALID_ARG
+    assert L.lamg_t_batch_config(lamg.BATCH_CONFIGS - 1) == 0
     assert L.lamg_t_batch_config(-1) == 0

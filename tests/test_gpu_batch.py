@@ -75,7 +75,7 @@ def test_batch_configs_identical(lg):
     hs = [_hier(lg, g) for g in gs]
     ref = None
     try:
-        for c in range(4):
+        for c in range(lg.BATCH_CONFIGS):
             assert lib().lamg_t_batch_config(c) == 0
             X, infos, rc = lg.solve_batch(hs, bs)
             assert rc == 0
@@ -151,3 +151,37 @@ def test_batch_rejects_duplicate_handles(lg):
     bp = (C.c_void_p * 2)(b.data_ptr(), b.data_ptr())
     xp = (C.c_void_p * 2)(x.data_ptr(), x.data_ptr())
     assert lib().lamg_solve_batch(2, hp, (C.c_int32 * 2)(1, 1), bp, xp, (Info * 2)()) == 1
+
+
+def test_tune_cache_persists(tmp_path):
+    """The tuner's choice for a batch shape is written to LAMG_TUNE_CACHE and
+    read back by a later process, which then does not tune again (the file
+    gains no line); both processes return the same solutions."""
+    import os
+    import subprocess
+    import sys
+    print("[case] batch tune cache", flush=True)
+    cache = tmp_path / "tune.txt"
+    out = [tmp_path / "x0.npy", tmp_path / "x1.npy"]
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = (
+        "import sys, numpy as np, torch\n"
+        f"sys.path.insert(0, {root!r})\n"
+        "from paper_1108_1310_amd import lamg, workloads as W\n"
+        "gs = W.graph_batch(6, 500, 5000, 53)\n"
+        "hs = [lamg.Hierarchy(g.n, g.eu, g.ev, g.w) for g in gs]\n"
+        "bs = [W.rhs_normal(g.n, 1, 60 + i) for i, g in enumerate(gs)]\n"
+        "X, infos, rc = lamg.solve_batch(hs, bs)\n"
+        "assert rc == 0\n"
+        "np.save(sys.argv[1], np.concatenate([x.cpu().numpy() for x in X]))\n")
+    env = dict(os.environ, LAMG_TUNE_CACHE=str(cache))
+    for i in range(2):
+        r = subprocess.run([sys.executable, "-c", code, str(out[i])], env=env, capture_output=True, text=True,
+                           timeout=240)
+        assert r.returncode == 0, r.stderr[-3000:]
+        lines = cache.read_text().split("\n")
+        lines = [l for l in lines if l.strip()]
+        assert len(lines) == 1, lines  # tuned once, reused by the second process
+        key, cfg = lines[0].split()
+        assert 0 <= int(cfg) < 10 and len(key) == 16
+    assert np.array_equal(np.load(out[0]), np.load(out[1]))
