@@ -25,12 +25,24 @@ namespace lamg {
 
 namespace {
 
-// One workgroup size for every kernel of this file (k_tail, k_batch): the
-// wavefront-sum scratch sh[..][TAIL_WAVES] and every stride assume it, so a
-// launch of any other size would write past that scratch.
+// The largest workgroup of the kernels of this file (k_batch launches it):
+// it sizes the wavefront-sum scratch sh[..][TAIL_WAVES] and the launch
+// bounds.  A launch larger than this would write past that scratch.
 constexpr int TAIL_THREADS = 1024;
 constexpr int TAIL_WAVES = TAIL_THREADS / 64;
 static_assert(TAIL_WAVES * 64 == TAIL_THREADS, "whole wavefronts");
+// Launch size of the single-workgroup tail (k_tail).  Measured on one box
+// against 512 threads (whose barriers span half the wavefronts but whose
+// register-resident sweeps cover only levels of up to 1,024 rows): RGG 2^20
+// 191.6 / 196.3 ms per solve, 64^2 grid 6.06 / 5.74 ms, 64^3 anisotropic
+// grid 596 / 594 ms, geometric multigrid 1024^2 9.14 / 9.19 ms.
+constexpr int TAIL_LAUNCH = 1024;
+static_assert(TAIL_LAUNCH % 64 == 0 && TAIL_LAUNCH <= TAIL_THREADS, "whole wavefronts within the scratch");
+// Every stride and wavefront count of the interpreter comes from the
+// launch; TAIL_THREADS / TAIL_WAVES only bound it (launch bounds, the size
+// of the wavefront-sum scratch).
+__device__ __attribute__((always_inline)) inline int tail_nt() { return (int)blockDim.x; }
+__device__ __attribute__((always_inline)) inline int tail_nw() { return (int)(blockDim.x >> 6); }
 
 enum TailOp {
   OP_GS = 1,      // a = multicolour sweeps of level l (one staging for all)
@@ -156,9 +168,9 @@ __device__ __attribute__((always_inline)) inline void tail_gs(const TailLevel& L
   const T* dg = TV<T>::diag(L);
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
   for (int c = 0; c < L.ncol; ++c) {
-    for (int u = L.cptr[c] + tid; u < L.cptr[c + 1]; u += TAIL_THREADS)
+    for (int u = L.cptr[c] + tid; u < L.cptr[c + 1]; u += tail_nt())
       if (L.rp[u + 1] - L.rp[u] <= SHORT_ROW) x[u] = (b[u] + row_short<T>(L, u, x)) / dg[u];
-    for (int k = L.lptr[c] + wv; k < L.lptr[c + 1]; k += TAIL_WAVES) {
+    for (int k = L.lptr[c] + wv; k < L.lptr[c + 1]; k += tail_nw()) {
       const int u = L.lrows[k];
       const T s = row_long<T>(L, u, x, lane);
       if (lane == 0) x[u] = (b[u] + s) / dg[u];
@@ -195,12 +207,12 @@ __device__ __attribute__((always_inline)) inline void lds_sweeps(const TailLevel
   for (int sw = 0; sw < sweeps; ++sw)
     for (int c = 0; c < nc; ++c) {
       const int c1 = scp[c + 1];
-      for (int u = scp[c] + tid; u < c1; u += TAIL_THREADS) {
+      for (int u = scp[c] + tid; u < c1; u += tail_nt()) {
         const int p0 = srp[u], len = srp[u + 1] - p0;
         if (len > SHORT_ROW) continue;
         sx[u] = (sbv[u] + row_seq_p<T>(val, ci, p0, len, sx)) / sd[u];
       }
-      for (int k = slp[c] + wv; k < slp[c + 1]; k += TAIL_WAVES) {
+      for (int k = slp[c] + wv; k < slp[c + 1]; k += tail_nw()) {
         const int u = L.lrows[k];
         const int p0 = srp[u], len = srp[u + 1] - p0;
         const T s = dev::row_sum_wave<T>(len, lane, [&](int t) { return val[p0 + t] * sx[ci[p0 + t]]; });
@@ -228,20 +240,20 @@ __device__ __attribute__((always_inline)) inline void tail_gs_lds(const TailLeve
   LP<T> sval = (LP<T>)(size_t)((mend + 15u) & ~15u);
   LP<int> sci = (LP<int>)(sval + (all ? L.nnz : 0));
   const int tid = threadIdx.x;
-  for (int i = tid; i < n; i += TAIL_THREADS) { sx[i] = x[i]; sbv[i] = b[i]; sd[i] = dg[i]; srp[i] = L.rp[i]; }
-  for (int i = tid; i <= nc; i += TAIL_THREADS) { scp[i] = L.cptr[i]; slp[i] = L.lptr[i]; }
+  for (int i = tid; i < n; i += tail_nt()) { sx[i] = x[i]; sbv[i] = b[i]; sd[i] = dg[i]; srp[i] = L.rp[i]; }
+  for (int i = tid; i <= nc; i += tail_nt()) { scp[i] = L.cptr[i]; slp[i] = L.lptr[i]; }
   if (tid == 0) srp[n] = L.rp[n];
   if (all) {
     const T* gv = TV<T>::val(L);
-    for (int i = tid; i < L.nnz; i += TAIL_THREADS) { sval[i] = gv[i]; sci[i] = L.ci[i]; }
+    for (int i = tid; i < L.nnz; i += tail_nt()) { sval[i] = gv[i]; sci[i] = L.ci[i]; }
   }
   __syncthreads();
   if (all) lds_sweeps<T>(L, sweeps, sx, sbv, sd, srp, scp, slp, sval, sci);
   else lds_sweeps<T>(L, sweeps, sx, sbv, sd, srp, scp, slp, TV<T>::val(L), L.ci);
-  for (int i = tid; i < n; i += TAIL_THREADS) x[i] = sx[i];
+  for (int i = tid; i < n; i += tail_nt()) x[i] = sx[i];
 }
-// Sweeps of a small level (n <= R * TAIL_THREADS rows): thread t owns rows
-// t, t + TAIL_THREADS, ... for the whole op.  Each row's colour, first RMAX
+// Sweeps of a small level (n <= R * tail_nt() rows): thread t owns rows
+// t, t + tail_nt(), ... for the whole op.  Each row's colour, first RMAX
 // weights and column indices, b and diagonal stay in registers and x lives
 // in LDS (with the colours' long-row bounds), so a colour phase is one round
 // of LDS gathers before the barrier.  The sums run left to right as in every
@@ -262,12 +274,12 @@ __device__ __attribute__((always_inline)) inline void tail_gs_small(const TailLe
   // the colours' long-row bounds, read every phase, staged beside x (the
   // level's own list may sit in global memory)
   LP<int> slp = (LP<int>)(sx + n);
-  for (int c = tid; c <= nc; c += TAIL_THREADS) slp[c] = L.lptr[c];
+  for (int c = tid; c <= nc; c += tail_nt()) slp[c] = L.lptr[c];
   int col[R], p0[R], len[R], cj[R][RMAX];
   T bu[R], du[R], wj[R][RMAX];
 #pragma unroll
   for (int k = 0; k < R; ++k) {
-    const int u = tid + k * TAIL_THREADS;
+    const int u = tid + k * tail_nt();
     col[k] = -1;
     len[k] = 0;
     p0[k] = 0;
@@ -304,9 +316,9 @@ __device__ __attribute__((always_inline)) inline void tail_gs_small(const TailLe
         for (int q = 0; q < RMAX; ++q)
           if (q < len[k]) s += wj[k][q] * xg[q];
         for (int t = RMAX; t < len[k]; ++t) s += val[p0[k] + t] * sx[L.ci[p0[k] + t]];
-        sx[tid + k * TAIL_THREADS] = (bu[k] + s) / du[k];
+        sx[tid + k * tail_nt()] = (bu[k] + s) / du[k];
       }
-      for (int k = slp[c] + wv; k < slp[c + 1]; k += TAIL_WAVES) {
+      for (int k = slp[c] + wv; k < slp[c + 1]; k += tail_nw()) {
         const int u = L.lrows[k];
         const int q0 = L.rp[u], ln = L.rp[u + 1] - q0;
         const T s = dev::row_sum_wave<T>(ln, lane, [&](int t) { return val[q0 + t] * sx[L.ci[q0 + t]]; });
@@ -316,7 +328,7 @@ __device__ __attribute__((always_inline)) inline void tail_gs_small(const TailLe
     }
 #pragma unroll
   for (int k = 0; k < R; ++k) {
-    const int u = tid + k * TAIL_THREADS;
+    const int u = tid + k * tail_nt();
     if (u < n) x[u] = sx[u];
   }
 }
@@ -325,9 +337,9 @@ template <class T, bool MV>
 __device__ __attribute__((always_inline)) inline void tail_sweeps(const TailLevel& L, ColOf<MV> C, char* lds,
                                                                   int budget, int sweeps) {
   const size_t small = (size_t)L.n * sizeof(T) + (size_t)(L.ncol + 1) * sizeof(int);
-  if (L.n <= TAIL_THREADS && small <= (size_t)budget) {
+  if (L.n <= tail_nt() && small <= (size_t)budget) {
     tail_gs_small<T, MV, 1>(L, C, lds, sweeps);
-  } else if (L.n <= 2 * TAIL_THREADS && small <= (size_t)budget) {
+  } else if (L.n <= 2 * tail_nt() && small <= (size_t)budget) {
     tail_gs_small<T, MV, 2>(L, C, lds, sweeps);
   } else if (tail_fits<T>(L, budget)) {
     tail_gs_lds<T, MV>(L, C, lds, budget, sweeps);
@@ -348,8 +360,8 @@ __device__ __attribute__((always_inline)) inline void res_rows(const TailLevel& 
                                                                bool save, Col<T, MV> Xs) {
   constexpr int Q = 8;
   const int n = L.n, tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
-  for (int u0 = tid; u0 < n; u0 += 2 * TAIL_THREADS) {
-    const int u[2] = {u0, u0 + TAIL_THREADS};
+  for (int u0 = tid; u0 < n; u0 += 2 * tail_nt()) {
+    const int u[2] = {u0, u0 + tail_nt()};
     int p0[2], len[2];
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
@@ -389,7 +401,7 @@ __device__ __attribute__((always_inline)) inline void res_rows(const TailLevel& 
       if (save) Xs[u[k]] = xu;
     }
   }
-  for (int k = wv; k < L.nlong; k += TAIL_WAVES) {
+  for (int k = wv; k < L.nlong; k += tail_nw()) {
     const int u = L.lrows[k];
     const int q0 = rpa[u], ln = rpa[u + 1] - q0;
     const T s = dev::row_sum_wave<T>(ln, lane, [&](int t) { return val[q0 + t] * xa[L.ci[q0 + t]]; });
@@ -421,7 +433,7 @@ __device__ __attribute__((always_inline)) inline bool tail_residual(const TailLe
     LP<T> sd = sb + n;
     LP<T> sr = sd + n;
     LP<int> srp = (LP<int>)(sr + n);
-    for (int i = tid; i < n; i += TAIL_THREADS) { sx[i] = x[i]; sb[i] = b[i]; sd[i] = dg[i]; srp[i] = L.rp[i]; }
+    for (int i = tid; i < n; i += tail_nt()) { sx[i] = x[i]; sb[i] = b[i]; sd[i] = dg[i]; srp[i] = L.rp[i]; }
     if (tid == 0) srp[n] = L.rp[n];
     __syncthreads();
     res_rows<T, MV>(L, sx, sb, sd, srp, val, out, sr, true, save, Xs);
@@ -433,7 +445,7 @@ __device__ __attribute__((always_inline)) inline bool tail_residual(const TailLe
 }
 
 // Fixed-order sum of NV values per thread over the workgroup: a butterfly
-// inside each wavefront, then the 16 wavefront sums left to right.
+// inside each wavefront, then the launch's wavefront sums left to right.
 template <int NV>
 __device__ inline void block_sums(double (&v)[NV], double (*sh)[TAIL_WAVES]) {
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -446,7 +458,7 @@ __device__ inline void block_sums(double (&v)[NV], double (*sh)[TAIL_WAVES]) {
 #pragma unroll
   for (int i = 0; i < NV; ++i) {
     double t = 0;
-    for (int w = 0; w < TAIL_WAVES; ++w) t += sh[i][w];
+    for (int w = 0; w < tail_nw(); ++w) t += sh[i][w];
     v[i] = t;
   }
   __syncthreads();
@@ -480,7 +492,7 @@ __device__ __attribute__((always_inline)) inline void run_ops(const TailParams& 
       case OP_SAVEX: {
         auto x = C.v(L, TV<T>::x(L));
         auto X = C.v(L, TV<T>::X(L, op.z));
-        for (int u = tid; u < L.n; u += TAIL_THREADS) X[u] = x[u];
+        for (int u = tid; u < L.n; u += tail_nt()) X[u] = x[u];
         break;
       }
       case OP_RAGG: {
@@ -488,7 +500,7 @@ __device__ __attribute__((always_inline)) inline void run_ops(const TailParams& 
         auto src = C.v(L, op.z == 0 ? TV<T>::r(L) : TV<T>::R(L, op.z - 1));
         auto bc = C.v(Lc, TV<T>::b(Lc));
         const T mu = op.w ? (T)PP.mu : T(1);
-        for (int U = tid; U < L.nc; U += TAIL_THREADS) {
+        for (int U = tid; U < L.nc; U += tail_nt()) {
           T s = 0;
           for (int j = L.agg_ptr[U]; j < L.agg_ptr[U + 1]; ++j) s += src[L.members[j]];
           bc[U] = mu * s;
@@ -509,7 +521,7 @@ __device__ __attribute__((always_inline)) inline void run_ops(const TailParams& 
         auto bc = C.v(Lc, TV<T>::b(Lc));
         auto xc = C.v(Lc, TV<T>::x(Lc));
         const T mu = op.w ? (T)PP.mu : T(1);
-        for (int U = tid; U < L.nc; U += TAIL_THREADS) {
+        for (int U = tid; U < L.nc; U += tail_nt()) {
           T s = 0;
           if (inl)
             for (int j = L.agg_ptr[U]; j < L.agg_ptr[U + 1]; ++j) s += rl[L.members[j]];
@@ -522,14 +534,14 @@ __device__ __attribute__((always_inline)) inline void run_ops(const TailParams& 
       }
       case OP_ZERO: {
         auto x = C.v(L, TV<T>::x(L));
-        for (int u = tid; u < L.n; u += TAIL_THREADS) x[u] = T(0);
+        for (int u = tid; u < L.n; u += tail_nt()) x[u] = T(0);
         break;
       }
       case OP_IAGG: {
         const TailLevel& Lc = Ls[op.y + 1 - PP.lc];
         auto e = C.v(Lc, TV<T>::x(Lc));
         auto x = C.v(L, TV<T>::x(L));
-        for (int u = tid; u < L.n; u += TAIL_THREADS) x[u] += e[L.agg[u]];
+        for (int u = tid; u < L.n; u += tail_nt()) x[u] += e[L.agg[u]];
         break;
       }
       case OP_RELIM: {
@@ -537,7 +549,7 @@ __device__ __attribute__((always_inline)) inline void run_ops(const TailParams& 
         auto r = C.v(L, TV<T>::r(L));
         const T* er = TV<T>::er(L);
         auto bc = C.v(Lc, TV<T>::b(Lc));
-        for (int c = tid; c < L.nc; c += TAIL_THREADS) {
+        for (int c = tid; c < L.nc; c += tail_nt()) {
           T s = 0;
           for (int j = L.er_rp[c]; j < L.er_rp[c + 1]; ++j) s += er[j] * r[L.er_ci[j]];
           bc[c] = r[L.cfine[c]] + s;
@@ -551,7 +563,7 @@ __device__ __attribute__((always_inline)) inline void run_ops(const TailParams& 
         const T* val = TV<T>::val(L);
         const T* dg = TV<T>::diag(L);
         auto x = C.v(L, TV<T>::x(L));
-        for (int u = tid; u < L.n; u += TAIL_THREADS) {
+        for (int u = tid; u < L.n; u += tail_nt()) {
           const int c = L.cidx[u];
           if (c >= 0) { x[u] += e[c]; continue; }
           T s = r[u];
@@ -573,13 +585,13 @@ __device__ __attribute__((always_inline)) inline void run_ops(const TailParams& 
         auto X1 = C.v(L, TV<T>::X(L, 1));
         const int norm = PP.rnorm;
         double v[6] = {0, 0, 0, 0, 0, 0};
-        for (int u = tid; u < L.n; u += TAIL_THREADS)
+        for (int u = tid; u < L.n; u += tail_nt())
           dev::recomb_terms<T>(norm, th, r[u], R0[u], th > 1 ? R1[u] : T(0), norm ? x[u] : T(0),
                                norm ? X0[u] : T(0), norm && th > 1 ? X1[u] : T(0), v);
         block_sums<6>(v, sh);
         double a0 = 0, a1 = 0;
         dev::recomb_alpha(norm, th, v, &a0, &a1);
-        for (int u = tid; u < L.n; u += TAIL_THREADS) {
+        for (int u = tid; u < L.n; u += tail_nt()) {
           const double xu = (double)x[u];
           double y = xu;
           y += a0 * ((double)X0[u] - xu);
@@ -599,7 +611,7 @@ __device__ __attribute__((always_inline)) inline void run_ops(const TailParams& 
         auto x = C.v(L, TV<T>::x(L));
         const int wv = tid >> 6, lane = tid & 63;
         if (L.vres || (size_t)PP.nL * sizeof(double) > (size_t)budget) {
-          for (int r = wv; r < PP.nL; r += TAIL_WAVES) {
+          for (int r = wv; r < PP.nL; r += tail_nw()) {
             const double* row = PP.Minv + (size_t)r * PP.nL;
             double s = 0;
             for (int j = lane; j < PP.nL; j += 64) s += row[j] * (double)b[j];
@@ -608,9 +620,9 @@ __device__ __attribute__((always_inline)) inline void run_ops(const TailParams& 
           }
           break;
         }
-        for (int j = tid; j < PP.nL; j += TAIL_THREADS) sb[j] = (double)b[j];
+        for (int j = tid; j < PP.nL; j += tail_nt()) sb[j] = (double)b[j];
         __syncthreads();
-        for (int r = wv; r < PP.nL; r += TAIL_WAVES) {
+        for (int r = wv; r < PP.nL; r += tail_nw()) {
           const double* row = PP.Minv + (size_t)r * PP.nL;
           double s = 0;
           for (int j = lane; j < PP.nL; j += 64) s += row[j] * sb[j];
@@ -622,10 +634,10 @@ __device__ __attribute__((always_inline)) inline void run_ops(const TailParams& 
       case OP_MEAN: {
         auto x = C.v(L, TV<T>::x(L));
         double v[1] = {0};
-        for (int u = tid; u < L.n; u += TAIL_THREADS) v[0] += (double)x[u];
+        for (int u = tid; u < L.n; u += tail_nt()) v[0] += (double)x[u];
         block_sums<1>(v, sh);
         const double mean = v[0] / (double)L.n;
-        for (int u = tid; u < L.n; u += TAIL_THREADS) x[u] = (T)((double)x[u] - mean);
+        for (int u = tid; u < L.n; u += tail_nt()) x[u] = (T)((double)x[u] - mean);
         break;
       }
       default:
@@ -668,7 +680,7 @@ template <class U>
 __device__ inline U* lds_put(char*& cur, const U* src, size_t count) {
   U* dst = (U*)cur;
   if (src)
-    for (size_t i = threadIdx.x; i < count; i += TAIL_THREADS) dst[i] = src[i];
+    for (size_t i = threadIdx.x; i < count; i += tail_nt()) dst[i] = src[i];
   cur += al16(count * sizeof(U));
   return dst;
 }
@@ -732,7 +744,7 @@ __device__ __attribute__((always_inline)) inline void run_resident(const TailPar
   TailLevel* dl = (TailLevel*)lds;
   // one thread per descriptor, copied as the struct it is (no reinterpreting
   // of its words through another type)
-  for (int i = tid; i < nlev; i += TAIL_THREADS) dl[i] = P.L[i];
+  for (int i = tid; i < nlev; i += tail_nt()) dl[i] = P.L[i];
   __syncthreads();
   char* cur = lds + al16((size_t)nlev * sizeof(TailLevel));
   const int rfrom = resident_from<T>(dl, nlev, P.lds_bytes, P.res_bytes, nullptr);
@@ -772,7 +784,7 @@ __device__ __attribute__((always_inline)) inline void run_resident(const TailPar
       x0 = TV<T>::x(o);
       auto gx = C.v(o, TV<T>::x(o));
       auto gb = C.v(o, TV<T>::b(o));
-      for (size_t k = tid; k < n; k += TAIL_THREADS) {
+      for (size_t k = tid; k < n; k += tail_nt()) {
         w[0][k] = gx[(int)k];
         w[1][k] = gb[(int)k];
       }
@@ -793,7 +805,7 @@ __device__ __attribute__((always_inline)) inline void run_resident(const TailPar
     // write the entry level's iterate back (the caller interpolates from it)
     const Col<T, MV> gx{MV ? x0 + C.j : x0, C.k};
     const T* sx = TV<T>::x(dl[0]);
-    for (int k = tid; k < dl[0].n; k += TAIL_THREADS) gx[k] = sx[k];
+    for (int k = tid; k < dl[0].n; k += tail_nt()) gx[k] = sx[k];
     __syncthreads();
   }
 }
@@ -1075,7 +1087,7 @@ void launch_tail(Hierarchy* H, const void* levels, int kc) {
   const int kid = sizeof(T) == 8 ? 14 : 15;
   if (!MV) prof_begin(H->s, kid);
   if (!MV && prof_on()) prof_count(kid, 0);  // latency-bound: time and launches only
-  hipLaunchKernelGGL((k_tail<T, MV>), dim3(MV ? kc : 1), dim3(TAIL_THREADS), lds, H->s, P,
+  hipLaunchKernelGGL((k_tail<T, MV>), dim3(MV ? kc : 1), dim3(TAIL_LAUNCH), lds, H->s, P,
                      (const int4*)(H->tail_prog + seg.x), seg.y);
   if (!MV) prof_end(H->s);
   LAMG_HIP(hipGetLastError());
@@ -1173,7 +1185,7 @@ __device__ __attribute__((noinline)) void run_cycle(const TailParams& P, const i
 template <class F>
 __device__ inline double wg_sum(int n, double (*sh)[TAIL_WAVES], F f) {
   double v[1] = {0};
-  for (int i = threadIdx.x; i < n; i += TAIL_THREADS) v[0] += f(i);
+  for (int i = threadIdx.x; i < n; i += tail_nt()) v[0] += f(i);
   block_sums<1>(v, sh);
   return v[0];
 }
@@ -1186,7 +1198,7 @@ __device__ __attribute__((always_inline)) inline void solve_graph(const BatchGra
   double* x64 = L0.x64;
   double* r64 = g.r64;
   const double mean = wg_sum(n, sh, [&](int i) { return g.b[i]; }) / (double)n;
-  for (int i = tid; i < n; i += TAIL_THREADS) {
+  for (int i = tid; i < n; i += tail_nt()) {
     b64[i] = g.b[g.perm[i]] - mean;
     x64[i] = g.warm ? g.x[g.perm[i]] : 0.0;
   }
@@ -1207,16 +1219,16 @@ __device__ __attribute__((always_inline)) inline void solve_graph(const BatchGra
         float* b32 = L0.b32;
         float* x32 = L0.x32;
         const double mr = wg_sum(n, sh, [&](int i) { return r64[i]; }) / (double)n;
-        for (int i = tid; i < n; i += TAIL_THREADS) {
+        for (int i = tid; i < n; i += tail_nt()) {
           b32[i] = (float)(r64[i] - mr);
           x32[i] = 0.0f;
         }
         __syncthreads();
         run_cycle<float>(g.P, g.prog, g.nops, lds, sh);
-        for (int i = tid; i < n; i += TAIL_THREADS) x64[i] += (double)x32[i];
+        for (int i = tid; i < n; i += tail_nt()) x64[i] += (double)x32[i];
         __syncthreads();
         const double mx = wg_sum(n, sh, [&](int i) { return x64[i]; }) / (double)n;
-        for (int i = tid; i < n; i += TAIL_THREADS) x64[i] -= mx;
+        for (int i = tid; i < n; i += tail_nt()) x64[i] -= mx;
         __syncthreads();
       }
       res_rows<double, false>(L0, x64, b64, L0.diag64, L0.rp, L0.val64, Col<double, false>{r64, 1}, (LP<double>)lds,
@@ -1226,7 +1238,7 @@ __device__ __attribute__((always_inline)) inline void solve_graph(const BatchGra
       ++it;
     }
   }
-  for (int i = tid; i < n; i += TAIL_THREADS) g.x[g.perm[i]] = x64[i];
+  for (int i = tid; i < n; i += tail_nt()) g.x[g.perm[i]] = x64[i];
   if (tid == 0) {
     out->rel = nb > 0 ? rk / nb : 0.0;
     out->r0 = r0;
