@@ -230,10 +230,12 @@ lamg_status lamg_edge_gradient(int64_t m, const int32_t* eu, const int32_t* ev, 
  *   tol    stop when ||A x_j - lambda_j x_j||_2 <= tol * lambda_j for all j.
  *   max_iter  LOBPCG iterations at most; cycles >= 1 per preconditioner call.
  *   iters  HOST int32 out (nullable): iterations taken.
- *   resid  HOST double[k] out (nullable): ||A x_j - lambda_j x_j|| / lambda_j.
+ *   resid  HOST double[k] out (nullable): ||A x_j - lambda_j x_j|| / lambda_j
+ *          of the returned vectors.
  * 1 <= k <= 8 and 4k <= n, else LAMG_E_INVALID_ARG.  LAMG_E_NOT_CONVERGED
  * still writes the last iterate; LAMG_E_BREAKDOWN when the search space
- * loses rank.  Runs on the hierarchy's stream and returns after it.
+ * loses rank or a Ritz value or residual is not finite: then X, evals and
+ * resid are left untouched and iters holds the iterations run.  Runs on the hierarchy's stream and returns after it.
  * Internally the iterated block has kb = k + min(k, 4) columns (at most n/4);
  * only the first k are tested and returned.  For the call it allocates, through
  * the hierarchy's allocator: eleven n x kb FP64 blocks, about 19 MB of Gram
@@ -247,6 +249,30 @@ lamg_status lamg_eigs(lamg_handle h, int32_t k, double* X, double* evals, double
  * nu_pre, nu_post, recomb_norm, tol, max_cycles, warm_start, stream);
  * setup-phase fields are ignored. */
 lamg_status lamg_set_solve_options(lamg_handle h, const lamg_options* o);
+
+/* Statistics of one level of a hierarchy (Sections 3-4). */
+typedef struct lamg_level_stats {
+  int64_t nnz;          /* stored off-diagonal entries (each edge twice) */
+  int32_t n;            /* nodes */
+  int32_t kind;         /* 0 finest, 1 elimination (Section 3.2), 2 aggregation (Section 3.4) */
+  int32_t colours;      /* colour classes of the Gauss-Seidel order */
+  int32_t hub_colours;  /* of these, the last ones swept by the single-workgroup hub kernel (0: none) */
+  int32_t in_tail;      /* 1: relaxed inside the single-workgroup coarse-level kernel */
+  int32_t reserved;     /* 0 */
+  double gamma;         /* cycle index of the visits from this level to the next (eq. cycle_index; 1 if none) */
+  double visits;        /* bodies run at this level per finest-level cycle (the coarsest: its solves) */
+} lamg_level_stats;
+
+/* Fill *out for level l in [0, levels) of h (0 = finest).  Host-side only: no
+ * device work.  LAMG_E_INVALID_ARG for a NULL argument or l out of range.
+ *
+ * Diagnostics: with the environment variable LAMG_LOG=1 (read once per
+ * process) every setup and solve prints one summary line to stderr; with
+ * LAMG_LOG=2 also the level table of each setup and the residual of every
+ * cycle.  Setups, solves, batches and eigensolves are marked as roctx ranges
+ * ("lamg_setup", "lamg_solve", ...; each level's construction as "lamg_level
+ * l"), which rocprofv3 --marker-trace records. */
+lamg_status lamg_level_info(lamg_handle h, int32_t l, lamg_level_stats* out);
 
 /* Release a hierarchy; NULL is a no-op. */
 void lamg_free(lamg_handle h);

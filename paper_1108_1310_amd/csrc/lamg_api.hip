@@ -5,7 +5,10 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <cstdlib>
 #include <vector>
+
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include "lamg_device.hpp"
 #include "lamg_internal.hpp"
@@ -331,6 +334,82 @@ static bool opts_ok(const lamg_options& o) {
 
 }  // extern "C"
 
+namespace {
+// LAMG_LOG verbosity (0 silent, 1 one line per setup / solve, 2 also the level
+// table and every cycle's residual), read once.
+int log_level() {
+  static const int v = [] {
+    const char* e = std::getenv("LAMG_LOG");
+    return e ? std::atoi(e) : 0;
+  }();
+  return v;
+}
+// A roctx range for the lifetime of the object.
+struct Range {
+  explicit Range(const char* name) { roctxRangePushA(name); }
+  ~Range() { roctxRangePop(); }
+  Range(const Range&) = delete;
+  Range& operator=(const Range&) = delete;
+};
+struct LevelRange {
+  explicit LevelRange(int l) {
+    char b[32];
+    std::snprintf(b, sizeof(b), "lamg_level %d", l);
+    roctxRangePushA(b);
+  }
+  ~LevelRange() { roctxRangePop(); }
+  LevelRange(const LevelRange&) = delete;
+  LevelRange& operator=(const LevelRange&) = delete;
+};
+
+// Bodies per finest-level cycle at every level: the recursion of visit and
+// body above (an elimination level is visited once per body of its finer
+// level; an aggregation level th times, th from the fractional cycle index).
+void count_bodies(const Hierarchy* H, int l, int th, std::vector<int64_t>& count, std::vector<double>& bodies) {
+  const int Lc = (int)H->lv.size() - 1;
+  const int reps = l == Lc ? 1 : th;
+  for (int i = 0; i < reps; ++i) {
+    bodies[l] += 1;
+    if (l == Lc) return;
+    if (H->lv[l + 1].type == LT_ELIM) {
+      count_bodies(H, l + 1, 1, count, bodies);
+      continue;
+    }
+    const int64_t c = count[l]++;
+    const double gl = H->lv[l].gamma_next;
+    count_bodies(H, l + 1, (int)(std::ceil((double)(c + 1) * gl) - std::ceil((double)c * gl)), count, bodies);
+  }
+}
+std::vector<double> bodies_per_cycle(const Hierarchy* H) {
+  std::vector<int64_t> count(H->lv.size(), 0);
+  std::vector<double> bodies(H->lv.size(), 0.0);
+  count_bodies(H, 0, 1, count, bodies);
+  return bodies;
+}
+int tail_first_level(const Hierarchy* H) {
+  const int nl = (int)H->lv.size();
+  int lc = nl;
+  if (H->o.tail_max_n > 0)
+    for (int l = nl - 1; l >= 0 && H->lv[l].n <= H->o.tail_max_n; --l) lc = l;
+  return lc;
+}
+void log_setup(const Hierarchy* H) {
+  if (log_level() < 1) return;
+  std::fprintf(stderr, "[lamg] setup: n %d, m %lld, %d levels, %.2f ms\n", H->n, (long long)H->m, (int)H->lv.size(),
+               H->setup_ms);
+  if (log_level() < 2) return;
+  const std::vector<double> bod = bodies_per_cycle(H);
+  const int tl = tail_first_level(H);
+  static const char* kind[] = {"finest", "elim", "agg"};
+  for (size_t l = 0; l < H->lv.size(); ++l) {
+    const Level& L = H->lv[l];
+    std::fprintf(stderr, "[lamg]   level %2zu %-6s n %9d nnz %10d colours %3d hub %3d gamma %.4f bodies %6.0f%s\n", l,
+                 kind[L.type], L.n, L.nnz, L.ncol, L.hub_k >= 0 ? L.ncol - L.hub_k : 0, L.gamma_next, bod[l],
+                 (int)l >= tl ? " tail" : "");
+  }
+}
+}  // namespace
+
 // Setup frame shared by the entry points: options, handle, allocator scope,
 // the level construction `levels` (returns a status), finishing and errors.
 template <class Levels>
@@ -353,6 +432,7 @@ static lamg_status run_setup(int64_t n, int64_t m, const lamg_options* o, lamg_h
   H->s = (hipStream_t)opt.stream;
   H->gamma_every_level = gamma_every_level;
   AllocScope scope(&H->o);  // setup temporaries through the same allocator
+  Range range("lamg_setup");
   H->n = (int)n;
   H->m = m;
   auto t0 = std::chrono::steady_clock::now();
@@ -374,6 +454,7 @@ static lamg_status run_setup(int64_t n, int64_t m, const lamg_options* o, lamg_h
     return e.e == hipErrorOutOfMemory ? LAMG_E_OUT_OF_MEMORY : LAMG_E_DEVICE;
   }
   H->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  log_setup(H);
   *out = h;
   return LAMG_OK;
 }
@@ -393,6 +474,7 @@ lamg_status lamg_setup(int64_t n, int64_t m, const int32_t* eu, const int32_t* e
     int nagg = 0;
     while (H->lv.back().n >= H->o.coarsest_max_n && (int)H->lv.size() < 60) {
       const int l = (int)H->lv.size() - 1;
+      LevelRange lr(l + 1);
       if (try_eliminate(H, l)) continue;
       const int r = aggregate(H, l, nagg);
       if (r == 2) { H->coarsest_relax = true; break; }
@@ -413,6 +495,7 @@ lamg_status lamg_setup_lgm(int32_t side, const lamg_options* o, lamg_handle* out
     if (st != LAMG_OK) return st;
     int sd = side;
     while (H->lv.back().n >= H->o.coarsest_max_n && sd >= 4 && (int)H->lv.size() < 60) {
+      LevelRange lr((int)H->lv.size());
       lgm_coarsen(H, (int)H->lv.size() - 1, sd);
       sd /= 2;
     }
@@ -508,6 +591,7 @@ static lamg_status solve_one(Hierarchy* H, const double* b, double* x, lamg_info
       LAMG_HIP(hipStreamSynchronize(s));
       rk = std::sqrt(hr[2]);
       ++it;
+      if (log_level() >= 2) std::fprintf(stderr, "[lamg]   cycle %3d  rel. residual %.3e\n", it, rk / nb);
     }
   }
   hipLaunchKernelGGL(k_scatter, grid1(n), dim3(256), 0, s, n, L.perm, (const double*)H->x64, x);
@@ -523,6 +607,9 @@ static lamg_status solve_one(Hierarchy* H, const double* b, double* x, lamg_info
     info->solve_ms = ms;
     info->bytes_moved = (int64_t)it * cycle_bytes(H, H->o.precision);
   }
+  if (log_level() >= 1)
+    std::fprintf(stderr, "[lamg] solve: %s, %d cycles, rel. residual %.3e, %.3f ms\n", fp32 ? "fp32+refine" : "fp64", it,
+                 nb > 0 ? rk / nb : 0.0, ms);
   if (!std::isfinite(rk)) return LAMG_E_BREAKDOWN;
   if (nb > 0 && rk > H->o.tol * nb) return LAMG_E_NOT_CONVERGED;
   return LAMG_OK;
@@ -530,6 +617,7 @@ static lamg_status solve_one(Hierarchy* H, const double* b, double* x, lamg_info
 
 lamg_status lamg_solve(lamg_handle h, const double* b, double* x, lamg_info* info) {
   if (!h || !b || !x) return LAMG_E_INVALID_ARG;
+  Range range("lamg_solve");
   try {
     return solve_one(&h->H, b, x, info);
   } catch (const DevError& e) {
@@ -547,6 +635,7 @@ lamg_status lamg_solve_batch(int32_t count, const lamg_handle* hs, const int32_t
     for (int j = 0; j < i; ++j)
       if (hs[j] == hs[i]) return LAMG_E_INVALID_ARG;  // one handle, one solve at a time
   }
+  Range range("lamg_solve_batch");
   try {
     std::vector<int> many;  // single right-hand sides of small graphs: one persistent launch
     for (int i = 0; i < count; ++i) {
@@ -607,6 +696,7 @@ lamg_status lamg_solve_batch_noalloc(int32_t count, const lamg_handle* hs, const
   std::vector<Hierarchy*> sorted(H);
   std::sort(sorted.begin(), sorted.end());
   if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end()) return LAMG_E_INVALID_ARG;
+  Range range("lamg_solve_batch_noalloc");
   try {
     return solve_graphs(count, H.data(), B, X, infos, true);
   } catch (const DevError& e) {
@@ -637,6 +727,23 @@ lamg_status lamg_edge_gradient(int64_t m, const int32_t* eu, const int32_t* ev, 
     set_last_error("lamg_edge_gradient", e.e);
     return LAMG_E_DEVICE;
   }
+  return LAMG_OK;
+}
+
+lamg_status lamg_level_info(lamg_handle h, int32_t l, lamg_level_stats* out) {
+  if (!h || !out || l < 0 || l >= (int32_t)h->H.lv.size()) return LAMG_E_INVALID_ARG;
+  const Hierarchy* H = &h->H;
+  const Level& L = H->lv[l];
+  const std::vector<double> bod = bodies_per_cycle(H);
+  std::memset(out, 0, sizeof(*out));
+  out->nnz = L.nnz;
+  out->n = L.n;
+  out->kind = L.type;
+  out->colours = L.ncol;
+  out->hub_colours = L.hub_k >= 0 ? L.ncol - L.hub_k : 0;
+  out->in_tail = l >= tail_first_level(H) ? 1 : 0;
+  out->gamma = l + 1 < (int32_t)H->lv.size() ? L.gamma_next : 1.0;
+  out->visits = bod[l];
   return LAMG_OK;
 }
 

@@ -24,6 +24,8 @@
 #include <numeric>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "lamg_device.hpp"
 #include "lamg_internal.hpp"
 #include "../../include/lamg.h"
@@ -406,13 +408,17 @@ lamg_status eigs(Hierarchy* H, int k, double* X, double* evals, double tol, int 
     std::swap(NX, NXn);
     return true;
   };
-  if (!rr_x()) return LAMG_E_BREAKDOWN;
-  bool haveP = false;
   int it = 0;
+  auto breakdown = [&]() {
+    if (iters) *iters = it;  // X and evals untouched
+    return LAMG_E_BREAKDOWN;
+  };
+  if (!rr_x()) return breakdown();
+  bool haveP = false;
   std::vector<double> rn(kb, 0.0);
-  lamg_status st = LAMG_E_NOT_CONVERGED;
-  for (;;) {
-    // R = A X - X Lambda = -(NX) - X Lambda
+  // R = A X - X Lambda = -(NX) - X Lambda and its column norms in rn; false
+  // if a norm or a Ritz value is not finite
+  auto residuals = [&]() {
     std::vector<double> Cr((size_t)2 * kb * kb, 0.0);
     for (int c = 0; c < kb; ++c) {
       Cr[(size_t)c * kb + c] = -1.0;
@@ -420,13 +426,19 @@ lamg_status eigs(Hierarchy* H, int k, double* X, double* evals, double tol, int 
     }
     E.combine(2, Blocks3{{NX, Xb, nullptr}}, Cr, 0, R);
     const std::vector<double> GR = E.gram(1, Blocks3{{R, nullptr, nullptr}}, Blocks3{{R, nullptr, nullptr}});
-    bool done = true, bad = false;
+    bool ok = true;
     for (int c = 0; c < kb; ++c) {
       rn[c] = std::sqrt(std::max(0.0, GR[(size_t)c * kb + c]));
-      if (!std::isfinite(rn[c]) || !std::isfinite(theta[c])) bad = true;
-      if (c < k && rn[c] > tol * std::fabs(theta[c])) done = false;
+      if (!std::isfinite(rn[c]) || !std::isfinite(theta[c])) ok = false;
     }
-    if (bad) { st = LAMG_E_BREAKDOWN; break; }
+    return ok;
+  };
+  lamg_status st = LAMG_E_NOT_CONVERGED;
+  for (;;) {
+    if (!residuals()) return breakdown();
+    bool done = true;
+    for (int c = 0; c < k; ++c)
+      if (rn[c] > tol * std::fabs(theta[c])) done = false;
     if (done) { st = LAMG_OK; break; }
     if (it >= max_iter) break;
     ++it;
@@ -454,7 +466,7 @@ lamg_status eigs(Hierarchy* H, int k, double* X, double* evals, double tol, int 
       for (double& v : GA) v = -v;
       const int r = rayleigh_ritz(nb * kb, kb, GB, GA, C, theta);
       if (r >= kb) break;
-      if (nb == 2) return LAMG_E_BREAKDOWN;
+      if (nb == 2) return breakdown();
       nb = 2;  // drop the search directions and retry
     }
     const Blocks3 S{{Xb, Wb, nb == 3 ? Pb : nullptr}}, NS{{NX, NW, nb == 3 ? NP : nullptr}};
@@ -470,8 +482,9 @@ lamg_status eigs(Hierarchy* H, int k, double* X, double* evals, double tol, int 
     haveP = true;
   }
   // a last Rayleigh-Ritz on the final block restores orthonormality lost to
-  // the ill-conditioned Gram matrices of the last iterations
-  if (st != LAMG_E_BREAKDOWN && !rr_x()) st = LAMG_E_BREAKDOWN;
+  // the ill-conditioned Gram matrices of the last iterations; the residuals
+  // returned are those of the block it produces
+  if (!rr_x() || !residuals()) return breakdown();
   hipLaunchKernelGGL(k_eig_scatter, grid_nk((int64_t)n * k), dim3(ET), 0, s, n, k, kb, perm, (const double*)Xb, X);
   LAMG_HIP(hipGetLastError());
   LAMG_HIP(hipStreamSynchronize(s));
@@ -492,6 +505,10 @@ extern "C" {
 lamg_status lamg_eigs(lamg_handle h, int32_t k, double* X, double* evals, double tol, int32_t max_iter,
                       int32_t cycles, int32_t* iters, double* resid) {
   if (!h || !X || !evals) return LAMG_E_INVALID_ARG;
+  roctxRangePushA("lamg_eigs");
+  struct Pop {
+    ~Pop() { roctxRangePop(); }
+  } pop;
   try {
     return eigs(&h->H, k, X, evals, tol, max_iter, cycles, iters, resid);
   } catch (const DevError& e) {

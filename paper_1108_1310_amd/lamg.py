@@ -51,6 +51,15 @@ class Info(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class LevelStats(C.Structure):
+    _fields_ = [("nnz", C.c_int64), ("n", C.c_int32), ("kind", C.c_int32), ("colours", C.c_int32),
+                ("hub_colours", C.c_int32), ("in_tail", C.c_int32), ("reserved", C.c_int32), ("gamma", C.c_double),
+                ("visits", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
 class LamgError(RuntimeError):
     def __init__(self, status: int, where: str):
         self.status = status
@@ -80,6 +89,7 @@ def lib():
             "lamg_set_solve_options": (C.c_int, [vp, C.POINTER(Options)]),
             "lamg_edge_gradient": (C.c_int, [i64, vp, vp, vp, vp, vp, vp]),
             "lamg_eigs": (C.c_int, [vp, i32, vp, vp, d, i32, i32, C.POINTER(i32), vp]),
+            "lamg_level_info": (C.c_int, [vp, i32, C.POINTER(LevelStats)]),
             "lamg_free": (None, [vp]),
             "lamg_status_str": (C.c_char_p, [C.c_int]),
             "lamg_last_error": (C.c_char_p, []),
@@ -273,6 +283,14 @@ class Hierarchy:
         if check and rc not in (OK, E_NOT_CONVERGED):
             _check(rc, "lamg_eigs")
         return ev, X, {"iters": int(it.value), "resid": rs, "status": rc}
+
+    def level_info(self, l: int) -> dict:
+        """Per-level statistics: n, nnz, kind (0 finest, 1 elimination, 2
+        aggregation), colours, hub_colours, in_tail, gamma, visits (bodies per
+        finest-level cycle)."""
+        st = LevelStats()
+        _check(lib().lamg_level_info(self.h, l, C.byref(st)), "lamg_level_info")
+        return st.as_dict()
 
     # ------------------------------------------------------ inspection (tests)
     @property

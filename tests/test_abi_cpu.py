@@ -55,6 +55,10 @@ def test_host_only_entry_points():
     half = lamg.options()
     half.dealloc = lamg.DEALLOC_FN(lambda ptr, ctx: None)
     assert L.lamg_setup(4, 0, None, None, None, ctypes.byref(half), ctypes.byref(h)) == lamg.E_INVALID_ARG
+    # per-level statistics: host-only, NULL handle refused; struct layout of the header
+    st = lamg.LevelStats()
+    assert ctypes.sizeof(lamg.LevelStats) == 48
+    assert L.lamg_level_info(None, 0, ctypes.byref(st)) == lamg.E_INVALID_ARG
     # lean geometric multigrid: side a power of two in [4, LAMG_LGM_MAX_SIDE]
     for side in (0, 2, 3, 6, 100, 32768, -4):
         assert L.lamg_setup_lgm(side, None, ctypes.byref(h)) == lamg.E_INVALID_ARG, side
