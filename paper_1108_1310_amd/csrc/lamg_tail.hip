@@ -2,10 +2,10 @@
 // levels).  The coarse levels are visited many times per finest cycle
 // (fractional cycle index, eq. cycle_index) but hold few nodes, so one launch
 // per colour pass would be dominated by launch latency.  Instead, every entry
-// into level tail_lc runs one 1024-thread workgroup that executes a
-// precomputed op program (the same relaxations, transfers, recombinations and
-// coarsest solves the multi-launch path performs, in the same order), with a
-// workgroup barrier between ops.  Sums keep the fixed order of the other
+// into level tail_lc runs one workgroup (512 threads in FP64, 1024 in FP32)
+// that executes a precomputed op program (the same relaxations, transfers,
+// recombinations and coarsest solves the multi-launch path performs, in the
+// same order), with a workgroup barrier between ops.  Sums keep the fixed order of the other
 // kernels: short rows left to right by one thread, long rows (> 64 entries)
 // by one wavefront in 512-entry chunks.
 #include <algorithm>
@@ -31,13 +31,19 @@ namespace {
 constexpr int TAIL_THREADS = 1024;
 constexpr int TAIL_WAVES = TAIL_THREADS / 64;
 static_assert(TAIL_WAVES * 64 == TAIL_THREADS, "whole wavefronts");
-// Launch size of the single-workgroup tail (k_tail).  Measured on one box
-// against 512 threads (whose barriers span half the wavefronts but whose
-// register-resident sweeps cover only levels of up to 1,024 rows): RGG 2^20
-// 191.6 / 196.3 ms per solve, 64^2 grid 6.06 / 5.74 ms, 64^3 anisotropic
-// grid 596 / 594 ms, geometric multigrid 1024^2 9.14 / 9.19 ms.
-constexpr int TAIL_LAUNCH = 1024;
-static_assert(TAIL_LAUNCH % 64 == 0 && TAIL_LAUNCH <= TAIL_THREADS, "whole wavefronts within the scratch");
+// Launch size (and launch bound) of the single-workgroup tail k_tail, per
+// precision.  At 512 threads the FP64 interpreter gets up to 256 VGPRs
+// instead of 128 (248 used; private scratch 92 instead of 228 bytes per
+// lane), which outweighs the halved thread count; the FP32 one does not
+// gain.  Measured on one box, 1024 threads for both / FP64 at 512 / both at
+// 512: RGG 2^20 FP64 189.3 / 185.5 / 185.5 ms per solve, FP32 158.5 / 158.2 /
+// 167.3 ms, 64^2 grid 5.91 / 5.17 / 5.17 ms, 64^3 anisotropic grid 587 / 556
+// / 556 ms, geometric multigrid 1024^2 9.09 / 8.51 / 8.51 ms, 8 columns on
+// the 64^3 grid FP64 677 / 648 / 648 ms, FP32 607 / 607 / 628 ms.
+template <class T>
+constexpr int tail_launch() { return sizeof(T) == 8 ? 512 : 1024; }
+static_assert(tail_launch<double>() % 64 == 0 && tail_launch<float>() % 64 == 0, "whole wavefronts");
+static_assert(tail_launch<double>() <= TAIL_THREADS && tail_launch<float>() <= TAIL_THREADS, "within the scratch");
 // Every stride and wavefront count of the interpreter comes from the
 // launch; TAIL_THREADS / TAIL_WAVES only bound it (launch bounds, the size
 // of the wavefront-sum scratch).
@@ -816,7 +822,7 @@ __device__ __attribute__((noinline)) void run_program(const TailParams& P, const
   run_resident<T, MV>(P, prog, nops, lds, sh);
 }
 template <class T, bool MV>
-__global__ __launch_bounds__(TAIL_THREADS) void k_tail(TailParams P, const int4* __restrict__ prog, int nops) {
+__global__ __launch_bounds__(tail_launch<T>()) void k_tail(TailParams P, const int4* __restrict__ prog, int nops) {
   __shared__ double sh[6][TAIL_WAVES];
   extern __shared__ double lds_d[];
   run_program<T, MV>(P, prog, nops, (char*)lds_d, sh);
@@ -1087,7 +1093,7 @@ void launch_tail(Hierarchy* H, const void* levels, int kc) {
   const int kid = sizeof(T) == 8 ? 14 : 15;
   if (!MV) prof_begin(H->s, kid);
   if (!MV && prof_on()) prof_count(kid, 0);  // latency-bound: time and launches only
-  hipLaunchKernelGGL((k_tail<T, MV>), dim3(MV ? kc : 1), dim3(TAIL_LAUNCH), lds, H->s, P,
+  hipLaunchKernelGGL((k_tail<T, MV>), dim3(MV ? kc : 1), dim3(tail_launch<T>()), lds, H->s, P,
                      (const int4*)(H->tail_prog + seg.x), seg.y);
   if (!MV) prof_end(H->s);
   LAMG_HIP(hipGetLastError());
