@@ -102,6 +102,20 @@ lamg_status lamg_t_residual(int32_t n, const int32_t* rp, const int32_t* ci, con
 lamg_status lamg_t_colour(int32_t n, const int32_t* rp, const int32_t* ci, uint64_t seed, int32_t level,
                           int32_t* colour, void* stream);
 
+/* The setup's stable LSD radix sort (8-bit digits, keys compared on bits
+ * [0, endbit), 1 <= endbit <= key bits) and exclusive scan, on DEVICE arrays
+ * of n elements (out arrays must not overlap the inputs).  Pairs of 64-bit
+ * keys and doubles (sparse assembly), of 32-bit keys and ints (renumbering,
+ * aggregate lists), double keys alone (ascending, -0 before +0: the stage-1
+ * quantile); scan: out[0] = 0, out[i+1] = in[0] + ... + in[i] (n + 1 outputs).
+ * Run on the null stream and return after it; temporaries from hipMalloc. */
+lamg_status lamg_t_sort_pairs64(int64_t n, const uint64_t* keys, const double* vals, uint64_t* keys_out,
+                                double* vals_out, int32_t endbit);
+lamg_status lamg_t_sort_pairs32(int64_t n, const uint32_t* keys, const int32_t* vals, uint32_t* keys_out,
+                                int32_t* vals_out, int32_t endbit);
+lamg_status lamg_t_sort_f64(int64_t n, const double* keys, double* keys_out);
+lamg_status lamg_t_excl_scan(int64_t n, const int32_t* in, int32_t* out);
+
 /* Hub sweep of level l (Section 3.1.1, eq. gs, multicolour order): out[4] =
  * first hub colour (-1: the level's sweeps do not take the hub path), first
  * hub row, hub rows, hub-to-hub entries.  HOST out. */

@@ -6,8 +6,6 @@
 // same floating-point order as the CPU reference: short rows left to right,
 // long rows as 64 strided partial sums and an xor butterfly, no contraction.
 #include <cstring>
-#include <rocprim/device/device_radix_sort.hpp>
-#include <rocprim/device/device_scan.hpp>
 
 #include <algorithm>
 #include <cmath>
@@ -15,6 +13,7 @@
 
 #include "lamg_device.hpp"
 #include "lamg_internal.hpp"
+#include "lamg_sort.hpp"
 
 namespace lamg {
 
@@ -72,24 +71,22 @@ unsigned bits_for(uint64_t maxkey) {
 template <class K, class V>
 void sort_pairs(hipStream_t s, Tmp& tmp, const K* kin, K* kout, const V* vin, V* vout, int64_t n, unsigned endbit) {
   if (n == 0) return;
-  size_t bytes = 0;
-  LAMG_HIP(rocprim::radix_sort_pairs(nullptr, bytes, kin, kout, vin, vout, (size_t)n, 0u, endbit, s));
-  void* t = tmp.get<char>(bytes);
-  LAMG_HIP(rocprim::radix_sort_pairs(t, bytes, kin, kout, vin, vout, (size_t)n, 0u, endbit, s));
+  void* t = tmp.get<char>(sortk::sort_scratch_bytes<K, V>(n));
+  sortk::radix_sort<K, V>(s, kin, kout, vin, vout, n, endbit, t);
+  LAMG_HIP(hipGetLastError());
 }
 template <class K>
 void sort_keys_double(hipStream_t s, Tmp& tmp, const K* kin, K* kout, int64_t n) {
-  size_t bytes = 0;
-  LAMG_HIP(rocprim::radix_sort_keys(nullptr, bytes, kin, kout, (size_t)n, 0u, (unsigned)(8 * sizeof(K)), s));
-  void* t = tmp.get<char>(bytes);
-  LAMG_HIP(rocprim::radix_sort_keys(t, bytes, kin, kout, (size_t)n, 0u, (unsigned)(8 * sizeof(K)), s));
+  if (n == 0) return;
+  void* t = tmp.get<char>(sortk::sort_scratch_bytes<K, sortk::NoVal>(n));
+  sortk::radix_sort<K, sortk::NoVal>(s, kin, kout, nullptr, nullptr, n, (unsigned)(8 * sizeof(K)), t);
+  LAMG_HIP(hipGetLastError());
 }
 // exclusive scan of n ints; out has n+1 entries (out[n] = total)
 void excl_scan(hipStream_t s, Tmp& tmp, const int* in, int* out, int64_t n) {
-  size_t bytes = 0;
-  LAMG_HIP(rocprim::exclusive_scan(nullptr, bytes, in, out, 0, (size_t)n + 1, rocprim::plus<int>(), s));
-  void* t = tmp.get<char>(bytes);
-  LAMG_HIP(rocprim::exclusive_scan(t, bytes, in, out, 0, (size_t)n + 1, rocprim::plus<int>(), s));
+  int* t = tmp.get<int>(sortk::scan_scratch(n));
+  sortk::exclusive_scan(s, in, out, n, t);
+  LAMG_HIP(hipGetLastError());
 }
 template <class T>
 T to_host(hipStream_t s, const T* p) {

@@ -5,6 +5,7 @@
 
 #include "../../include/lamg_test.h"
 #include "lamg_internal.hpp"
+#include "lamg_sort.hpp"
 
 using namespace lamg;
 
@@ -37,9 +38,55 @@ Level borrowed_level(Scratch& S, int n, const int32_t* rp, const int32_t* ci, in
   build_tiles(&S.H, L);
   return L;
 }
+// Device temporaries of one test call.
+struct DevTmp {
+  void* p = nullptr;
+  explicit DevTmp(size_t bytes) { LAMG_HIP(hipMalloc(&p, std::max<size_t>(bytes, 16))); }
+  ~DevTmp() { (void)hipFree(p); }
+};
+template <class K, class V>
+lamg_status sort_entry(int64_t n, const K* k, const V* v, K* ko, V* vo, int endbit) {
+  if (n < 0 || (n > 0 && (!k || !ko)) || endbit < 1 || endbit > (int)(8 * sizeof(K))) return LAMG_E_INVALID_ARG;
+  if (n == 0) return LAMG_OK;
+  try {
+    DevTmp t(sortk::sort_scratch_bytes<K, V>(n));
+    sortk::radix_sort<K, V>(nullptr, k, ko, v, vo, n, (unsigned)endbit, t.p);
+    LAMG_HIP(hipGetLastError());
+    LAMG_HIP(hipStreamSynchronize(nullptr));
+  } catch (const DevError&) {
+    return LAMG_E_DEVICE;
+  }
+  return LAMG_OK;
+}
 }  // namespace
 
 extern "C" {
+
+lamg_status lamg_t_sort_pairs64(int64_t n, const uint64_t* keys, const double* vals, uint64_t* keys_out,
+                                double* vals_out, int32_t endbit) {
+  if (n > 0 && (!vals || !vals_out)) return LAMG_E_INVALID_ARG;
+  return sort_entry<uint64_t, double>(n, keys, vals, keys_out, vals_out, endbit);
+}
+lamg_status lamg_t_sort_pairs32(int64_t n, const uint32_t* keys, const int32_t* vals, uint32_t* keys_out,
+                                int32_t* vals_out, int32_t endbit) {
+  if (n > 0 && (!vals || !vals_out)) return LAMG_E_INVALID_ARG;
+  return sort_entry<uint32_t, int32_t>(n, keys, vals, keys_out, vals_out, endbit);
+}
+lamg_status lamg_t_sort_f64(int64_t n, const double* keys, double* keys_out) {
+  return sort_entry<double, sortk::NoVal>(n, keys, nullptr, keys_out, nullptr, 64);
+}
+lamg_status lamg_t_excl_scan(int64_t n, const int32_t* in, int32_t* out) {
+  if (n < 0 || !out || (n > 0 && !in)) return LAMG_E_INVALID_ARG;
+  try {
+    DevTmp t(sortk::scan_scratch(n) * sizeof(int));
+    sortk::exclusive_scan(nullptr, in, out, n, (int*)t.p);
+    LAMG_HIP(hipGetLastError());
+    LAMG_HIP(hipStreamSynchronize(nullptr));
+  } catch (const DevError&) {
+    return LAMG_E_DEVICE;
+  }
+  return LAMG_OK;
+}
 
 int lamg_t_num_levels(lamg_handle h) { return h ? (int)h->H.lv.size() : 0; }
 int lamg_t_coarsest_relax(lamg_handle h) { return h && h->H.coarsest_relax ? 1 : 0; }
