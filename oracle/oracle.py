@@ -315,7 +315,7 @@ class Hierarchy:
 
     def __del__(self):
         h = getattr(self, "h", None)
-        if h:
+        if h and lib is not None:  # module globals may be gone at interpreter exit
             lib().ora_free(h)
             self.h = None
 

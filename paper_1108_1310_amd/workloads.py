@@ -238,6 +238,25 @@ def erdos_renyi(n: int, mean_deg: float, seed: int) -> Graph:
     return Graph(f"er_{n}", n2, eu, ev, w)
 
 
+def er_with_hubs(n: int, mean_deg: float, hub_degrees, seed: int) -> Graph:
+    """G(n, p) background plus hubs: node i (i < len(hub_degrees)) joined to
+    hub_degrees[i] distinct random other nodes (a test input with rows far
+    longer than a relaxation chunk)."""
+    g = erdos_renyi(n, mean_deg, seed)
+    rng = _rng(seed, _S_LABEL + 1)
+    eu, ev = [g.eu.astype(np.int64)], [g.ev.astype(np.int64)]
+    for h, d in enumerate(hub_degrees):
+        nb = rng.choice(np.arange(len(hub_degrees), g.n), size=int(d), replace=False)
+        eu.append(np.full(nb.shape[0], h, np.int64))
+        ev.append(nb)
+    a, b = np.concatenate(eu), np.concatenate(ev)
+    key = np.unique(np.minimum(a, b) * g.n + np.maximum(a, b))
+    eu2 = (key // g.n).astype(np.int32)
+    ev2 = (key % g.n).astype(np.int32)
+    w = _rng(seed, _S_WEIGHT + 8).uniform(0.1, 1.0, eu2.shape[0])
+    return Graph(f"er_hubs_{n}", g.n, eu2, ev2, w)
+
+
 def graph_batch(count: int = 256, nmin: float = 1e3, nmax: float = 2e5,
                 seed: int = SEEDS["graph_batch"]) -> list[Graph]:
     """Uneven batch: type g mod 3 in {2-D grid, ER(mean deg 8), RGG}."""

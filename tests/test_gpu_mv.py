@@ -61,15 +61,17 @@ def test_mv_cycle_matches_oracle(ora, lg, name, k):
     B = _block(n, k, 5)
     X1 = Hg.mv_cycle(B, np.zeros((n, k))).cpu().numpy()
     X2 = Hg.mv_cycle(B, X1).cpu().numpy()
-    # The recombination Gram sums (eq. recomb) are reduced in another order
-    # than the oracle's left-to-right sums.  On the anisotropic grid (weights
-    # down to 5e-5) the cycle amplifies that rounding to ~1e-12 relative.
-    tol = 1e-10 if name.startswith("grid3d") else 1e-12
+    # Element by element, |x_g - x_o|_i <= tol * max|x_o|.  The recombination
+    # Gram sums (eq. recomb) are reduced in another order than the oracle's
+    # left-to-right sums.  Measured: <= 2.6e-14 on the 2-D grid, RGG, Chung-Lu
+    # and ER graphs; 2.5e-12 and 3.4e-12 on the anisotropic 3-D grids, whose
+    # weights span 1 to 5e-5 and whose cycle carries that rounding further.
+    tol = 1e-11 if name.startswith("grid3d") else 1e-13
     for j in range(k):
         xo = Ho.cycle(B[:, j], np.zeros(n))
-        assert np.linalg.norm(X1[:, j] - xo) <= tol * np.linalg.norm(xo), j
+        assert np.abs(X1[:, j] - xo).max() <= tol * np.abs(xo).max(), j
         xo2 = Ho.cycle(B[:, j], X1[:, j])
-        assert np.linalg.norm(X2[:, j] - xo2) <= 10 * tol * np.linalg.norm(xo2), j
+        assert np.abs(X2[:, j] - xo2).max() <= tol * np.abs(xo2).max(), j
 
 
 @pytest.mark.parametrize("name,k,tail", [("grid3d16", 4, True), ("grid3d16", 3, False), ("chung_lu16k", 8, False),

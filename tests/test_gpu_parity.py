@@ -30,6 +30,8 @@ def _graphs():
     out["grid3d16"] = (g.n, g.eu, g.ev, g.w)
     g = W.erdos_renyi(20000, 8.0, 3)
     out["er20k"] = (g.n, g.eu, g.ev, g.w)
+    g = W.er_with_hubs(60000, 6.0, [40000, 5000, 3000, 1000, 600], 11)
+    out["er_hubs60k"] = (g.n, g.eu, g.ev, g.w)
     return out
 
 
@@ -101,10 +103,13 @@ def test_colouring_kernel_bit_exact(ora, lg):
         assert np.array_equal(cg, ora.colour(A, seed=seed, level=level))
 
 
-@pytest.mark.parametrize("name", ["grid64", "chung_lu16k"])
+@pytest.mark.parametrize("name", ["grid64", "chung_lu16k", "er_hubs60k"])
 def test_relaxation_kernels_bit_exact(ora, lg, name):
     """Multicolour GS sweeps (FP64, FP32) and the residual on the oracle's
-    colour-ordered finest level, including rows longer than 64 entries."""
+    colour-ordered finest level, including rows longer than 64 entries (one
+    wavefront each), rows longer than 512 (a workgroup, chunks spread over
+    its wavefronts) and one of 40,001 entries (more chunks than one pass of
+    the workgroup stages)."""
     _print_case(name)
     n, eu, ev, w = graphs()[name]
     Ho = ora.Hierarchy(n, eu, ev, w)
@@ -127,8 +132,14 @@ def test_relaxation_kernels_bit_exact(ora, lg, name):
     assert np.array_equal(xg32, xo32)
 
 
-@pytest.mark.parametrize("name", ["random3k", "grid64", "chung_lu16k", "rgg16k", "er20k"])
+@pytest.mark.parametrize("name", ["random3k", "grid64", "chung_lu16k", "rgg16k", "er20k", "grid3d16"])
 def test_one_cycle_matches_oracle(ora, lg, name):
+    """One cycle, then a second from its result, element by element against
+    the oracle: |x_g - x_o|_i <= tol * max|x_o|.  The GS sweeps are bit-exact;
+    the recombination sums and norms are reduced in another order, and the
+    cycle carries that rounding.  Measured: <= 1.4e-14 on the 2-D grid, RGG,
+    Chung-Lu and ER graphs, 9e-13 on the anisotropic 3-D grid, whose weights
+    span 1 to 5e-5, hence tol 1e-13 and 1e-11 there."""
     _print_case(name)
     n, eu, ev, w = graphs()[name]
     Ho = ora.Hierarchy(n, eu, ev, w)
@@ -137,12 +148,13 @@ def test_one_cycle_matches_oracle(ora, lg, name):
     b = rng.standard_normal(n)
     b -= b.mean()
     x0 = np.zeros(n)
+    tol = 1e-11 if name.startswith("grid3d") else 1e-13
     xo = Ho.cycle(b, x0)
     xg = Hg.cycle(b, x0).cpu().numpy()
-    assert np.linalg.norm(xg - xo) <= 1e-12 * np.linalg.norm(xo)
+    assert np.abs(xg - xo).max() <= tol * np.abs(xo).max()
     xo2 = Ho.cycle(b, xo)
     xg2 = Hg.cycle(b, xg).cpu().numpy()
-    assert np.linalg.norm(xg2 - xo2) <= 1e-11 * np.linalg.norm(xo2)
+    assert np.abs(xg2 - xo2).max() <= tol * np.abs(xo2).max()
 
 
 @pytest.mark.parametrize("name", ["random3k", "grid64", "chung_lu16k", "rgg16k", "grid3d16", "er20k"])
