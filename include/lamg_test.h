@@ -126,6 +126,11 @@ lamg_status lamg_t_hub_info(lamg_handle h, int32_t l, int64_t* out);
  * colour order, FP64 (precision 0, the level's FP64 matrix) or FP32
  * (precision 1, its FP32 copy). */
 lamg_status lamg_t_level_gs(lamg_handle h, int32_t l, int32_t precision, int32_t sweeps, const void* b, void* x);
+/* The same from a zero iterate as the cycle runs it below the finest level:
+ * x is zero-filled here and the first sweep skips the gathers of colours not
+ * yet relaxed (they hold +0); the result must equal lamg_t_level_gs on a
+ * zero x bit for bit. */
+lamg_status lamg_t_level_gs_zero(lamg_handle h, int32_t l, int32_t precision, int32_t sweeps, const void* b, void* x);
 
 /* Instrumentation of the relaxation kernel (Section 3.1.1, eq. gs) and of the
  * residual kernel.  lamg_t_prof_enable(1) clears the counters and brackets

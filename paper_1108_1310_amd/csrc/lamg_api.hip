@@ -72,8 +72,9 @@ void body(Hierarchy* H, int l, int sub, std::vector<int64_t>& count) {
   Vecs<T>& v = Prec<T>::v(L);
   if (l == Lc) {
     if (H->coarsest_relax) {  // relaxation converges rapidly on this level
+      // below the finest level a visit starts from the zero fill of its caller
       for (int i = 0; i < H->o.coarsest_sweeps; ++i)
-        gs_sweep<T>(s, L, Prec<T>::val(L), Prec<T>::diag(L), v.b, v.x);
+        gs_sweep<T>(s, L, Prec<T>::val(L), Prec<T>::diag(L), v.b, v.x, l > 0 && i == 0);
       return;
     }
     if constexpr (sizeof(T) == 8) coarsest_solve(s, H, (const double*)v.b, (double*)v.x);
@@ -95,7 +96,7 @@ void body(Hierarchy* H, int l, int sub, std::vector<int64_t>& count) {
     return;
   }
   const bool rec = H->o.ec == LAMG_EC_RECOMBINE;
-  for (int i = 0; i < H->o.nu_pre; ++i) gs_sweep<T>(s, L, val, dg, v.b, v.x);
+  for (int i = 0; i < H->o.nu_pre; ++i) gs_sweep<T>(s, L, val, dg, v.b, v.x, l > 0 && sub == 0 && i == 0);
   T* r = rec ? v.R[sub] : v.r;
   residual<T>(s, L, val, dg, v.b, v.x, r);
   if (rec) hipLaunchKernelGGL(k_copy<T>, grid1(L.n), dim3(256), 0, s, L.n, (const T*)v.x, v.X[sub]);

@@ -273,9 +273,10 @@ constexpr int RED_BLOCKS = 512, RED_THREADS = 256;
 void build_tiles(Hierarchy* H, Level& L);
 // Relaxation and residual (FP64 / FP32), k vectors row-major for the multi-vector form.
 template <class T>
-void gs_colour(hipStream_t s, const Level& L, int c, const T* val, const T* diag, const T* b, T* x);
+void gs_colour(hipStream_t s, const Level& L, int c, const T* val, const T* diag, const T* b, T* x,
+               bool from_zero = false);
 template <class T>
-void gs_sweep(hipStream_t s, const Level& L, const T* val, const T* diag, const T* b, T* x);
+void gs_sweep(hipStream_t s, const Level& L, const T* val, const T* diag, const T* b, T* x, bool from_zero = false);
 template <class T>
 void residual(hipStream_t s, const Level& L, const T* val, const T* diag, const T* b, const T* x, T* r);
 void gs_multi_sweep(hipStream_t s, const Level& L, const double* b, double* X, int K);

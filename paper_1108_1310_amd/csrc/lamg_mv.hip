@@ -15,6 +15,7 @@
 // FP64, one cycle from zero on the zero-mean R (FP64, or FP32 for the
 // refinement variant), X += correction for the columns still iterating.
 #include <algorithm>
+#include <climits>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -98,13 +99,15 @@ __device__ __attribute__((always_inline)) inline void store_mv(int u, size_t o, 
 // lane g handling the VW-wide column slices g, g + G, ... (the G lanes of a
 // row read one contiguous segment per entry).  Long rows (listed in lrows):
 // one wavefront per row, column slices one after the other.  The first nlb
-// blocks take the long rows.
+// blocks take the long rows.  zthr: rows >= zthr of x hold +0 (the first
+// sweep from a zero iterate), so their slices are taken as +0 without a
+// load; the terms and their order are unchanged.
 template <class T, int MODE, int VW>
 __global__ __launch_bounds__(MVT) void k_relax_mv(const int* __restrict__ rp, const int* __restrict__ ci,
                                                   const T* __restrict__ val, const T* __restrict__ diag,
                                                   const T* __restrict__ b, T* x, T* __restrict__ r,
                                                   const int* __restrict__ map, int k, int glog, int r0, int r1,
-                                                  const int* __restrict__ lrows, int nlong, int nlb) {
+                                                  const int* __restrict__ lrows, int nlong, int nlb, int zthr) {
   const int ncv = k / VW;
   int bid = blockIdx.x;
   if (bid < nlb) {
@@ -125,8 +128,12 @@ __global__ __launch_bounds__(MVT) void k_relax_mv(const int* __restrict__ rp, co
           const int t = c0 + lane + 64 * q;
           if (t < len) {
             const T w = val[p0 + t];
+            const int cj = ci[p0 + t];
             T xv[VW];
-            ldv<T, VW>(x + (size_t)ci[p0 + t] * k + cv * VW, xv);
+            if (cj < zthr) ldv<T, VW>(x + (size_t)cj * k + cv * VW, xv);
+            else
+#pragma unroll
+              for (int i = 0; i < VW; ++i) xv[i] = T(0);
 #pragma unroll
             for (int i = 0; i < VW; ++i) s[i] += w * xv[i];
           }
@@ -157,7 +164,12 @@ __global__ __launch_bounds__(MVT) void k_relax_mv(const int* __restrict__ rp, co
 #pragma unroll
       for (int q = 0; q < 4; ++q) { cj[q] = ci[p0 + t + q]; wj[q] = val[p0 + t + q]; }
 #pragma unroll
-      for (int q = 0; q < 4; ++q) ldv<T, VW>(x + (size_t)cj[q] * k + cv * VW, xv[q]);
+      for (int q = 0; q < 4; ++q) {
+        if (cj[q] < zthr) ldv<T, VW>(x + (size_t)cj[q] * k + cv * VW, xv[q]);
+        else
+#pragma unroll
+          for (int i = 0; i < VW; ++i) xv[q][i] = T(0);
+      }
 #pragma unroll
       for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -165,8 +177,12 @@ __global__ __launch_bounds__(MVT) void k_relax_mv(const int* __restrict__ rp, co
     }
     for (; t < len; ++t) {
       const T w = val[p0 + t];
+      const int cj = ci[p0 + t];
       T xv[VW];
-      ldv<T, VW>(x + (size_t)ci[p0 + t] * k + cv * VW, xv);
+      if (cj < zthr) ldv<T, VW>(x + (size_t)cj * k + cv * VW, xv);
+      else
+#pragma unroll
+        for (int i = 0; i < VW; ++i) xv[i] = T(0);
 #pragma unroll
       for (int i = 0; i < VW; ++i) s[i] += w * xv[i];
     }
@@ -183,7 +199,7 @@ int mv_width(int k) {
 
 template <class T, int MODE>
 void relax_mv(hipStream_t s, const int* rp, const int* ci, const T* val, const T* diag, const T* b, T* x, T* r,
-              const int* map, int k, int r0, int r1, const Tiles& t) {
+              const int* map, int k, int r0, int r1, const Tiles& t, int zthr = INT_MAX) {
   if (r1 <= r0) return;
   const int vw = mv_width<T>(k);
   const int ncv = k / vw;
@@ -203,13 +219,13 @@ void relax_mv(hipStream_t s, const int* rp, const int* ci, const T* val, const T
   if (prof) prof_count(kid, bytes);
   if (vw == 1)
     hipLaunchKernelGGL((k_relax_mv<T, MODE, 1>), dim3(grid), dim3(MVT), 0, s, rp, ci, val, diag, b, x, r, map, k, glog,
-                       r0, r1, lr, t.nlong, nlb);
+                       r0, r1, lr, t.nlong, nlb, zthr);
   else if constexpr (sizeof(T) == 8)
     hipLaunchKernelGGL((k_relax_mv<T, MODE, 2>), dim3(grid), dim3(MVT), 0, s, rp, ci, val, diag, b, x, r, map, k, glog,
-                       r0, r1, lr, t.nlong, nlb);
+                       r0, r1, lr, t.nlong, nlb, zthr);
   else
     hipLaunchKernelGGL((k_relax_mv<T, MODE, 4>), dim3(grid), dim3(MVT), 0, s, rp, ci, val, diag, b, x, r, map, k, glog,
-                       r0, r1, lr, t.nlong, nlb);
+                       r0, r1, lr, t.nlong, nlb, zthr);
   LAMG_HIP(hipGetLastError());
 }
 
@@ -227,12 +243,13 @@ template <> struct PrecM<float> {
   static const float* er(const Level& L) { return L.er_val32; }
 };
 
+// from_zero: x is +0 on entry, so colour c gathers only colours < c
 template <class T>
-void gs_sweep_mv(hipStream_t s, const Level& L, int k, const T* b, T* x) {
+void gs_sweep_mv(hipStream_t s, const Level& L, int k, const T* b, T* x, bool from_zero = false) {
   prof_begin(s, sizeof(T) == 4 ? 6 : 4);
   for (int c = 0; c < L.ncol; ++c)
     relax_mv<T, 0>(s, L.rp, L.ci, PrecM<T>::val(L), PrecM<T>::diag(L), b, x, (T*)nullptr, nullptr, k, L.cptr[c],
-                   L.cptr[c + 1], L.tiles[c]);
+                   L.cptr[c + 1], L.tiles[c], from_zero ? L.cptr[c] : INT_MAX);
   prof_end(s);
 }
 template <class T>
@@ -451,7 +468,10 @@ void body_mv(Hierarchy* H, int l, int sub, std::vector<int64_t>& count) {
   Vecs<T>& v = PrecM<T>::v(H, l);
   if (l == Lc) {
     if (H->coarsest_relax) {
-      for (int i = 0; i < H->o.coarsest_sweeps; ++i) gs_sweep_mv<T>(s, L, k, v.b, v.x);
+      // x = 0 on entry below the finest level (the caller's fill) and at the
+      // finest in correction form
+      const bool z = l > 0 || H->top_res_known;
+      for (int i = 0; i < H->o.coarsest_sweeps; ++i) gs_sweep_mv<T>(s, L, k, v.b, v.x, z && i == 0);
       return;
     }
     hipLaunchKernelGGL(k_dense_solve_mv<T>, dim3(k), dim3(256), H->nL * sizeof(double), s, H->nL, k,
@@ -474,7 +494,8 @@ void body_mv(Hierarchy* H, int l, int sub, std::vector<int64_t>& count) {
     return;
   }
   const bool rec = H->o.ec == LAMG_EC_RECOMBINE;
-  for (int i = 0; i < H->o.nu_pre; ++i) gs_sweep_mv<T>(s, L, k, v.b, v.x);
+  const bool z = (l > 0 || H->top_res_known) && sub == 0;
+  for (int i = 0; i < H->o.nu_pre; ++i) gs_sweep_mv<T>(s, L, k, v.b, v.x, z && i == 0);
   T* r = rec ? v.R[sub] : v.r;
   residual_mv<T>(s, L, k, v.b, v.x, r);
   if (rec) hipLaunchKernelGGL(k_copy_mv<T>, gridn(nk), dim3(MVT), 0, s, nk, (const T*)v.x, v.X[sub]);

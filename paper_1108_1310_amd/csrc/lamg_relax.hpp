@@ -18,6 +18,11 @@ namespace lamg {
 // it writes are never read in the same launch.
 // MODE 0: GS update; MODE 1: residual; MODE 2: elimination restriction
 // out_u = x_{map(u)} + sum (the gathered vector is the fine residual).
+// zthr: the gathered vector is known to hold +0 at every index >= zthr (the
+// first sweep after a zero fill: colours at or above the current one are
+// untouched), so those entries take the constant +0 instead of a load.  The
+// product w * (+0) and its place in the sum are unchanged, so the result is
+// bitwise the same; only the gathers are saved.  INT_MAX: gather every entry.
 // The per-row operands are loaded as soon as the row is known (relax_pre),
 // so that their latency overlaps the gathers; none of them is written in
 // the same launch (a GS pass writes only x of its own colour, which it does
@@ -52,7 +57,7 @@ __device__ inline void relax_store(int u, T s, RowOps<T> o, T* x, T* __restrict_
 // then the butterfly folds the 64 partials.
 template <class T>
 __device__ inline T chunk_sum(const int* __restrict__ ci, const T* __restrict__ val, const T* x, int p0, int c0,
-                              int len, int lane) {
+                              int len, int lane, int zthr) {
   constexpr int UNR = ROW_CHUNK / 64;
   int cj[UNR];
   T wj[UNR], xj[UNR];
@@ -63,7 +68,7 @@ __device__ inline T chunk_sum(const int* __restrict__ ci, const T* __restrict__ 
     wj[q] = t < len ? val[p0 + t] : T(0);
   }
 #pragma unroll
-  for (int q = 0; q < UNR; ++q) xj[q] = x[cj[q]];
+  for (int q = 0; q < UNR; ++q) xj[q] = cj[q] < zthr ? x[cj[q]] : T(0);
   T s = 0;
 #pragma unroll
   for (int q = 0; q < UNR; ++q)
@@ -76,7 +81,7 @@ __global__ __launch_bounds__(RELAX_THREADS) void k_relax(
     const int* __restrict__ rp, const int* __restrict__ ci, const T* __restrict__ val,
     const T* __restrict__ diag, const T* __restrict__ b, T* x, T* __restrict__ r,
     const int4* __restrict__ vlong, int nvlong, const int4* __restrict__ med, int nmed, int nmed_blocks,
-    const int4* __restrict__ sblk, int nstream, const int* __restrict__ map) {
+    const int4* __restrict__ sblk, int nstream, const int* __restrict__ map, int zthr) {
   constexpr int PER = TILE_NNZ / RELAX_THREADS;  // entries per thread in a stream tile
   constexpr int MAXC = 64;                       // chunk sums staged per pass
   __shared__ T prod[TILE_NNZ];
@@ -95,7 +100,7 @@ __global__ __launch_bounds__(RELAX_THREADS) void k_relax(
     for (int pass = 0; pass < nch; pass += MAXC) {
       const int lim = min(MAXC, nch - pass);
       for (int k = wv; k < lim; k += LONG_PER_BLOCK) {
-        const T sk = chunk_sum<T>(ci, val, x, p0, (pass + k) * ROW_CHUNK, len, lane);
+        const T sk = chunk_sum<T>(ci, val, x, p0, (pass + k) * ROW_CHUNK, len, lane, zthr);
         if (lane == 0) csum[k] = sk;
       }
       __syncthreads();
@@ -114,7 +119,7 @@ __global__ __launch_bounds__(RELAX_THREADS) void k_relax(
     const int u = e.x, p0 = e.y, len = e.z;
     RowOps<T> o{};
     if (lane == 0) o = relax_pre<T, MODE>(u, diag, b, x, map);
-    const T sk = chunk_sum<T>(ci, val, x, p0, 0, len, lane);
+    const T sk = chunk_sum<T>(ci, val, x, p0, 0, len, lane, zthr);
     T total = 0;
     total += sk;
     if (lane == 0) relax_store<T, MODE>(u, total, o, x, r);
@@ -138,7 +143,7 @@ __global__ __launch_bounds__(RELAX_THREADS) void k_relax(
     wj[q] = j < cnt ? val[base + j] : T(0);
   }
 #pragma unroll
-  for (int q = 0; q < PER; ++q) xj[q] = x[cj[q]];
+  for (int q = 0; q < PER; ++q) xj[q] = cj[q] < zthr ? x[cj[q]] : T(0);
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int j = threadIdx.x + q * RELAX_THREADS;

@@ -2,6 +2,7 @@
 // rows, aggregation / elimination transfers, deterministic reductions for
 // iterate recombination, mean removal and norms, and the coarsest solve.
 #include <algorithm>
+#include <climits>
 #include <cmath>
 
 #include "lamg_device.hpp"
@@ -86,12 +87,13 @@ void prof_flush() {
 
 template <class T, int MODE>
 static void launch_relax(hipStream_t s, const int* rp, const int* ci, const Tiles& t, const T* val, const T* diag,
-                         const T* b, T* x, T* r, const int* map = nullptr) {
+                         const T* b, T* x, T* r, const int* map = nullptr, int zthr = INT_MAX) {
   const int grid = t.blocks();
   if (grid == 0) return;
   if (MODE == 2) {
     hipLaunchKernelGGL((k_relax<T, MODE>), dim3(grid), dim3(RELAX_THREADS), 0, s, rp, ci, val, diag, b, x, r,
-                       (const int4*)t.vlong, t.nvlong, (const int4*)t.med, t.nmed, t.nmed_blocks, (const int4*)t.stream, t.nstream, map);
+                       (const int4*)t.vlong, t.nvlong, (const int4*)t.med, t.nmed, t.nmed_blocks, (const int4*)t.stream, t.nstream, map,
+                       zthr);
     LAMG_HIP(hipGetLastError());
     return;
   }
@@ -103,7 +105,8 @@ static void launch_relax(hipStream_t s, const int* rp, const int* ci, const Tile
                         3 * t.rows * (int64_t)sizeof(T);
   if (prof) prof_count(kid, bytes);
   hipLaunchKernelGGL((k_relax<T, MODE>), dim3(grid), dim3(RELAX_THREADS), 0, s, rp, ci, val, diag, b, x, r,
-                     (const int4*)t.vlong, t.nvlong, (const int4*)t.med, t.nmed, t.nmed_blocks, (const int4*)t.stream, t.nstream, map);
+                     (const int4*)t.vlong, t.nvlong, (const int4*)t.med, t.nmed, t.nmed_blocks, (const int4*)t.stream, t.nstream, map,
+                       zthr);
   LAMG_HIP(hipGetLastError());
 }
 
@@ -306,14 +309,16 @@ static void hub_sweep(hipStream_t s, const Level& L, const T* val, const T* diag
 }
 
 template <class T>
-void gs_colour(hipStream_t s, const Level& L, int c, const T* val, const T* diag, const T* b, T* x) {
-  launch_relax<T, 0>(s, L.rp, L.ci, L.tiles[c], val, diag, b, x, (T*)nullptr);
+void gs_colour(hipStream_t s, const Level& L, int c, const T* val, const T* diag, const T* b, T* x, bool from_zero) {
+  // from a zero iterate, colours c and above still hold +0: no gathers there
+  launch_relax<T, 0>(s, L.rp, L.ci, L.tiles[c], val, diag, b, x, (T*)nullptr, nullptr,
+                     from_zero ? L.cptr[c] : INT_MAX);
 }
 template <class T>
-void gs_sweep(hipStream_t s, const Level& L, const T* val, const T* diag, const T* b, T* x) {
+void gs_sweep(hipStream_t s, const Level& L, const T* val, const T* diag, const T* b, T* x, bool from_zero) {
   const int K = L.hub_k >= 0 ? L.hub_k : L.ncol;
   prof_begin(s, sizeof(T) == 4 ? 2 : 0);
-  for (int c = 0; c < K; ++c) gs_colour<T>(s, L, c, val, diag, b, x);
+  for (int c = 0; c < K; ++c) gs_colour<T>(s, L, c, val, diag, b, x, from_zero);
   prof_end(s);
   if (K < L.ncol) {
     prof_begin(s, sizeof(T) == 4 ? 9 : 8);
@@ -327,10 +332,11 @@ void residual(hipStream_t s, const Level& L, const T* val, const T* diag, const 
   launch_relax<T, 1>(s, L.rp, L.ci, L.all, val, diag, b, (T*)x, r);
   prof_end(s);
 }
-template void gs_colour<double>(hipStream_t, const Level&, int, const double*, const double*, const double*, double*);
-template void gs_colour<float>(hipStream_t, const Level&, int, const float*, const float*, const float*, float*);
-template void gs_sweep<double>(hipStream_t, const Level&, const double*, const double*, const double*, double*);
-template void gs_sweep<float>(hipStream_t, const Level&, const float*, const float*, const float*, float*);
+template void gs_colour<double>(hipStream_t, const Level&, int, const double*, const double*, const double*, double*,
+                                bool);
+template void gs_colour<float>(hipStream_t, const Level&, int, const float*, const float*, const float*, float*, bool);
+template void gs_sweep<double>(hipStream_t, const Level&, const double*, const double*, const double*, double*, bool);
+template void gs_sweep<float>(hipStream_t, const Level&, const float*, const float*, const float*, float*, bool);
 template void residual<double>(hipStream_t, const Level&, const double*, const double*, const double*, const double*, double*);
 template void residual<float>(hipStream_t, const Level&, const float*, const float*, const float*, const float*, float*);
 

@@ -227,6 +227,27 @@ lamg_status lamg_t_level_gs(lamg_handle h, int32_t l, int32_t precision, int32_t
   return LAMG_OK;
 }
 
+lamg_status lamg_t_level_gs_zero(lamg_handle h, int32_t l, int32_t precision, int32_t sweeps, const void* b,
+                                 void* x) {
+  if (!h || !x || l < 0 || l >= (int)h->H.lv.size() || sweeps < 1 || (precision != 0 && precision != 1))
+    return LAMG_E_INVALID_ARG;
+  try {
+    Hierarchy* H = &h->H;
+    const Level& L = H->lv[l];
+    const size_t bytes = (size_t)L.n * (precision == 0 ? sizeof(double) : sizeof(float));
+    LAMG_HIP(hipMemsetAsync(x, 0, bytes, H->s));
+    for (int i = 0; i < sweeps; ++i) {
+      if (precision == 0) gs_sweep<double>(H->s, L, L.val, L.diag, (const double*)b, (double*)x, i == 0);
+      else gs_sweep<float>(H->s, L, L.val32, L.diag32, (const float*)b, (float*)x, i == 0);
+    }
+    LAMG_HIP(hipStreamSynchronize(H->s));
+  } catch (const DevError& e) {
+    set_last_error("lamg_t_level_gs_zero", e.e);
+    return LAMG_E_DEVICE;
+  }
+  return LAMG_OK;
+}
+
 lamg_status lamg_t_gs32(int32_t n, const int32_t* rp, const int32_t* ci, const float* val, const float* diag,
                         int32_t ncol, const int32_t* cptr, const float* b, float* x, int32_t sweeps, void* stream) {
   if (n < 1 || !rp || !ci || !val || !diag || !x || ncol < 1 || !cptr || cptr[0] != 0 || cptr[ncol] != n)

@@ -111,6 +111,7 @@ def lib():
             "lamg_t_colour": (C.c_int, [i32, vp, vp, u64, i32, vp, vp]),
             "lamg_t_hub_info": (C.c_int, [vp, i32, vp]),
             "lamg_t_level_gs": (C.c_int, [vp, i32, i32, i32, vp, vp]),
+            "lamg_t_level_gs_zero": (C.c_int, [vp, i32, i32, i32, vp, vp]),
             "lamg_t_prof_enable": (None, [C.c_int]),
             "lamg_t_prof_read": (C.c_int, [C.c_int, C.POINTER(d), C.POINTER(i64), C.POINTER(i64)]),
         }
@@ -355,6 +356,16 @@ class Hierarchy:
         x = _dev(x_perm, t).clone().contiguous()
         _check(lib().lamg_t_level_gs(self.h, l, precision, sweeps, None if b is None else _ptr(b), _ptr(x)),
                "lamg_t_level_gs")
+        return x
+
+    def level_gs_zero(self, l: int, b_perm, sweeps: int = 1, precision: int = 0):
+        """level_gs from a zero iterate with the first sweep's gathers of
+        untouched colours skipped, as inside the cycle."""
+        t = torch.float64 if precision == 0 else torch.float32
+        b = None if b_perm is None else _dev(b_perm, t).contiguous()
+        x = torch.empty(self.dims(l)["n"], dtype=t, device="cuda")
+        _check(lib().lamg_t_level_gs_zero(self.h, l, precision, sweeps, None if b is None else _ptr(b), _ptr(x)),
+               "lamg_t_level_gs_zero")
         return x
 
     def cycle(self, b_perm, x_perm):

@@ -132,6 +132,25 @@ def test_relaxation_kernels_bit_exact(ora, lg, name):
     assert np.array_equal(xg32, xo32)
 
 
+@pytest.mark.parametrize("name", ["grid64", "chung_lu16k", "rgg16k", "er_hubs60k"])
+def test_gs_from_zero_bit_exact(lg, name):
+    """Below the finest level the cycle's first sweep starts from the zero
+    fill and skips the gathers of colours not yet relaxed (they hold +0):
+    the sweeps must equal the plain ones from a zero iterate bit for bit, on
+    every level, hub path included, FP64 and FP32."""
+    _print_case(name)
+    n, eu, ev, w = graphs()[name]
+    Hg = lg.Hierarchy(n, eu, ev, w)
+    rng = np.random.default_rng(7)
+    for l in range(Hg.num_levels):
+        nl = Hg.dims(l)["n"]
+        b = rng.standard_normal(nl)
+        for prec in (0, 1):
+            xa = Hg.level_gs(l, b, np.zeros(nl), sweeps=3, precision=prec).cpu().numpy()
+            xb = Hg.level_gs_zero(l, b, sweeps=3, precision=prec).cpu().numpy()
+            assert np.array_equal(xa.view(np.uint8), xb.view(np.uint8)), (l, prec)
+
+
 @pytest.mark.parametrize("name", ["random3k", "grid64", "chung_lu16k", "rgg16k", "er20k", "grid3d16"])
 def test_one_cycle_matches_oracle(ora, lg, name):
     """One cycle, then a second from its result, element by element against
