@@ -235,7 +235,7 @@ constexpr int PROF_KERNELS = 16;
 // Spans: prof_begin records the opening event of a run of launches of one
 // kernel, prof_count adds each launch (and its algorithmic bytes) of that
 // kernel to the open span, prof_end records the closing event.
-void prof_begin(hipStream_t s, int kernel);
+void prof_begin(hipStream_t s, int kernel, int launches = 1);
 void prof_count(int kernel, int64_t bytes);
 void prof_end(hipStream_t s);
 bool prof_on();

@@ -246,7 +246,7 @@ template <> struct PrecM<float> {
 // from_zero: x is +0 on entry, so colour c gathers only colours < c
 template <class T>
 void gs_sweep_mv(hipStream_t s, const Level& L, int k, const T* b, T* x, bool from_zero = false) {
-  prof_begin(s, sizeof(T) == 4 ? 6 : 4);
+  prof_begin(s, sizeof(T) == 4 ? 6 : 4, L.ncol);
   for (int c = 0; c < L.ncol; ++c)
     relax_mv<T, 0>(s, L.rp, L.ci, PrecM<T>::val(L), PrecM<T>::diag(L), b, x, (T*)nullptr, nullptr, k, L.cptr[c],
                    L.cptr[c + 1], L.tiles[c], from_zero ? L.cptr[c] : INT_MAX);

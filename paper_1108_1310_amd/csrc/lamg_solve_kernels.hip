@@ -16,10 +16,31 @@ namespace lamg {
 // ---------------------------------------------------------- instrumentation
 // A span is an event pair around a run of back-to-back launches of one
 // kernel (a whole sweep: every colour class of a level).  Kernels of one
-// stream run without gaps between them, so span time / launches is the
-// kernel's average duration; one pair per launch would add the event
-// markers' own latency to every launch.
+// stream run without gaps between them once they are queued, so span time /
+// launches is the kernel's average duration; one pair per launch would add
+// the event markers' own latency to every launch.  Instrumented cycles are
+// launched eagerly from the host, which enqueues a launch more slowly than
+// a short colour class runs; a span of several launches therefore starts
+// behind a hold (one wavefront sleeping for a bounded wall-clock time, 15 us
+// per launch of the span, 40 us for the multi-vector kernels, whose launches
+// take the host longer) during which the host queues the span's launches, so
+// that the span holds kernel time and not host gaps.
 namespace {
+__global__ void k_prof_hold(long long ticks) {
+  const long long t0 = wall_clock64();
+  // bounded twice: by the wall clock and by an iteration cap (~50 ms)
+  for (int i = 0; i < (1 << 20) && wall_clock64() - t0 < ticks; ++i) __builtin_amdgcn_s_sleep(2);
+}
+long long wall_ticks_per_us() {
+  static long long t = [] {
+    int dev = 0, khz = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
+      khz = 100000;  // 100 MHz
+    return std::max<long long>(1, khz / 1000);
+  }();
+  return t;
+}
 struct Pair {
   hipEvent_t a, b;
   int kid;
@@ -48,9 +69,14 @@ hipEvent_t new_event() {
 }
 }  // namespace
 bool prof_on() { return g_prof.on; }
-void prof_begin(hipStream_t s, int kernel) {
+void prof_begin(hipStream_t s, int kernel, int launches) {
   Prof& P = g_prof;
   if (!P.on || P.open) return;
+  if (launches > 1) {
+    const long long us = kernel >= 4 && kernel <= 7 ? 40 : 15;
+    hipLaunchKernelGGL(k_prof_hold, dim3(1), dim3(64), 0, s, (long long)launches * us * wall_ticks_per_us());
+    LAMG_HIP(hipGetLastError());
+  }
   P.cur = Pair{new_event(), nullptr, kernel, 0, 0};
   LAMG_HIP(hipEventRecord(P.cur.a, s));
   P.open = true;
@@ -317,7 +343,7 @@ void gs_colour(hipStream_t s, const Level& L, int c, const T* val, const T* diag
 template <class T>
 void gs_sweep(hipStream_t s, const Level& L, const T* val, const T* diag, const T* b, T* x, bool from_zero) {
   const int K = L.hub_k >= 0 ? L.hub_k : L.ncol;
-  prof_begin(s, sizeof(T) == 4 ? 2 : 0);
+  prof_begin(s, sizeof(T) == 4 ? 2 : 0, K);
   for (int c = 0; c < K; ++c) gs_colour<T>(s, L, c, val, diag, b, x, from_zero);
   prof_end(s);
   if (K < L.ncol) {
