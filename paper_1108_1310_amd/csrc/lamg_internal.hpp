@@ -30,17 +30,7 @@ constexpr uint64_t STREAM_COLOUR = 7, STREAM_TV = 3;
 // butterfly; shorter rows are summed sequentially in column order.
 constexpr int SHORT_ROW = 64;
 
-// Relaxation work list of one colour class (or of all rows), as three kinds
-// of 512-thread blocks launched together, longest work first:
-//   very long rows (> CHUNK entries): one block per row, its 512-entry chunks
-//     spread over the 8 wavefronts;
-//   medium rows (65..CHUNK entries): one wavefront per row, 8 rows per block;
-//   stream tiles: up to TILE_ROWS consecutive short rows whose entries fit in
-//     TILE_NNZ products staged in LDS, one thread per row for the sums.
-constexpr int RELAX_THREADS = 512;
-constexpr int TILE_ROWS = 512;
-constexpr int TILE_NNZ = 4096;
-constexpr int LONG_PER_BLOCK = RELAX_THREADS / 64;
+// Chunk length of the wavefront sum of a long row (the fixed summation order).
 constexpr int ROW_CHUNK = 512;
 
 // Hub sweep of a relaxed level.  On power-law levels the last colour classes

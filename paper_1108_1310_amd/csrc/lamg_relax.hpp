@@ -7,6 +7,25 @@
 
 namespace lamg {
 
+// Relaxation work list of one colour class (or of all rows), as three kinds
+// of 512-thread blocks launched together, longest work first:
+//   very long rows (> ROW_CHUNK entries): one block per row, its 512-entry
+//     chunks spread over the 8 wavefronts;
+//   medium rows (65..ROW_CHUNK entries): one wavefront per row, 8 rows per
+//     block;
+//   stream tiles: up to TILE_ROWS consecutive short rows whose entries fit in
+//     TILE_NNZ products staged in LDS, one thread per row for the sums.
+// Measured on the Chung-Lu 2^20 FP64 solve (threads / tile entries, ms per
+// solve): 512 / 4096 26.2, 512 / 2048 24.8, 512 / 1024 23.7, 512 / 512 24.0,
+// 256 / 2048 24.9, 256 / 1024 24.2, 128 / 1024 26.3, 1024 / 1024 30.5,
+// 1024 / 4096 30.1; RGG 2^20: 176.0, 167.6, 161.1, 159.9, 168.0, 163.1,
+// 164.1, 163.6, 177.3.  Small tiles give more blocks per colour class and
+// fewer dependent loads per thread; the long rows want 8 wavefronts.
+constexpr int RELAX_THREADS = 512;
+constexpr int TILE_ROWS = 512;
+constexpr int TILE_NNZ = 1024;
+constexpr int LONG_PER_BLOCK = RELAX_THREADS / 64;
+
 // One pass over a set of rows of a colour-ordered level.
 //   MODE 0: Gauss-Seidel update x_u <- (b_u + sum_v w_uv x_v) / a_uu (eq. gs)
 //   MODE 1: residual r_u <- (b_u + sum_v w_uv x_v) - a_uu x_u

@@ -13,6 +13,7 @@
 
 #include "lamg_device.hpp"
 #include "lamg_internal.hpp"
+#include "lamg_relax.hpp"
 #include "lamg_sort.hpp"
 
 namespace lamg {
