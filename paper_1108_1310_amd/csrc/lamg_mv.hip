@@ -98,8 +98,10 @@ __device__ __attribute__((always_inline)) inline void store_mv(int u, size_t o, 
 // level for n x k blocks.  Short rows: a group of G = 2^glog lanes per row,
 // lane g handling the VW-wide column slices g, g + G, ... (the G lanes of a
 // row read one contiguous segment per entry).  Long rows (listed in lrows):
-// one wavefront per row, column slices one after the other.  The first nlb
-// blocks take the long rows.  zthr: rows >= zthr of x hold +0 (the first
+// 2^wlog wavefronts per row, wavefront w taking the column slices w,
+// w + 2^wlog, ... one after the other (each slice's sums in the canonical
+// chunk order, so the split does not change a bit).  The first nlb blocks
+// take the long rows.  zthr: rows >= zthr of x hold +0 (the first
 // sweep from a zero iterate), so their slices are taken as +0 without a
 // load; the terms and their order are unchanged.
 template <class T, int MODE, int VW>
@@ -107,16 +109,18 @@ __global__ __launch_bounds__(MVT) void k_relax_mv(const int* __restrict__ rp, co
                                                   const T* __restrict__ val, const T* __restrict__ diag,
                                                   const T* __restrict__ b, T* x, T* __restrict__ r,
                                                   const int* __restrict__ map, int k, int glog, int r0, int r1,
-                                                  const int* __restrict__ lrows, int nlong, int nlb, int zthr) {
+                                                  const int* __restrict__ lrows, int nlong, int nlb, int zthr,
+                                                  int wlog) {
   const int ncv = k / VW;
   int bid = blockIdx.x;
   if (bid < nlb) {
-    const int idx = bid * (MVT / 64) + ((int)threadIdx.x >> 6);
+    const int wv = (int)threadIdx.x >> 6;
+    const int idx = bid * ((MVT / 64) >> wlog) + (wv >> wlog);
     if (idx >= nlong) return;
     const int lane = threadIdx.x & 63;
     const int u = lrows[idx];
     const int p0 = rp[u], len = rp[u + 1] - p0;
-    for (int cv = 0; cv < ncv; ++cv) {
+    for (int cv = wv & ((1 << wlog) - 1); cv < ncv; cv += 1 << wlog) {
       T tot[VW];
 #pragma unroll
       for (int i = 0; i < VW; ++i) tot[i] = T(0);
@@ -207,7 +211,11 @@ void relax_mv(hipStream_t s, const int* rp, const int* ci, const T* val, const T
   while ((1 << glog) < ncv && glog < 6) ++glog;
   const int rows_per_block = MVT >> glog;
   const int nsb = (r1 - r0 + rows_per_block - 1) / rows_per_block;
-  const int nlb = (t.nlong + MVT / 64 - 1) / (MVT / 64);
+  // long rows: up to all the block's wavefronts per row, one per column slice
+  int wlog = 0;
+  while ((2 << wlog) <= MVT / 64 && (2 << wlog) <= ncv) ++wlog;
+  const int rpb = (MVT / 64) >> wlog;
+  const int nlb = (t.nlong + rpb - 1) / rpb;
   const int grid = nlb + nsb;
   const bool prof = MODE != 2 && prof_on();
   const int kid = 4 + MODE + (sizeof(T) == 4 ? 2 : 0);
@@ -219,13 +227,13 @@ void relax_mv(hipStream_t s, const int* rp, const int* ci, const T* val, const T
   if (prof) prof_count(kid, bytes);
   if (vw == 1)
     hipLaunchKernelGGL((k_relax_mv<T, MODE, 1>), dim3(grid), dim3(MVT), 0, s, rp, ci, val, diag, b, x, r, map, k, glog,
-                       r0, r1, lr, t.nlong, nlb, zthr);
+                       r0, r1, lr, t.nlong, nlb, zthr, wlog);
   else if constexpr (sizeof(T) == 8)
     hipLaunchKernelGGL((k_relax_mv<T, MODE, 2>), dim3(grid), dim3(MVT), 0, s, rp, ci, val, diag, b, x, r, map, k, glog,
-                       r0, r1, lr, t.nlong, nlb, zthr);
+                       r0, r1, lr, t.nlong, nlb, zthr, wlog);
   else
     hipLaunchKernelGGL((k_relax_mv<T, MODE, 4>), dim3(grid), dim3(MVT), 0, s, rp, ci, val, diag, b, x, r, map, k, glog,
-                       r0, r1, lr, t.nlong, nlb, zthr);
+                       r0, r1, lr, t.nlong, nlb, zthr, wlog);
   LAMG_HIP(hipGetLastError());
 }
 
