@@ -450,6 +450,51 @@ __device__ __attribute__((always_inline)) inline bool tail_residual(const TailLe
   return false;
 }
 
+// x_r = sum_j M_rj b_j over the rows of the dense coarsest inverse: one
+// wavefront per row, lane l summing the entries l, l + 64, ... left to right,
+// the butterfly folding the 64 partials.  A wavefront takes four of its rows
+// at a time so that their loads are in flight together; each row's sum keeps
+// its order.  (FP64 programs only: the FP32 interpreter, at 128 VGPRs, was
+// measured slower with it.)
+template <class T, class BF, class XO>
+__device__ __attribute__((always_inline)) inline void coarse_rows(const double* __restrict__ M, int nL, BF bj,
+                                                                  XO x) {
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = tail_nw();
+  int r = wv;
+  if constexpr (sizeof(T) == 8)
+  for (; r + 3 * nw < nL; r += 4 * nw) {
+    const double* m0 = M + (size_t)r * nL;
+    const double* m1 = m0 + (size_t)nw * nL;
+    const double* m2 = m1 + (size_t)nw * nL;
+    const double* m3 = m2 + (size_t)nw * nL;
+    double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+    for (int j = lane; j < nL; j += 64) {
+      const double v = bj(j);
+      s0 += m0[j] * v;
+      s1 += m1[j] * v;
+      s2 += m2[j] * v;
+      s3 += m3[j] * v;
+    }
+    s0 = dev::wave_fold(s0);
+    s1 = dev::wave_fold(s1);
+    s2 = dev::wave_fold(s2);
+    s3 = dev::wave_fold(s3);
+    if (lane == 0) {
+      x[r] = (T)s0;
+      x[r + nw] = (T)s1;
+      x[r + 2 * nw] = (T)s2;
+      x[r + 3 * nw] = (T)s3;
+    }
+  }
+  for (; r < nL; r += nw) {
+    const double* row = M + (size_t)r * nL;
+    double s = 0;
+    for (int j = lane; j < nL; j += 64) s += row[j] * bj(j);
+    s = dev::wave_fold(s);
+    if (lane == 0) x[r] = (T)s;
+  }
+}
+
 // Fixed-order sum of NV values per thread over the workgroup: a butterfly
 // inside each wavefront, then the launch's wavefront sums left to right.
 template <int NV>
@@ -615,26 +660,13 @@ __device__ __attribute__((always_inline)) inline void run_ops(const TailParams& 
         // in LDS unless it already sits there or does not fit
         auto b = C.v(L, TV<T>::b(L));
         auto x = C.v(L, TV<T>::x(L));
-        const int wv = tid >> 6, lane = tid & 63;
         if (L.vres || (size_t)PP.nL * sizeof(double) > (size_t)budget) {
-          for (int r = wv; r < PP.nL; r += tail_nw()) {
-            const double* row = PP.Minv + (size_t)r * PP.nL;
-            double s = 0;
-            for (int j = lane; j < PP.nL; j += 64) s += row[j] * (double)b[j];
-            s = dev::wave_fold(s);
-            if (lane == 0) x[r] = (T)s;
-          }
+          coarse_rows<T>(PP.Minv, PP.nL, [&](int j) { return (double)b[j]; }, x);
           break;
         }
         for (int j = tid; j < PP.nL; j += tail_nt()) sb[j] = (double)b[j];
         __syncthreads();
-        for (int r = wv; r < PP.nL; r += tail_nw()) {
-          const double* row = PP.Minv + (size_t)r * PP.nL;
-          double s = 0;
-          for (int j = lane; j < PP.nL; j += 64) s += row[j] * sb[j];
-          s = dev::wave_fold(s);
-          if (lane == 0) x[r] = (T)s;
-        }
+        coarse_rows<T>(PP.Minv, PP.nL, [&](int j) { return sb[j]; }, x);
         break;
       }
       case OP_MEAN: {
