@@ -185,9 +185,9 @@ __device__ __attribute__((always_inline)) inline void tail_gs(const TailLevel& L
   }
 }
 // The same sweep with the level staged in LDS for its whole duration: x, b,
-// diagonal, row pointers and colour bounds always; column indices and weights
-// too when they fit.  One bulk load and one write-back replace the global
-// round trips of every colour phase.  Same sums in the same order.
+// diagonal, row pointers and colour bounds.  One bulk load and one write-back
+// replace the global round trips of every colour phase.  Same sums in the
+// same order.
 constexpr int TAIL_LDS = 152 * 1024;  // dynamic LDS of a tail workgroup (of 160 KB per CU)
 constexpr int TAIL_RES = 96 * 1024;   // of which at most this much holds resident levels
 template <class T>
@@ -197,10 +197,6 @@ __host__ __device__ inline size_t tail_vec_bytes(const TailLevel& L) {
 template <class T>
 __device__ inline bool tail_fits(const TailLevel& L, int budget) {
   return tail_vec_bytes<T>(L) <= (size_t)budget;
-}
-template <class T>
-__device__ inline bool tail_fits_all(const TailLevel& L, int budget) {
-  return tail_vec_bytes<T>(L) + (size_t)L.nnz * (sizeof(T) + sizeof(int)) + 16 <= (size_t)budget;
 }
 // Sweeps over a level staged in LDS: x, b, diagonal, row pointers, colour
 // and long-row bounds in LDS; weights and column indices in LDS or global.
@@ -240,24 +236,19 @@ __device__ __attribute__((always_inline)) inline void tail_gs_lds(const TailLeve
   LP<int> srp = (LP<int>)(sd + n);
   LP<int> scp = srp + n + 1;
   LP<int> slp = scp + nc + 1;
-  const bool all = tail_fits_all<T>(L, budget);
-  // 16-byte aligned start for the matrix entries
-  const unsigned mend = (unsigned)(size_t)(slp + nc + 1);
-  LP<T> sval = (LP<T>)(size_t)((mend + 15u) & ~15u);
-  LP<int> sci = (LP<int>)(sval + (all ? L.nnz : 0));
   const int tid = threadIdx.x;
   for (int i = tid; i < n; i += tail_nt()) { sx[i] = x[i]; sbv[i] = b[i]; sd[i] = dg[i]; srp[i] = L.rp[i]; }
   for (int i = tid; i <= nc; i += tail_nt()) { scp[i] = L.cptr[i]; slp[i] = L.lptr[i]; }
   if (tid == 0) srp[n] = L.rp[n];
-  if (all) {
-    const T* gv = TV<T>::val(L);
-    for (int i = tid; i < L.nnz; i += tail_nt()) { sval[i] = gv[i]; sci[i] = L.ci[i]; }
-  }
   __syncthreads();
-  if (all) lds_sweeps<T>(L, sweeps, sx, sbv, sd, srp, scp, slp, sval, sci);
-  else lds_sweeps<T>(L, sweeps, sx, sbv, sd, srp, scp, slp, TV<T>::val(L), L.ci);
+  // the weights and column indices stay where the level keeps them (global
+  // memory, or LDS for a resident level): a variant that also staged them
+  // here gave non-converging FP32 cycles in a 512-thread FP32 build (cause not
+  // found) and is not used
+  lds_sweeps<T>(L, sweeps, sx, sbv, sd, srp, scp, slp, TV<T>::val(L), L.ci);
   for (int i = tid; i < n; i += tail_nt()) x[i] = sx[i];
 }
+
 // Sweeps of a small level (n <= R * tail_nt() rows): thread t owns rows
 // t, t + tail_nt(), ... for the whole op.  Each row's colour, first RMAX
 // weights and column indices, b and diagonal stay in registers and x lives
