@@ -71,7 +71,7 @@ typedef struct lamg_options {
   int coarsest_sweeps;      /* GS sweeps solving such a coarsest level, 3 */
   int dense_max;            /* largest coarsest level solved densely, 8192 */
   int tail_max_n;           /* coarse levels with at most this many nodes (and all
-                               coarser ones) run inside one workgroup per entry, 4096;
+                               coarser ones) run inside one workgroup per entry, 3072;
                                0 = every level launches its own kernels */
   lamg_energy_correction ec;
   lamg_precision precision;

@@ -292,7 +292,11 @@ void lamg_options_default(lamg_options* o) {
   o->relax_fast_ratio = 0.1;
   o->coarsest_sweeps = 3;
   o->dense_max = 8192;
-  o->tail_max_n = 4096;
+  // measured 2048 / 3072 / 4096 (ms per solve; FP64, FP32): RGG 2^20 153.1 /
+  // 152.5 / 158.8, 138.4 / 135.6 / 136.7; 64^3 grid 461 / 470 / 469, 432 / 428 /
+  // 427; geometric multigrid 1024^2 6.75 / 6.78 / 7.64, 6.48 / 6.49 / 7.28;
+  // 64^2 grid at 3072 / 4096: 4.89 / 5.07, 4.98 / 5.10
+  o->tail_max_n = 3072;
   o->ec = LAMG_EC_RECOMBINE;
   o->precision = LAMG_FP64;
   o->tol = 1e-8;
