@@ -161,10 +161,11 @@ def timed_multi(H, B, precision, steps, warmup, lamg, instrument=False):
     lamg.prof_enable(instrument)
     cycles, col_cycles, byts, worst = 0, 0, 0, 0.0
     t0 = time.perf_counter()
-    for _ in range(steps):
+    for i in range(steps):
         X, info, cols, rc = H.solve_multi(B)
         if rc != 0:
             raise RuntimeError(f"multi-vector solve status {rc}")
+        print(f"[bench] multi-vector solve {i + 1}/{steps}: {info['cycles']} cycles", file=sys.stderr, flush=True)
         cycles += info["cycles"]
         col_cycles += int(cols["cycles"].sum())
         byts += info["bytes_moved"]
