@@ -71,17 +71,23 @@ def copy_calibration(nbytes):
 # (the split sets which colours the kernel's launches cover).
 TRAFFIC = {
     # profiles/gs_fp64_chung_lu_2p20.md: FETCH_SIZE 12074.8 KiB x 1.9999 + WRITE_SIZE 228.7 KiB x 1.0000
-    "chung_lu_2p20": {"bytes_per_launch": 24962600, "kernel_sha": "5eb2f1ecc43b20b6", "source": "lamg_relax.hpp",
-                      "hub_split": [24, 27]},
+    "chung_lu_2p20": {"bytes_per_launch": 24962600, "kernel_sha": "5eb2f1ecc43b20b6",
+                      "source": ["lamg_relax.hpp", "lamg_device.hpp"], "hub_split": [24, 27]},
     # profiles/mv_grid3d_128_k32.md: k_relax_mv<float, 0, 4>, FETCH_SIZE 6463.9 KiB x 1.9999 + WRITE_SIZE 1625.6 KiB x 1.0
-    "grid3d_128_k32": {"bytes_per_launch": 14902339, "kernel_sha": "6e584f88a5ee283d", "source": "lamg_mv.hip"},
+    "grid3d_128_k32": {"bytes_per_launch": 14902339, "kernel_sha": "6e584f88a5ee283d",
+                       "source": ["lamg_mv.hip", "lamg_device.hpp"]},
 }
 
 
-def kernel_source_hash(name="lamg_relax.hpp"):
+def kernel_source_hash(names=("lamg_relax.hpp", "lamg_device.hpp")):
+    """First 16 hex digits of the sha256 of the named kernel sources, read in
+    the order given (the kernel file and the device helpers it inlines)."""
     import hashlib
-    src = os.path.join(ROOT, "paper_1108_1310_amd", "csrc", name)
-    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for name in ([names] if isinstance(names, str) else names):
+        with open(os.path.join(ROOT, "paper_1108_1310_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def recorded_traffic(workload, H):

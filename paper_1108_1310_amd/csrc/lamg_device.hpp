@@ -27,12 +27,43 @@ __device__ __host__ inline double unit_pm1(uint64_t h) {
   return (double)(h >> 11) * (1.0 / 4503599627370496.0) - 1.0;
 }
 
+// The value of lane j ^ OFF, one 32-bit word.  Partners inside a row of 16
+// lanes come through DPP moves (register to register): xor 1 and xor 2 as
+// quad permutations [1,0,3,2] and [2,3,0,1], xor 8 as a rotation of the row
+// by 8, xor 4 as the half-row mirror (lane i of 8 reads 7 - i) followed by
+// the quad reversal [3,2,1,0] (i ^ 3), whose composition reads i ^ 4.  The
+// offsets 16 and 32 cross rows and go through ds_bpermute.
+template <int OFF>
+__device__ __attribute__((always_inline)) inline int lane_xor32(int v) {
+  if constexpr (OFF == 1) return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);
+  else if constexpr (OFF == 2) return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);
+  else if constexpr (OFF == 4)
+    return __builtin_amdgcn_mov_dpp(__builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, false), 0x1B, 0xF, 0xF, false);
+  else if constexpr (OFF == 8) return __builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, false);
+  else return __shfl_xor(v, OFF, 64);
+}
+template <int OFF>
+__device__ __attribute__((always_inline)) inline float lane_xor(float v) {
+  return __builtin_bit_cast(float, lane_xor32<OFF>(__builtin_bit_cast(int, v)));
+}
+template <int OFF>
+__device__ __attribute__((always_inline)) inline double lane_xor(double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const int lo = lane_xor32<OFF>((int)(uint32_t)u), hi = lane_xor32<OFF>((int)(uint32_t)(u >> 32));
+  return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
 // xor-butterfly fold of 64 lane partial sums: after the offsets 32..1 every
-// lane holds the same total; lane j adds its partner j^off at each step.
+// lane holds the same total; lane j adds its partner j^off at each step (the
+// two partners add the same pair, so they stay equal bit for bit).
 template <class T>
 __device__ inline T wave_fold(T s) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) s = s + __shfl_xor(s, off, 64);
+  s = s + lane_xor<32>(s);
+  s = s + lane_xor<16>(s);
+  s = s + lane_xor<8>(s);
+  s = s + lane_xor<4>(s);
+  s = s + lane_xor<2>(s);
+  s = s + lane_xor<1>(s);
   return s;
 }
 

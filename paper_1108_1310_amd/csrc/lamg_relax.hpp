@@ -1,6 +1,7 @@
 // The relaxation kernel (multicolour Gauss-Seidel, residual and elimination
 // restriction over tiled CSR rows).  Kept in a file of its own: the recorded
-// HBM traffic of this kernel is tied to this file's contents.
+// HBM traffic of this kernel is tied to this file's contents and to those of
+// the device helpers it inlines (lamg_device.hpp).
 #pragma once
 #include "lamg_device.hpp"
 #include "lamg_internal.hpp"
