@@ -487,9 +487,12 @@ __device__ __attribute__((always_inline)) inline void coarse_rows(const double* 
 }
 
 // Fixed-order sum of NV values per thread over the workgroup: a butterfly
-// inside each wavefront, then the launch's wavefront sums left to right.
+// inside each wavefront, then the launch's wavefront sums left to right,
+// added by one thread per value (thread i for value i) and read back by all;
+// every thread adding all of them cost 16 x NV LDS reads per wavefront.
 template <int NV>
 __device__ inline void block_sums(double (&v)[NV], double (*sh)[TAIL_WAVES]) {
+  static_assert(NV >= 1 && NV <= 6, "the scratch holds six rows");
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll
   for (int i = 0; i < NV; ++i) {
@@ -497,12 +500,15 @@ __device__ inline void block_sums(double (&v)[NV], double (*sh)[TAIL_WAVES]) {
     if (lane == 0) sh[i][wv] = t;
   }
   __syncthreads();
-#pragma unroll
-  for (int i = 0; i < NV; ++i) {
+  if (threadIdx.x < NV) {
+    const int i = threadIdx.x;
     double t = 0;
     for (int w = 0; w < tail_nw(); ++w) t += sh[i][w];
-    v[i] = t;
+    sh[i][0] = t;  // only this thread reads row i before the barrier
   }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NV; ++i) v[i] = sh[i][0];
   __syncthreads();
 }
 
