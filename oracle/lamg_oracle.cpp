@@ -19,7 +19,7 @@
 // paper prints no aggregates; only invariants and the scan equivalence are
 // pinned) and the constants of the stage-1 threshold, the weak-edge ratio,
 // the elimination stop fraction and the fast-relaxation ratio (parity
-// unpinned: builder choices where the paper gives no value).
+// unpinned: implementation choices where the paper gives no value).
 
 #include <algorithm>
 #include <cmath>

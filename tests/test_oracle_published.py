@@ -3,8 +3,8 @@ Laplacians on 1024 x 1024 grids, case (a)): the 5-point Laplacian with
 Neumann boundary conditions -- the unit-weight grid graph, m = 2,095,104 --
 is solved at an asymptotic convergence factor of 0.216.  The oracle's ACF on
 seeded right-hand sides must be close to it.  (The paper's level count, 19,
-is not compared: this build counts every elimination level as a level of
-its own and has 23.)"""
+is not compared: this implementation counts every elimination level as a
+level of its own and has 23.)"""
 import numpy as np
 
 from oracle import oracle as O
