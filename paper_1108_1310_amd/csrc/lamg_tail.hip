@@ -63,6 +63,7 @@ enum TailOp {
   OP_COARSE = 10, // coarsest solve of level l
   OP_MEAN = 11,   // x_l -= mean(x_l)
   OP_RRAGG = 12,  // fused: residual into src(a), X[sub] = x when a > 0, b_{l+1} = mu^(b) P^T src, x_{l+1} = 0
+  OP_RRELIM = 13, // fused: r = residual, b_{l+1} = elimination restriction of r, x_{l+1} = 0
 };
 
 struct TailParams {
@@ -580,6 +581,31 @@ __device__ __attribute__((always_inline)) inline void run_ops(const TailParams& 
         }
         break;
       }
+      case OP_RRELIM: {
+        // residual rows (staged in LDS when they fit), then one thread per
+        // coarse node: its fine value plus the eliminated neighbours' terms
+        // in stencil order, read from the staged copy; zeroed coarse iterate
+        const TailLevel& Lc = Ls[op.y + 1 - PP.lc];
+        auto r = C.v(L, TV<T>::r(L));
+        LP<T> rl;
+        const bool inl = tail_residual<T, MV>(L, C, lds, budget, r, false, r, &rl);
+        __syncthreads();
+        const T* er = TV<T>::er(L);
+        auto bc = C.v(Lc, TV<T>::b(Lc));
+        auto xc = C.v(Lc, TV<T>::x(Lc));
+        for (int c = tid; c < L.nc; c += tail_nt()) {
+          T s = 0;
+          if (inl) {
+            for (int j = L.er_rp[c]; j < L.er_rp[c + 1]; ++j) s += er[j] * rl[L.er_ci[j]];
+            bc[c] = rl[L.cfine[c]] + s;
+          } else {
+            for (int j = L.er_rp[c]; j < L.er_rp[c + 1]; ++j) s += er[j] * r[L.er_ci[j]];
+            bc[c] = r[L.cfine[c]] + s;
+          }
+          xc[c] = T(0);
+        }
+        break;
+      }
       case OP_ZERO: {
         auto x = C.v(L, TV<T>::x(L));
         for (int u = tid; u < L.n; u += tail_nt()) x[u] = T(0);
@@ -877,9 +903,7 @@ struct Gen {
     const int Lc = (int)H->lv.size() - 1;
     if (l == Lc) { op(OP_COARSE, l); return; }
     if (H->lv[l + 1].type == LT_ELIM) {
-      op(OP_RES, l, 0);
-      op(OP_RELIM, l);
-      op(OP_ZERO, l + 1);
+      op(OP_RRELIM, l);
       visit(l + 1, 1);
       op(OP_IELIM, l);
       return;
@@ -1033,7 +1057,7 @@ std::string program_check(const Hierarchy* H, const std::vector<TailLevel>& d, c
   for (size_t k = 0; k < prog.size(); ++k) {
     const int4 op = prog[k];
     const int li = op.y - lc;
-    bool ok = op.x >= OP_GS && op.x <= OP_RRAGG && li >= 0 && li < nlev;
+    bool ok = op.x >= OP_GS && op.x <= OP_RRELIM && li >= 0 && li < nlev;
     if (ok) {
       const TailLevel& t = d[li];
       switch (op.x) {
@@ -1042,7 +1066,7 @@ std::string program_check(const Hierarchy* H, const std::vector<TailLevel>& d, c
         case OP_SAVEX: ok = op.z >= 0 && op.z <= 1; break;
         case OP_RAGG: case OP_RRAGG: ok = t.agg != nullptr && op.z >= 0 && op.z <= 2; break;
         case OP_IAGG: ok = t.agg != nullptr; break;
-        case OP_RELIM: case OP_IELIM: ok = t.cidx != nullptr; break;
+        case OP_RELIM: case OP_IELIM: case OP_RRELIM: ok = t.cidx != nullptr; break;
         case OP_ZERO: case OP_MEAN: break;
         case OP_RECOMB: ok = op.z >= 1 && op.z <= 2 && t.agg != nullptr; break;
         case OP_COARSE: ok = li == nlev - 1; break;
