@@ -64,6 +64,7 @@ enum TailOp {
   OP_MEAN = 11,   // x_l -= mean(x_l)
   OP_RRAGG = 12,  // fused: residual into src(a), X[sub] = x when a > 0, b_{l+1} = mu^(b) P^T src, x_{l+1} = 0
   OP_RRELIM = 13, // fused: r = residual, b_{l+1} = elimination restriction of r, x_{l+1} = 0
+  OP_IGS = 14,    // fused: x_l += P x_{l+1}, then a = multicolour sweeps of level l
 };
 
 struct TailParams {
@@ -226,7 +227,7 @@ __device__ __attribute__((always_inline)) inline void lds_sweeps(const TailLevel
 }
 template <class T, bool MV>
 __device__ __attribute__((always_inline)) inline void tail_gs_lds(const TailLevel& L, ColOf<MV> C, char* lds,
-                                                                  int budget, int sweeps) {
+                                                                  int budget, int sweeps, const TailLevel* Lq) {
   auto x = C.v(L, TV<T>::x(L));
   auto b = C.v(L, TV<T>::b(L));
   const T* dg = TV<T>::diag(L);
@@ -238,7 +239,14 @@ __device__ __attribute__((always_inline)) inline void tail_gs_lds(const TailLeve
   LP<int> scp = srp + n + 1;
   LP<int> slp = scp + nc + 1;
   const int tid = threadIdx.x;
-  for (int i = tid; i < n; i += tail_nt()) { sx[i] = x[i]; sbv[i] = b[i]; sd[i] = dg[i]; srp[i] = L.rp[i]; }
+  if (Lq) {
+    // the aggregation correction x += P x_{l+1} applied while staging
+    auto e = C.v(*Lq, TV<T>::x(*Lq));
+    for (int i = tid; i < n; i += tail_nt()) sx[i] = x[i] + e[L.agg[i]];
+  } else {
+    for (int i = tid; i < n; i += tail_nt()) sx[i] = x[i];
+  }
+  for (int i = tid; i < n; i += tail_nt()) { sbv[i] = b[i]; sd[i] = dg[i]; srp[i] = L.rp[i]; }
   for (int i = tid; i <= nc; i += tail_nt()) { scp[i] = L.cptr[i]; slp[i] = L.lptr[i]; }
   if (tid == 0) srp[n] = L.rp[n];
   __syncthreads();
@@ -259,7 +267,7 @@ __device__ __attribute__((always_inline)) inline void tail_gs_lds(const TailLeve
 // long rows (> 64) from the wavefront path.
 template <class T, bool MV, int R>
 __device__ __attribute__((always_inline)) inline void tail_gs_small(const TailLevel& L, ColOf<MV> C, char* lds,
-                                                                    int sweeps) {
+                                                                    int sweeps, const TailLevel* Lq) {
   // entries held in registers per row: 16 for one row per thread, 8 for two
   constexpr int RMAX = R == 1 ? 16 : 8;
   auto x = C.v(L, TV<T>::x(L));
@@ -284,7 +292,13 @@ __device__ __attribute__((always_inline)) inline void tail_gs_small(const TailLe
     bu[k] = T(0);
     du[k] = T(1);
     if (u < n) {
-      sx[u] = x[u];
+      if (Lq) {
+        // the aggregation correction x += P x_{l+1} applied while staging
+        auto e = C.v(*Lq, TV<T>::x(*Lq));
+        sx[u] = x[u] + e[L.agg[u]];
+      } else {
+        sx[u] = x[u];
+      }
       bu[k] = b[u];
       du[k] = dg[u];
       p0[k] = L.rp[u];
@@ -331,17 +345,26 @@ __device__ __attribute__((always_inline)) inline void tail_gs_small(const TailLe
   }
 }
 
+// Lq (optional): the coarse level of an aggregation whose correction
+// x += P x_{l+1} precedes the sweeps; the staged paths add it as they load x.
 template <class T, bool MV>
 __device__ __attribute__((always_inline)) inline void tail_sweeps(const TailLevel& L, ColOf<MV> C, char* lds,
-                                                                  int budget, int sweeps) {
+                                                                  int budget, int sweeps,
+                                                                  const TailLevel* Lq = nullptr) {
   const size_t small = (size_t)L.n * sizeof(T) + (size_t)(L.ncol + 1) * sizeof(int);
   if (L.n <= tail_nt() && small <= (size_t)budget) {
-    tail_gs_small<T, MV, 1>(L, C, lds, sweeps);
+    tail_gs_small<T, MV, 1>(L, C, lds, sweeps, Lq);
   } else if (L.n <= 2 * tail_nt() && small <= (size_t)budget) {
-    tail_gs_small<T, MV, 2>(L, C, lds, sweeps);
+    tail_gs_small<T, MV, 2>(L, C, lds, sweeps, Lq);
   } else if (tail_fits<T>(L, budget)) {
-    tail_gs_lds<T, MV>(L, C, lds, budget, sweeps);
+    tail_gs_lds<T, MV>(L, C, lds, budget, sweeps, Lq);
   } else {
+    if (Lq) {
+      auto e = C.v(*Lq, TV<T>::x(*Lq));
+      auto x = C.v(L, TV<T>::x(L));
+      for (int u = threadIdx.x; u < L.n; u += tail_nt()) x[u] += e[L.agg[u]];
+      __syncthreads();
+    }
     for (int sw = 0; sw < sweeps; ++sw) tail_gs<T, MV>(L, C);
   }
 }
@@ -531,6 +554,9 @@ __device__ __attribute__((always_inline)) inline void run_ops(const TailParams& 
     switch (op.x) {
       case OP_GS:
         tail_sweeps<T, MV>(L, C, lds, budget, op.z);
+        break;
+      case OP_IGS:
+        tail_sweeps<T, MV>(L, C, lds, budget, op.z, &Ls[op.y + 1 - PP.lc]);
         break;
       case OP_RES: {
         auto dst = C.v(L, op.z == 0 ? TV<T>::r(L) : TV<T>::R(L, op.z - 1));
@@ -916,8 +942,11 @@ struct Gen {
     const double gl = H->lv[l].gamma_next;
     const int th = (int)(std::ceil((double)(c + 1) * gl) - std::ceil((double)c * gl));
     visit(l + 1, th);
-    op(OP_IAGG, l);
-    if (H->o.nu_post > 0) op(OP_GS, l, H->o.nu_post);
+    if (H->o.nu_post > 0) {
+      op(OP_IGS, l, H->o.nu_post);
+    } else {
+      op(OP_IAGG, l);
+    }
   }
 };
 
@@ -1057,7 +1086,7 @@ std::string program_check(const Hierarchy* H, const std::vector<TailLevel>& d, c
   for (size_t k = 0; k < prog.size(); ++k) {
     const int4 op = prog[k];
     const int li = op.y - lc;
-    bool ok = op.x >= OP_GS && op.x <= OP_RRELIM && li >= 0 && li < nlev;
+    bool ok = op.x >= OP_GS && op.x <= OP_IGS && li >= 0 && li < nlev;
     if (ok) {
       const TailLevel& t = d[li];
       switch (op.x) {
@@ -1066,6 +1095,7 @@ std::string program_check(const Hierarchy* H, const std::vector<TailLevel>& d, c
         case OP_SAVEX: ok = op.z >= 0 && op.z <= 1; break;
         case OP_RAGG: case OP_RRAGG: ok = t.agg != nullptr && op.z >= 0 && op.z <= 2; break;
         case OP_IAGG: ok = t.agg != nullptr; break;
+        case OP_IGS: ok = t.agg != nullptr && op.z >= 1; break;
         case OP_RELIM: case OP_IELIM: case OP_RRELIM: ok = t.cidx != nullptr; break;
         case OP_ZERO: case OP_MEAN: break;
         case OP_RECOMB: ok = op.z >= 1 && op.z <= 2 && t.agg != nullptr; break;
