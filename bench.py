@@ -107,9 +107,11 @@ def workload(name):
 
 def timed_solves(H, b, precision, steps, warmup, lamg, instrument=False):
     """Time `steps` full solves.  Plain runs replay the captured cycle graphs;
-    instrumented runs launch every kernel eagerly with a HIP event pair around
-    each relaxation launch (same stream), which yields the kernel's summed
-    duration, launch count and algorithmic bytes."""
+    instrumented runs launch every kernel eagerly with a HIP event pair (same
+    stream) around each run of back-to-back relaxation launches (one span per
+    sweep's launched colours, behind a bounded wait that lets the host queue
+    the span first), which yields the kernel's summed duration, launch count
+    and algorithmic bytes."""
     import torch
     H.set_solve_options(precision=precision)
     for _ in range(warmup):
