@@ -375,10 +375,14 @@ __device__ __attribute__((always_inline)) inline void tail_sweeps(const TailLeve
 // (LDS copies or global memory).  Rows longer than 64 entries: one wavefront
 // each in the canonical chunk order.  Optionally also writes the residual to
 // an LDS copy rl and the iterate to Xs.
-template <class T, bool MV, class XA, class BA, class DA, class RA>
+struct NoEpi {
+  template <class T>
+  __device__ void operator()(int, T, T) const {}
+};
+template <class T, bool MV, class XA, class BA, class DA, class RA, class EPI = NoEpi>
 __device__ __attribute__((always_inline)) inline void res_rows(const TailLevel& L, XA xa, BA ba, DA da, RA rpa,
                                                                const T* val, Col<T, MV> out, LP<T> rl, bool use_rl,
-                                                               bool save, Col<T, MV> Xs) {
+                                                               bool save, Col<T, MV> Xs, EPI epi = EPI()) {
   constexpr int Q = 8;
   const int n = L.n, tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
   for (int u0 = tid; u0 < n; u0 += 2 * tail_nt()) {
@@ -420,6 +424,7 @@ __device__ __attribute__((always_inline)) inline void res_rows(const TailLevel& 
       out[u[k]] = r;
       if (use_rl) rl[u[k]] = r;
       if (save) Xs[u[k]] = xu;
+      epi(u[k], r, xu);
     }
   }
   for (int k = wv; k < L.nlong; k += tail_nw()) {
@@ -439,10 +444,12 @@ __device__ __attribute__((always_inline)) inline void res_rows(const TailLevel& 
 // The residual of a level into out, its x, b, diagonal and row pointers
 // staged in LDS when they fit (and the level does not already sit in LDS).
 // Returns whether an LDS copy of the residual was left at *rl.
-template <class T, bool MV>
+// epi(u, r_u, x_u): called by the thread that computed short row u, right
+// after it (rows longer than 64 entries do not call it).
+template <class T, bool MV, class EPI = NoEpi>
 __device__ __attribute__((always_inline)) inline bool tail_residual(const TailLevel& L, ColOf<MV> C, char* lds,
                                                                     int budget, Col<T, MV> out, bool save,
-                                                                    Col<T, MV> Xs, LP<T>* rl) {
+                                                                    Col<T, MV> Xs, LP<T>* rl, EPI epi = EPI()) {
   auto x = C.v(L, TV<T>::x(L));
   auto b = C.v(L, TV<T>::b(L));
   const T* dg = TV<T>::diag(L);
@@ -457,11 +464,11 @@ __device__ __attribute__((always_inline)) inline bool tail_residual(const TailLe
     for (int i = tid; i < n; i += tail_nt()) { sx[i] = x[i]; sb[i] = b[i]; sd[i] = dg[i]; srp[i] = L.rp[i]; }
     if (tid == 0) srp[n] = L.rp[n];
     __syncthreads();
-    res_rows<T, MV>(L, sx, sb, sd, srp, val, out, sr, true, save, Xs);
+    res_rows<T, MV>(L, sx, sb, sd, srp, val, out, sr, true, save, Xs, epi);
     *rl = sr;
     return true;
   }
-  res_rows<T, MV>(L, x, b, dg, L.rp, val, out, (LP<T>)lds, false, save, Xs);
+  res_rows<T, MV>(L, x, b, dg, L.rp, val, out, (LP<T>)lds, false, save, Xs, epi);
   return false;
 }
 
@@ -675,9 +682,6 @@ __device__ __attribute__((always_inline)) inline void run_ops(const TailParams& 
       case OP_RECOMB: {
         const int th = op.z;
         auto r = C.v(L, TV<T>::r(L));
-        LP<T> rl;
-        tail_residual<T, MV>(L, C, lds, budget, r, false, r, &rl);
-        __syncthreads();
         auto R0 = C.v(L, TV<T>::R(L, 0));
         auto R1 = C.v(L, TV<T>::R(L, 1));
         auto x = C.v(L, TV<T>::x(L));
@@ -685,9 +689,22 @@ __device__ __attribute__((always_inline)) inline void run_ops(const TailParams& 
         auto X1 = C.v(L, TV<T>::X(L, 1));
         const int norm = PP.rnorm;
         double v[6] = {0, 0, 0, 0, 0, 0};
-        for (int u = tid; u < L.n; u += tail_nt())
-          dev::recomb_terms<T>(norm, th, r[u], R0[u], th > 1 ? R1[u] : T(0), norm ? x[u] : T(0),
-                               norm ? X0[u] : T(0), norm && th > 1 ? X1[u] : T(0), v);
+        LP<T> rl;
+        if (L.nlong == 0) {
+          // every row short: each thread adds its rows' terms as it computes
+          // their residuals (its rows in the same order as the separate pass
+          // below: tid, tid + threads, ...), no barrier between
+          tail_residual<T, MV>(L, C, lds, budget, r, false, r, &rl, [&](int u, T ru, T xu) {
+            dev::recomb_terms<T>(norm, th, ru, R0[u], th > 1 ? R1[u] : T(0), norm ? xu : T(0),
+                                 norm ? X0[u] : T(0), norm && th > 1 ? X1[u] : T(0), v);
+          });
+        } else {
+          tail_residual<T, MV>(L, C, lds, budget, r, false, r, &rl);
+          __syncthreads();
+          for (int u = tid; u < L.n; u += tail_nt())
+            dev::recomb_terms<T>(norm, th, r[u], R0[u], th > 1 ? R1[u] : T(0), norm ? x[u] : T(0),
+                                 norm ? X0[u] : T(0), norm && th > 1 ? X1[u] : T(0), v);
+        }
         block_sums<6>(v, sh);
         double a0 = 0, a1 = 0;
         dev::recomb_alpha(norm, th, v, &a0, &a1);
