@@ -52,12 +52,7 @@ __device__ __attribute__((always_inline)) inline int tail_nw() { return (int)(bl
 
 enum TailOp {
   OP_GS = 1,      // a = multicolour sweeps of level l (one staging for all)
-  OP_RES = 2,     // residual of level l into a = 0: r, 1: R0, 2: R1
-  OP_SAVEX = 3,   // X[a] = x
-  OP_RAGG = 4,    // b_{l+1} = mu^(b) * P^T src(a)
-  OP_ZERO = 5,    // x_l = 0
   OP_IAGG = 6,    // x_l += P x_{l+1}
-  OP_RELIM = 7,   // b_{l+1} = elimination restriction of r_l
   OP_IELIM = 8,   // x_l += exact elimination correction from x_{l+1}
   OP_RECOMB = 9,  // iterate recombination over a = theta sub-cycles
   OP_COARSE = 10, // coarsest solve of level l
@@ -565,30 +560,6 @@ __device__ __attribute__((always_inline)) inline void run_ops(const TailParams& 
       case OP_IGS:
         tail_sweeps<T, MV>(L, C, lds, budget, op.z, &Ls[op.y + 1 - PP.lc]);
         break;
-      case OP_RES: {
-        auto dst = C.v(L, op.z == 0 ? TV<T>::r(L) : TV<T>::R(L, op.z - 1));
-        LP<T> rl;
-        tail_residual<T, MV>(L, C, lds, budget, dst, false, dst, &rl);
-        break;
-      }
-      case OP_SAVEX: {
-        auto x = C.v(L, TV<T>::x(L));
-        auto X = C.v(L, TV<T>::X(L, op.z));
-        for (int u = tid; u < L.n; u += tail_nt()) X[u] = x[u];
-        break;
-      }
-      case OP_RAGG: {
-        const TailLevel& Lc = Ls[op.y + 1 - PP.lc];
-        auto src = C.v(L, op.z == 0 ? TV<T>::r(L) : TV<T>::R(L, op.z - 1));
-        auto bc = C.v(Lc, TV<T>::b(Lc));
-        const T mu = op.w ? (T)PP.mu : T(1);
-        for (int U = tid; U < L.nc; U += tail_nt()) {
-          T s = 0;
-          for (int j = L.agg_ptr[U]; j < L.agg_ptr[U + 1]; ++j) s += src[L.members[j]];
-          bc[U] = mu * s;
-        }
-        break;
-      }
       case OP_RRAGG: {
         // residual rows (saved iterate alongside), then one thread per
         // aggregate: restricted sum of its members in ascending order, zeroed
@@ -639,28 +610,11 @@ __device__ __attribute__((always_inline)) inline void run_ops(const TailParams& 
         }
         break;
       }
-      case OP_ZERO: {
-        auto x = C.v(L, TV<T>::x(L));
-        for (int u = tid; u < L.n; u += tail_nt()) x[u] = T(0);
-        break;
-      }
       case OP_IAGG: {
         const TailLevel& Lc = Ls[op.y + 1 - PP.lc];
         auto e = C.v(Lc, TV<T>::x(Lc));
         auto x = C.v(L, TV<T>::x(L));
         for (int u = tid; u < L.n; u += tail_nt()) x[u] += e[L.agg[u]];
-        break;
-      }
-      case OP_RELIM: {
-        const TailLevel& Lc = Ls[op.y + 1 - PP.lc];
-        auto r = C.v(L, TV<T>::r(L));
-        const T* er = TV<T>::er(L);
-        auto bc = C.v(Lc, TV<T>::b(Lc));
-        for (int c = tid; c < L.nc; c += tail_nt()) {
-          T s = 0;
-          for (int j = L.er_rp[c]; j < L.er_rp[c + 1]; ++j) s += er[j] * r[L.er_ci[j]];
-          bc[c] = r[L.cfine[c]] + s;
-        }
         break;
       }
       case OP_IELIM: {
@@ -1108,13 +1062,11 @@ std::string program_check(const Hierarchy* H, const std::vector<TailLevel>& d, c
       const TailLevel& t = d[li];
       switch (op.x) {
         case OP_GS: ok = op.z >= 0; break;
-        case OP_RES: ok = op.z >= 0 && op.z <= 2; break;
-        case OP_SAVEX: ok = op.z >= 0 && op.z <= 1; break;
-        case OP_RAGG: case OP_RRAGG: ok = t.agg != nullptr && op.z >= 0 && op.z <= 2; break;
+        case OP_RRAGG: ok = t.agg != nullptr && op.z >= 0 && op.z <= 2; break;
         case OP_IAGG: ok = t.agg != nullptr; break;
         case OP_IGS: ok = t.agg != nullptr && op.z >= 1; break;
-        case OP_RELIM: case OP_IELIM: case OP_RRELIM: ok = t.cidx != nullptr; break;
-        case OP_ZERO: case OP_MEAN: break;
+        case OP_IELIM: case OP_RRELIM: ok = t.cidx != nullptr; break;
+        case OP_MEAN: break;
         case OP_RECOMB: ok = op.z >= 1 && op.z <= 2 && t.agg != nullptr; break;
         case OP_COARSE: ok = li == nlev - 1; break;
         default: ok = false;
